@@ -1,0 +1,136 @@
+"""Benchmark of the Galerkin-FFT Newton--CG hot path on one MI355X.
+
+One step = one full solve of the workload's mean-strain path (every
+increment of Algorithm 1: return map, residual G:sigma, CG with the
+matrix-free G:(C:p) product, Newton updates, history commit) from a fresh
+history, inputs already resident in HBM.  The metric is
+voxel-CG-iterations per second: voxels x CG iterations of the timed steps
+divided by their wall time.
+
+Default workload: the 31^3 Bernoulli(0.3) two-phase RVE in FP64, pure shear
+E_eq = 0.02 in 10 increments.  Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import synth  # noqa: E402
+
+HBM_PEAK_GBS = 8000.0
+
+
+def workload(name: str):
+    if name == "random_31":
+        return synth.random_31(), "31^3 Bernoulli(0.3) two-phase J2 RVE, FP64, pure shear 0.02 in 10 increments"
+    if name == "voronoi_127_mixed":
+        return synth.voronoi_127(), "127^3 periodic Voronoi (200 grains, 20% hard), mixed precision, 20 increments"
+    raise SystemExit(f"unknown workload {name}")
+
+
+def tensor6(E):
+    return [E[0, 0], E[1, 1], E[2, 2], E[1, 2], E[0, 2], E[0, 1]]
+
+
+def x_pass_bytes_per_voxel(shape, real_bytes):
+    """Algorithmic HBM bytes of one x-pass launch per voxel: it reads and
+    writes the six complex half-spectrum planes once (n0*n1*H complex each)."""
+    n0, n1, n2 = shape
+    H = (n2 + 1) // 2
+    return 2 * 6 * 2 * real_bytes * (n0 * n1 * H) / float(n0 * n1 * n2)
+
+
+def cpu_baseline(w, budget_s=15.0):
+    """The FP64 oracle on the host cores, increments 1.. until ~budget_s."""
+    from oracle import solver as S
+    s = S.Solver(w.phase, w.materials, w.tol_newton, w.tol_cg)
+    t0 = time.perf_counter()
+    cg = 0
+    n = 0
+    while n < w.n_inc and time.perf_counter() - t0 < budget_s:
+        n += 1
+        cg += sum(s.solve_increment(w.E_at(n)).cg_iters)
+    dt = time.perf_counter() - t0
+    return {"value": w.nvox * cg / dt, "unit": "voxel-CG-iters/s", "cores": os.cpu_count(), "kind": "oracle",
+            "sample": f"{w.name}: increments 1-{n} of {w.n_inc} ({cg} CG iterations, {dt:.1f} s), numpy/scipy "
+                      f"FP64, scipy.fft workers=all cores"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="random_31")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--profile-kernel", type=int, default=2, help="fftg_kernel_id timed for the roofline")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}): the solve of one RVE is not sharded "
+              "across GPUs in this build", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1601_05970_amd import fftg
+
+    w, desc = workload(args.workload)
+    opts = fftg.fftg_options_default()
+    opts.tol_newton, opts.tol_cg = w.tol_newton, w.tol_cg
+    opts.precision = fftg.FFTG_MIXED if w.precision == "mixed" else fftg.FFTG_FP64
+    plan = fftg.Plan(w.phase, w.materials, opts)
+
+    def step():
+        h = fftg.History(plan)
+        cg = 0
+        for n in range(1, w.n_inc + 1):
+            cg += h.solve_increment(tensor6(w.dE(n)))["total_cg"]
+        h.close()
+        return cg
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    fftg.fftg_profiler_start(args.profile_kernel)
+    t0 = time.perf_counter()
+    total_cg = 0
+    for _ in range(args.steps):
+        total_cg += step()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    kms, klaunch, kvox = fftg.fftg_profiler_stop()
+
+    value = w.nvox * total_cg / dt
+    real_bytes = 4 if opts.precision == fftg.FFTG_MIXED else 8
+    bpv = x_pass_bytes_per_voxel(w.shape, real_bytes)
+    avg_ms = kms / max(klaunch, 1)
+    bytes_per_launch = bpv * kvox / max(klaunch, 1)
+    achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else 0.0
+    out = {
+        "metric": "voxel-CG-iters/s", "value": value, "unit": "voxel-CG-iters/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * dt / args.steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32+f64" if opts.precision == fftg.FFTG_MIXED else "f64", "data": "synthetic",
+        "config": {"workload": desc, "grid": list(w.shape), "increments": w.n_inc,
+                   "tol_newton": w.tol_newton, "tol_cg": w.tol_cg, "cg_iters_per_step": total_cg / args.steps},
+        "roofline": {"kernel": "k_xpass (DFT x, G^(k) projection, inverse DFT x)", "bound": "hbm",
+                     "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "avg_launch_us": 1e3 * avg_ms, "launches": klaunch,
+                     "bytes_per_launch": bytes_per_launch},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(w)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,219 @@
+// Batched 1-D complex FFTs of odd length held in LDS.
+//
+// A workgroup transforms nl lines at once; line l lives at buf + l * ld.
+// Lengths N whose prime factors are direct radices (3, 5, 7, 9, 11, 13, 17)
+// run a Stockham autosort chain (one radix per stage, ping-pong between two
+// LDS buffers).  A prime N beyond those runs Rader's algorithm: with g a
+// primitive root mod N, X[g^-m] = x_0 + (a (*) b)_m, a_q = x[g^q],
+// b_j = w^(g^-j), a cyclic convolution of length N-1 done as
+// DFT_{N-1}^-1 (DFT_{N-1}(a) * DFT_{N-1}(b)/(N-1)), and X_0 = x_0 + sum a_q.
+// The length-(N-1) chains use radix 2 or 4 for the even part.
+//
+// These are the fast transforms F and F^-1 of the paper's Eq.
+// (DFT_forward_inverse); normalisation is left to the caller.
+#pragma once
+
+#include "fftg_internal.h"
+
+namespace fftg {
+
+template <int R>
+struct RadixConst;
+#include "radix_consts.h"
+
+template <class T>
+__device__ __forceinline__ cx<T> cadd(cx<T> a, cx<T> b) { return {a.re + b.re, a.im + b.im}; }
+template <class T>
+__device__ __forceinline__ cx<T> csub(cx<T> a, cx<T> b) { return {a.re - b.re, a.im - b.im}; }
+template <class T>
+__device__ __forceinline__ cx<T> cmul(cx<T> a, cx<T> b) {
+  return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+// a * (s * i) for s = +1 / -1
+template <int S, class T>
+__device__ __forceinline__ cx<T> mul_si(cx<T> a) {
+  return S > 0 ? cx<T>{-a.im, a.re} : cx<T>{a.im, -a.re};
+}
+
+// Direct DFT of R points in registers: X_k = sum_n v_n exp(DIR 2 pi i n k / R).
+template <int R, int DIR, class T>
+struct Dft {
+  // odd R: pair n and R-n, X_k = A_k + DIR i B_k, X_{R-k} = A_k - DIR i B_k
+  __device__ __forceinline__ static void run(cx<T>* v) {
+    constexpr int m = (R - 1) / 2;
+    cx<T> s[m + 1], d[m + 1];
+#pragma unroll
+    for (int j = 1; j <= m; ++j) {
+      s[j] = cadd(v[j], v[R - j]);
+      d[j] = csub(v[j], v[R - j]);
+    }
+    cx<T> x0 = v[0];
+#pragma unroll
+    for (int j = 1; j <= m; ++j) x0 = cadd(x0, s[j]);
+#pragma unroll
+    for (int k = 1; k <= m; ++k) {
+      cx<T> A = v[0];
+      cx<T> B = {T(0), T(0)};
+#pragma unroll
+      for (int j = 1; j <= m; ++j) {
+        const T c = T(RadixConst<R>::c[(j * k) % R]);
+        const T sn = T(RadixConst<R>::s[(j * k) % R]);
+        A.re += s[j].re * c;
+        A.im += s[j].im * c;
+        B.re += d[j].re * sn;
+        B.im += d[j].im * sn;
+      }
+      const cx<T> iB = mul_si<DIR>(B);
+      v[k] = cadd(A, iB);
+      v[R - k] = csub(A, iB);
+    }
+    v[0] = x0;
+  }
+};
+
+template <int DIR, class T>
+struct Dft<2, DIR, T> {
+  __device__ __forceinline__ static void run(cx<T>* v) {
+    const cx<T> a = v[0], b = v[1];
+    v[0] = cadd(a, b);
+    v[1] = csub(a, b);
+  }
+};
+
+template <int DIR, class T>
+struct Dft<4, DIR, T> {
+  __device__ __forceinline__ static void run(cx<T>* v) {
+    const cx<T> s02 = cadd(v[0], v[2]), d02 = csub(v[0], v[2]);
+    const cx<T> s13 = cadd(v[1], v[3]), d13 = csub(v[1], v[3]);
+    const cx<T> t = mul_si<DIR>(d13);
+    v[0] = cadd(s02, s13);
+    v[2] = csub(s02, s13);
+    v[1] = cadd(d02, t);
+    v[3] = csub(d02, t);
+  }
+};
+
+// One Stockham stage of radix R over nl lines of an M-point chain.
+// Butterfly j of a line reads src[j + q M/R], twiddles by w_M^(q k M/(Ns R))
+// with k = j mod Ns, and writes dst[(j - k) R + k + q Ns].
+template <int R, int DIR, class T>
+__device__ __forceinline__ void stockham_stage(const cx<T>* __restrict__ src, cx<T>* __restrict__ dst,
+                                               int ld, int nl, int M, int Ns,
+                                               const cx<T>* __restrict__ tw) {
+  const int nb = M / R;
+  const int total = nb * nl;
+  const int tstep = M / (Ns * R);
+  for (int t = threadIdx.x; t < total; t += blockDim.x) {
+    const int line = t / nb;
+    const int j = t - line * nb;
+    const int k = j % Ns;
+    const cx<T>* s = src + line * ld + j;
+    cx<T> v[R];
+#pragma unroll
+    for (int q = 0; q < R; ++q) v[q] = s[q * nb];
+    if (Ns > 1) {
+#pragma unroll
+      for (int q = 1; q < R; ++q) {
+        cx<T> w = tw[q * k * tstep];
+        if (DIR > 0) w.im = -w.im;
+        v[q] = cmul(v[q], w);
+      }
+    }
+    Dft<R, DIR, T>::run(v);
+    cx<T>* d = dst + line * ld + (j - k) * R + k;
+#pragma unroll
+    for (int q = 0; q < R; ++q) d[q * Ns] = v[q];
+  }
+}
+
+template <class T>
+__device__ __forceinline__ const cx<T>* axis_tw(const AxisDev& P);
+template <>
+__device__ __forceinline__ const cx<double>* axis_tw<double>(const AxisDev& P) { return P.tw64; }
+template <>
+__device__ __forceinline__ const cx<float>* axis_tw<float>(const AxisDev& P) { return P.tw32; }
+
+// Runs the Stockham chain of P on a (result ends in a; buffers are swapped).
+template <int DIR, class T>
+__device__ void run_chain(cx<T>*& a, cx<T>*& b, int ld, int nl, const AxisDev& P) {
+  const cx<T>* tw = axis_tw<T>(P);
+  int Ns = 1;
+  for (int s = 0; s < P.nst; ++s) {
+    const int R = P.radix[s];
+    switch (R) {
+      case 2: stockham_stage<2, DIR, T>(a, b, ld, nl, P.M, Ns, tw); break;
+      case 3: stockham_stage<3, DIR, T>(a, b, ld, nl, P.M, Ns, tw); break;
+      case 4: stockham_stage<4, DIR, T>(a, b, ld, nl, P.M, Ns, tw); break;
+      case 5: stockham_stage<5, DIR, T>(a, b, ld, nl, P.M, Ns, tw); break;
+      case 7: stockham_stage<7, DIR, T>(a, b, ld, nl, P.M, Ns, tw); break;
+      case 9: stockham_stage<9, DIR, T>(a, b, ld, nl, P.M, Ns, tw); break;
+      case 11: stockham_stage<11, DIR, T>(a, b, ld, nl, P.M, Ns, tw); break;
+      case 13: stockham_stage<13, DIR, T>(a, b, ld, nl, P.M, Ns, tw); break;
+      case 17: stockham_stage<17, DIR, T>(a, b, ld, nl, P.M, Ns, tw); break;
+      default: break;  // rejected at plan creation
+    }
+    __syncthreads();
+    cx<T>* t = a;
+    a = b;
+    b = t;
+    Ns *= R;
+  }
+}
+
+template <class T>
+__device__ __forceinline__ const cx<T>* rader_bhat(const AxisDev& P, int dir);
+template <>
+__device__ __forceinline__ const cx<double>* rader_bhat<double>(const AxisDev& P, int dir) {
+  return dir < 0 ? P.bf64 : P.bi64;
+}
+template <>
+__device__ __forceinline__ const cx<float>* rader_bhat<float>(const AxisDev& P, int dir) {
+  return dir < 0 ? P.bf32 : P.bi32;
+}
+
+// In-LDS FFT of nl lines of length P.N, DIR = -1 forward, +1 inverse
+// (unnormalised).  line and scratch each hold nl lines of stride ld >= N;
+// dc holds nl scratch slots (Rader only).  Returns the buffer holding the
+// result (line or scratch).  Must be called by the whole workgroup.
+template <int DIR, class T>
+__device__ cx<T>* line_fft(cx<T>* line, cx<T>* scratch, int ld, int nl, const AxisDev& P, cx<T>* dc) {
+  if (!P.rader) {
+    cx<T>* a = line;
+    cx<T>* b = scratch;
+    run_chain<DIR, T>(a, b, ld, nl, P);
+    return a;
+  }
+  const int M = P.M;
+  const int total = nl * M;
+  for (int t = threadIdx.x; t < total; t += blockDim.x) {
+    const int l = t / M;
+    const int q = t - l * M;
+    scratch[l * ld + q] = line[l * ld + P.perm_in[q]];
+  }
+  __syncthreads();
+  cx<T>* a = scratch;
+  cx<T>* b = line + 1;
+  run_chain<-1, T>(a, b, ld, nl, P);
+  const cx<T>* bh = rader_bhat<T>(P, DIR);
+  for (int t = threadIdx.x; t < total; t += blockDim.x) {
+    const int l = t / M;
+    const int q = t - l * M;
+    const cx<T> v = a[l * ld + q];
+    if (q == 0) dc[l] = v;
+    a[l * ld + q] = cmul(v, bh[q]);
+  }
+  __syncthreads();
+  run_chain<1, T>(a, b, ld, nl, P);
+  // a == scratch here (2 * nst swaps); scatter back, x_0 still in line[0]
+  for (int t = threadIdx.x; t < total; t += blockDim.x) {
+    const int l = t / M;
+    const int m = t - l * M;
+    line[l * ld + P.perm_out[m]] = cadd(line[l * ld], a[l * ld + m]);
+  }
+  __syncthreads();
+  for (int l = threadIdx.x; l < nl; l += blockDim.x) line[l * ld] = cadd(line[l * ld], dc[l]);
+  __syncthreads();
+  return line;
+}
+
+}  // namespace fftg

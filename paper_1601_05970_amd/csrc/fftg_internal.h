@@ -1,0 +1,108 @@
+// Internal device/host structures of the Galerkin-FFT library.
+//
+// Data layout in HBM (one RVE, grid n0 x n1 x n2, all odd, C order, axis 2
+// fastest):
+//   * real symmetric tensor fields: 6 SoA planes of nvox values each, Mandel
+//     order [11, 22, 33, sqrt2*23, sqrt2*13, sqrt2*12];
+//   * spectrum: 6 SoA planes of n0 * n1 * H complex values, H = (n2+1)/2
+//     (half spectrum along axis 2; odd n2 has no Nyquist bin);
+//   * compact consistent tangent: 7 SoA planes {2G', m_0..m_5} with
+//     C:p = (K - 2G'/3) tr(p) I + 2G' p - (m.p) m, K from the phase table.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace fftg {
+
+constexpr int kMaxStages = 8;
+constexpr int kMaxPhases = 16;
+constexpr int kMaxAxisLen = 1024;
+
+template <class T>
+struct cx {
+  T re, im;
+};
+
+// One transform length: either a Stockham chain of direct radices, or Rader's
+// algorithm for a prime p with its length-(p-1) cyclic convolution done by a
+// Stockham chain.
+struct AxisDev {
+  int N;
+  int rader;            // 0: direct chain over N; 1: Rader over prime N
+  int M;                // chain length (N, or N-1 for Rader)
+  int nst;              // stages of the chain
+  int radix[kMaxStages];
+  // tables (device pointers); roots are exp(-2 pi i m / M), m < M
+  const cx<double>* tw64;
+  const cx<float>* tw32;
+  // Rader only
+  const int* perm_in;        // g^q mod N, q < M
+  const int* perm_out;       // g^-m mod N, m < M
+  const cx<double>* bf64;    // DFT_M(b)/M, b_q = exp(-2 pi i g^-q / N)
+  const cx<double>* bi64;    // same with exp(+...)
+  const cx<float>* bf32;
+  const cx<float>* bi32;
+};
+
+struct MatDev {
+  double K, G, sy0, H;
+};
+
+// Per-RVE scalar state of the CG solve and the reductions.
+struct CgState {
+  double rr, rr_new, pAp, alpha, beta;
+  double bnorm2, target2, snorm2, dnorm2;
+  double eta2, floor2;
+  double Sigma[6];
+  int iters, done, force, max_iter, status;
+  int pad_;
+  unsigned int counter[8];
+};
+
+enum CgStatus { CG_RUNNING = 0, CG_CONVERGED = 1, CG_MAXITER = 2, CG_BREAKDOWN = 3, CG_FORCED = 4 };
+
+// Buffer roles referenced by kernels through the descriptor.
+enum Role {
+  R_EPS_FL = 0, R_EPS_P, R_EPBAR, R_SIG, R_X, R_R, R_P, R_AP, R_USER_IN, R_USER_OUT, R_NROLES
+};
+
+enum Pass { P_ZF = 0, P_Y, P_X, P_ZI, P_VEC, P_NPASS };
+
+struct RveDev {
+  int n0, n1, n2, H;
+  long long nvox, nspec;
+  const AxisDev* ax[3];
+  void* buf[R_NROLES];       // double* except R_AP / R_USER_OUT in mixed mode
+  void* tang;                // 7 planes, double (FP64) or float (mixed)
+  void* spec;                // 6 complex planes, sized for double
+  const uint8_t* phase;
+  MatDev mats[kMaxPhases];
+  int n_phases;
+  int mixed;                 // apply precision: 0 double, 1 float
+  CgState* cg;
+  double* partial;           // per-block partial sums, >= tiles of any pass
+  double E[6];               // mean strain, Mandel
+  double dE[6];              // load increment, Mandel
+  int tiles[P_NPASS];        // tiles of each pass for this RVE
+  int skip;                  // 1: RVE masked out of batched launches
+};
+
+// Apply modes (kernel flags)
+enum ApplyIn { IN_ROLE = 0, IN_CONST_DE = 1 };
+enum Tangent { TAN_CURRENT = 0, TAN_IDENTITY = 1, TAN_ELASTIC = 2 };
+enum ApplyOut {
+  OUT_CG = 0,        // write AP, dot p.AP -> pAp, alpha
+  OUT_RESIDUAL = 1,  // write R and P, zero X, dot r.r -> rr, bnorm2, target2
+  OUT_PLAIN = 2      // write the out role only
+};
+
+struct LaunchCfg {
+  int rows_per_tile;   // z passes
+  int lines_y;         // y pass: h-block width
+  int lines_x;         // x pass: h-block width (x 6 components)
+  int vec_per_tile;    // elementwise kernels
+  int threads;
+};
+
+}  // namespace fftg

@@ -1,0 +1,796 @@
+// HIP kernels of the Galerkin-FFT Newton--CG hot path (gfx950).
+//
+// One application of G:(C:p) (paper Eq. linear_system, with G = F^-1 G^ F of
+// Eq. discrete_projection) is four launches over a half spectrum:
+//   zf : tau = C(x):p(x) per voxel, then real-to-complex DFT along axis 2
+//        (two real rows packed into one complex line);
+//   y  : complex DFT along axis 1, per component;
+//   x  : complex DFT along axis 0 for all six components, the projection
+//        G^(k):tau^(k) evaluated on the fly from k (Appendix A,
+//        Eq. FT_projection, with G^(0) = 0), inverse DFT along axis 0;
+//   y  : inverse DFT along axis 1;
+//   zi : complex-to-real inverse DFT along axis 2, fused CG dot product.
+// The per-voxel J2 return map and consistent tangent (Sec. 4.2) and the
+// CG vector updates (Algorithm 1) are elementwise kernels.
+//
+// Every kernel walks a list of tiles that may span several RVEs (batched
+// launches); a single solve is a batch of one.  Reductions are deterministic:
+// per-tile partial sums, summed in fixed order by the last tile to finish.
+#include <hip/hip_runtime.h>
+
+#include "fft_lds.h"
+#include "fftg_internal.h"
+
+namespace fftg {
+
+constexpr double kSqrt2 = 1.41421356237309504880;
+
+// ------------------------------------------------------------------ helpers
+__device__ __forceinline__ int find_rve(const RveDev* __restrict__ rv, int nrve, int pass, int& tile) {
+  int b = blockIdx.x;
+  for (int r = 0; r < nrve; ++r) {
+    const int n = rv[r].tiles[pass];
+    if (b < n) {
+      tile = b;
+      return r;
+    }
+    b -= n;
+  }
+  tile = -1;
+  return -1;
+}
+
+// Sum over the workgroup; result valid in thread 0.
+__device__ __forceinline__ double block_sum(double v, double* sh) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (lane == 0) sh[w] = v;
+  __syncthreads();
+  double r = 0.0;
+  if (threadIdx.x == 0) {
+    const int nw = (blockDim.x + 63) >> 6;
+    for (int i = 0; i < nw; ++i) r += sh[i];
+  }
+  __syncthreads();
+  return r;
+}
+
+// Publishes this tile's partial sums (nv values, in thread 0) and returns
+// true in every thread of the tile that finished last; that tile then sees
+// the totals in out[] (thread 0 only).  Sum order is fixed: tile 0, 1, ...
+__device__ bool reduce_tiles(const double* vals, int nv, double* partial, int ntiles, int tile,
+                             unsigned int* counter, double* sh, double* out) {
+  __shared__ int s_last;
+  if (threadIdx.x == 0) {
+    for (int i = 0; i < nv; ++i) partial[i * ntiles + tile] = vals[i];
+    __threadfence();
+    const unsigned int t = atomicAdd(counter, 1u);
+    s_last = (t == (unsigned int)(ntiles - 1));
+  }
+  __syncthreads();
+  const bool last = s_last;
+  if (!last) return false;
+  __threadfence();
+  for (int i = 0; i < nv; ++i) {
+    double acc = 0.0;
+    for (int t = threadIdx.x; t < ntiles; t += blockDim.x)
+      acc += __hip_atomic_load(partial + i * ntiles + t, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const double s = block_sum(acc, sh);
+    if (threadIdx.x == 0) out[i] = s;
+  }
+  if (threadIdx.x == 0) *counter = 0u;
+  return true;
+}
+
+template <class T>
+struct ApType;
+template <>
+struct ApType<double> {
+  typedef double type;
+};
+template <>
+struct ApType<float> {
+  typedef float type;
+};
+
+// Compact consistent tangent applied to a Mandel vector:
+// tau = (K - g2/3) tr(p) [1,1,1,0,0,0] + g2 p - (m.p) m.
+template <class T>
+__device__ __forceinline__ void tangent_apply(const T p[6], T K, T g2, const T m[6], T tau[6]) {
+  const T tr = p[0] + p[1] + p[2];
+  const T mp = m[0] * p[0] + m[1] * p[1] + m[2] * p[2] + m[3] * p[3] + m[4] * p[4] + m[5] * p[5];
+  const T lam = (K - g2 * T(1.0 / 3.0)) * tr;
+#pragma unroll
+  for (int c = 0; c < 6; ++c) tau[c] = g2 * p[c] - mp * m[c] + (c < 3 ? lam : T(0));
+}
+
+// G^(k) : T for a complex Mandel vector t, q = xi/|xi| (Appendix A):
+// (G^ : T)_ij = q_i v_j + q_j v_i - (q.v) q_i q_j, v = T q.
+template <class T>
+__device__ __forceinline__ void ghat_apply(cx<T> t[6], T q0, T q1, T q2, T scale) {
+  const T r2 = T(1.0 / kSqrt2);
+  cx<T> T11 = t[0], T22 = t[1], T33 = t[2];
+  cx<T> T23 = {t[3].re * r2, t[3].im * r2};
+  cx<T> T13 = {t[4].re * r2, t[4].im * r2};
+  cx<T> T12 = {t[5].re * r2, t[5].im * r2};
+  cx<T> v0 = {T11.re * q0 + T12.re * q1 + T13.re * q2, T11.im * q0 + T12.im * q1 + T13.im * q2};
+  cx<T> v1 = {T12.re * q0 + T22.re * q1 + T23.re * q2, T12.im * q0 + T22.im * q1 + T23.im * q2};
+  cx<T> v2 = {T13.re * q0 + T23.re * q1 + T33.re * q2, T13.im * q0 + T23.im * q1 + T33.im * q2};
+  cx<T> a = {q0 * v0.re + q1 * v1.re + q2 * v2.re, q0 * v0.im + q1 * v1.im + q2 * v2.im};
+  const T s2 = T(kSqrt2) * scale;
+  t[0] = {scale * (T(2) * q0 * v0.re - a.re * q0 * q0), scale * (T(2) * q0 * v0.im - a.im * q0 * q0)};
+  t[1] = {scale * (T(2) * q1 * v1.re - a.re * q1 * q1), scale * (T(2) * q1 * v1.im - a.im * q1 * q1)};
+  t[2] = {scale * (T(2) * q2 * v2.re - a.re * q2 * q2), scale * (T(2) * q2 * v2.im - a.im * q2 * q2)};
+  t[3] = {s2 * (q1 * v2.re + q2 * v1.re - a.re * q1 * q2), s2 * (q1 * v2.im + q2 * v1.im - a.im * q1 * q2)};
+  t[4] = {s2 * (q0 * v2.re + q2 * v0.re - a.re * q0 * q2), s2 * (q0 * v2.im + q2 * v0.im - a.im * q0 * q2)};
+  t[5] = {s2 * (q0 * v1.re + q1 * v0.re - a.re * q0 * q1), s2 * (q0 * v1.im + q1 * v0.im - a.im * q0 * q1)};
+}
+
+__device__ __forceinline__ int sfreq(int m, int n) { return (2 * m < n) ? m : m - n; }
+
+// LDS carve-up for a tile of nl lines of stride ld
+template <class T>
+struct TileLds {
+  cx<T>* line;
+  cx<T>* scratch;
+  cx<T>* dc;
+  double* red;
+  __device__ TileLds(char* base, int nl, int ld) {
+    line = reinterpret_cast<cx<T>*>(base);
+    scratch = line + (size_t)nl * ld;
+    dc = scratch + (size_t)nl * ld;
+    red = reinterpret_cast<double*>(dc + nl + (nl & 1));
+  }
+};
+
+// ------------------------------------------------------------- z forward
+// tau = C(x):p(x) (or p, or Ce:p, or C(x):dE) for a tile of rows, R2C along z.
+template <class T>
+__global__ void __launch_bounds__(256) k_zfwd(const RveDev* __restrict__ rvs, int nrve, int rows_per_tile,
+                                              int in_mode, int in_role, int tan_mode, int want_norm,
+                                              int check_done) {
+  extern __shared__ __align__(16) char smem[];
+  int tile;
+  const int ri = find_rve(rvs, nrve, P_ZF, tile);
+  if (ri < 0) return;
+  const RveDev& rv = rvs[ri];
+  if (rv.skip || (check_done && rv.cg->done)) return;
+  const int n2 = rv.n2, H = rv.H;
+  const long long nvox = rv.nvox, nspec = rv.nspec;
+  const int nrows_tot = rv.n0 * rv.n1;
+  const int row0 = tile * rows_per_tile;
+  const int nrows = min(rows_per_tile, nrows_tot - row0);
+  const int ld = n2;
+  TileLds<T> L(smem, 3 * rows_per_tile, ld);
+
+  const double* in = (const double*)rv.buf[in_role];
+  const T* tg = (const T*)rv.tang;
+  double nrm = 0.0;
+  for (int t = threadIdx.x; t < nrows * n2; t += blockDim.x) {
+    const int r = t / n2;
+    const int z = t - r * n2;
+    const long long v = (long long)(row0 + r) * n2 + z;
+    T p[6], tau[6];
+    if (in_mode == IN_CONST_DE) {
+#pragma unroll
+      for (int c = 0; c < 6; ++c) p[c] = T(rv.dE[c]);
+    } else {
+#pragma unroll
+      for (int c = 0; c < 6; ++c) p[c] = T(in[c * nvox + v]);
+    }
+    if (tan_mode == TAN_IDENTITY) {
+#pragma unroll
+      for (int c = 0; c < 6; ++c) tau[c] = p[c];
+    } else {
+      const MatDev& mt = rv.mats[rv.phase[v]];
+      T g2, m[6];
+      if (tan_mode == TAN_ELASTIC) {
+        g2 = T(2.0 * mt.G);
+#pragma unroll
+        for (int c = 0; c < 6; ++c) m[c] = T(0);
+      } else {
+        g2 = tg[v];
+#pragma unroll
+        for (int c = 0; c < 6; ++c) m[c] = tg[(c + 1) * nvox + v];
+      }
+      tangent_apply<T>(p, T(mt.K), g2, m, tau);
+    }
+    if (want_norm) {
+#pragma unroll
+      for (int c = 0; c < 6; ++c) nrm += double(tau[c]) * double(tau[c]);
+    }
+#pragma unroll
+    for (int pr = 0; pr < 3; ++pr) L.line[(3 * r + pr) * ld + z] = cx<T>{tau[2 * pr], tau[2 * pr + 1]};
+  }
+  __syncthreads();
+  cx<T>* res = line_fft<-1, T>(L.line, L.scratch, ld, 3 * nrows, *rv.ax[2], L.dc);
+  // untangle two real transforms: A_k = (Z_k + conj Z_-k)/2, B_k = (Z_k - conj Z_-k)/(2i)
+  cx<T>* spec = (cx<T>*)rv.spec;
+  for (int t = threadIdx.x; t < nrows * 3 * H; t += blockDim.x) {
+    const int rp = t / H;
+    const int k = t - rp * H;
+    const int r = rp / 3, pr = rp - 3 * r;
+    const cx<T> zk = res[rp * ld + k];
+    const cx<T> zm = res[rp * ld + (k == 0 ? 0 : n2 - k)];
+    const cx<T> A = {T(0.5) * (zk.re + zm.re), T(0.5) * (zk.im - zm.im)};
+    const cx<T> B = {T(0.5) * (zk.im + zm.im), T(-0.5) * (zk.re - zm.re)};
+    const long long o = (long long)(row0 + r) * H + k;
+    spec[(2 * pr) * nspec + o] = A;
+    spec[(2 * pr + 1) * nspec + o] = B;
+  }
+  if (want_norm) {
+    const double s = block_sum(nrm, L.red);
+    double tot;
+    if (reduce_tiles(&s, 1, rv.partial, rv.tiles[P_ZF], tile, &rv.cg->counter[0], L.red, &tot)) {
+      if (threadIdx.x == 0) rv.cg->snorm2 = tot;
+    }
+  }
+}
+
+// --------------------------------------------------------------- y pass
+template <class T, int DIR>
+__global__ void __launch_bounds__(256) k_ypass(const RveDev* __restrict__ rvs, int nrve, int lines_per_tile,
+                                               int check_done) {
+  extern __shared__ __align__(16) char smem[];
+  int tile;
+  const int ri = find_rve(rvs, nrve, P_Y, tile);
+  if (ri < 0) return;
+  const RveDev& rv = rvs[ri];
+  if (rv.skip || (check_done && rv.cg->done)) return;
+  const int n0 = rv.n0, n1 = rv.n1, H = rv.H;
+  const int nhb = (H + lines_per_tile - 1) / lines_per_tile;
+  const int c = tile / (n0 * nhb);
+  const int rem = tile - c * n0 * nhb;
+  const int i0 = rem / nhb;
+  const int h0 = (rem - i0 * nhb) * lines_per_tile;
+  const int nh = min(lines_per_tile, H - h0);
+  const int ld = n1;
+  TileLds<T> L(smem, lines_per_tile, ld);
+  cx<T>* base = (cx<T>*)rv.spec + c * rv.nspec + (long long)i0 * n1 * H + h0;
+  for (int t = threadIdx.x; t < n1 * nh; t += blockDim.x) {
+    const int y = t / nh;
+    const int hh = t - y * nh;
+    L.line[hh * ld + y] = base[(long long)y * H + hh];
+  }
+  __syncthreads();
+  cx<T>* res = line_fft<DIR, T>(L.line, L.scratch, ld, nh, *rv.ax[1], L.dc);
+  for (int t = threadIdx.x; t < n1 * nh; t += blockDim.x) {
+    const int y = t / nh;
+    const int hh = t - y * nh;
+    base[(long long)y * H + hh] = res[hh * ld + y];
+  }
+}
+
+// --------------------------------------------------- x pass with G^(k)
+template <class T>
+__global__ void __launch_bounds__(256) k_xpass(const RveDev* __restrict__ rvs, int nrve, int lines_per_tile,
+                                               double scale_in, int check_done) {
+  extern __shared__ __align__(16) char smem[];
+  int tile;
+  const int ri = find_rve(rvs, nrve, P_X, tile);
+  if (ri < 0) return;
+  const RveDev& rv = rvs[ri];
+  if (rv.skip || (check_done && rv.cg->done)) return;
+  const int n0 = rv.n0, n1 = rv.n1, n2 = rv.n2, H = rv.H;
+  const long long nspec = rv.nspec;
+  const int nhb = (H + lines_per_tile - 1) / lines_per_tile;
+  const int i1 = tile / nhb;
+  const int h0 = (tile - i1 * nhb) * lines_per_tile;
+  const int nh = min(lines_per_tile, H - h0);
+  const int ld = n0;
+  const int nl = 6 * nh;
+  TileLds<T> L(smem, 6 * lines_per_tile, ld);
+  cx<T>* spec = (cx<T>*)rv.spec;
+  const long long rs = (long long)n1 * H;
+  const long long off = (long long)i1 * H + h0;
+  for (int t = threadIdx.x; t < 6 * n0 * nh; t += blockDim.x) {
+    const int cx_ = t / (n0 * nh);
+    const int r = t - cx_ * n0 * nh;
+    const int x = r / nh;
+    const int hh = r - x * nh;
+    L.line[(cx_ * nh + hh) * ld + x] = spec[cx_ * nspec + x * rs + off + hh];
+  }
+  __syncthreads();
+  cx<T>* res = line_fft<-1, T>(L.line, L.scratch, ld, nl, *rv.ax[0], L.dc);
+  cx<T>* oth = (res == L.line) ? L.scratch : L.line;
+  // projection on every frequency (k0, k1, k2) of the tile; xi_i = k_i / L_i, L_i = n_i
+  const T scale = T(scale_in / double(rv.nvox));   // inverse DFT normalisation 1/|N|
+  const double k1 = double(sfreq(i1, n1)) / double(n1);
+  for (int t = threadIdx.x; t < n0 * nh; t += blockDim.x) {
+    const int x = t / nh;
+    const int hh = t - x * nh;
+    const double k0 = double(sfreq(x, n0)) / double(n0);
+    const double k2 = double(h0 + hh) / double(n2);
+    const double nn = k0 * k0 + k1 * k1 + k2 * k2;
+    cx<T> v[6];
+#pragma unroll
+    for (int c = 0; c < 6; ++c) v[c] = res[(c * nh + hh) * ld + x];
+    if (nn == 0.0) {
+#pragma unroll
+      for (int c = 0; c < 6; ++c) v[c] = cx<T>{T(0), T(0)};
+    } else {
+      const double inv = 1.0 / sqrt(nn);
+      ghat_apply<T>(v, T(k0 * inv), T(k1 * inv), T(k2 * inv), scale);
+    }
+#pragma unroll
+    for (int c = 0; c < 6; ++c) res[(c * nh + hh) * ld + x] = v[c];
+  }
+  __syncthreads();
+  cx<T>* res2 = line_fft<1, T>(res, oth, ld, nl, *rv.ax[0], L.dc);
+  for (int t = threadIdx.x; t < 6 * n0 * nh; t += blockDim.x) {
+    const int cx_ = t / (n0 * nh);
+    const int r = t - cx_ * n0 * nh;
+    const int x = r / nh;
+    const int hh = r - x * nh;
+    spec[cx_ * nspec + x * rs + off + hh] = res2[(cx_ * nh + hh) * ld + x];
+  }
+}
+
+// ------------------------------------------------------------- z inverse
+template <class T>
+__global__ void __launch_bounds__(256) k_zinv(const RveDev* __restrict__ rvs, int nrve, int rows_per_tile,
+                                              int out_mode, int out_role, int check_done) {
+  extern __shared__ __align__(16) char smem[];
+  int tile;
+  const int ri = find_rve(rvs, nrve, P_ZI, tile);
+  if (ri < 0) return;
+  const RveDev& rv = rvs[ri];
+  if (rv.skip || (check_done && rv.cg->done)) return;
+  const int n2 = rv.n2, H = rv.H;
+  const long long nvox = rv.nvox, nspec = rv.nspec;
+  const int nrows_tot = rv.n0 * rv.n1;
+  const int row0 = tile * rows_per_tile;
+  const int nrows = min(rows_per_tile, nrows_tot - row0);
+  const int ld = n2;
+  TileLds<T> L(smem, 3 * rows_per_tile, ld);
+  const cx<T>* spec = (const cx<T>*)rv.spec;
+  // Z_k = A_k + i B_k, Z_{n-k} = conj(A_k) + i conj(B_k)
+  for (int t = threadIdx.x; t < nrows * 3 * n2; t += blockDim.x) {
+    const int rp = t / n2;
+    const int z = t - rp * n2;
+    const int r = rp / 3, pr = rp - 3 * r;
+    const long long rowo = (long long)(row0 + r) * H;
+    cx<T> Z;
+    if (z < H) {
+      const cx<T> A = spec[(2 * pr) * nspec + rowo + z];
+      const cx<T> B = spec[(2 * pr + 1) * nspec + rowo + z];
+      Z = cx<T>{A.re - B.im, A.im + B.re};
+    } else {
+      const int k = n2 - z;
+      const cx<T> A = spec[(2 * pr) * nspec + rowo + k];
+      const cx<T> B = spec[(2 * pr + 1) * nspec + rowo + k];
+      Z = cx<T>{A.re + B.im, -A.im + B.re};
+    }
+    L.line[rp * ld + z] = Z;
+  }
+  __syncthreads();
+  cx<T>* res = line_fft<1, T>(L.line, L.scratch, ld, 3 * nrows, *rv.ax[2], L.dc);
+  double dot = 0.0;
+  if (out_mode == OUT_CG) {
+    typedef typename ApType<T>::type AT;
+    AT* out = (AT*)rv.buf[R_AP];
+    const double* p = (const double*)rv.buf[R_P];
+    for (int t = threadIdx.x; t < nrows * n2; t += blockDim.x) {
+      const int r = t / n2;
+      const int z = t - r * n2;
+      const long long v = (long long)(row0 + r) * n2 + z;
+#pragma unroll
+      for (int pr = 0; pr < 3; ++pr) {
+        const cx<T> w = res[(3 * r + pr) * ld + z];
+        const AT a0 = AT(w.re), a1 = AT(w.im);
+        out[(2 * pr) * nvox + v] = a0;
+        out[(2 * pr + 1) * nvox + v] = a1;
+        dot += p[(2 * pr) * nvox + v] * double(a0) + p[(2 * pr + 1) * nvox + v] * double(a1);
+      }
+    }
+  } else if (out_mode == OUT_RESIDUAL) {
+    double* rr = (double*)rv.buf[R_R];
+    double* pp = (double*)rv.buf[R_P];
+    double* xx = (double*)rv.buf[R_X];
+    for (int t = threadIdx.x; t < nrows * n2; t += blockDim.x) {
+      const int r = t / n2;
+      const int z = t - r * n2;
+      const long long v = (long long)(row0 + r) * n2 + z;
+#pragma unroll
+      for (int pr = 0; pr < 3; ++pr) {
+        const cx<T> w = res[(3 * r + pr) * ld + z];
+        const double a0 = double(w.re), a1 = double(w.im);
+        rr[(2 * pr) * nvox + v] = a0;
+        rr[(2 * pr + 1) * nvox + v] = a1;
+        pp[(2 * pr) * nvox + v] = a0;
+        pp[(2 * pr + 1) * nvox + v] = a1;
+        xx[(2 * pr) * nvox + v] = 0.0;
+        xx[(2 * pr + 1) * nvox + v] = 0.0;
+        dot += a0 * a0 + a1 * a1;
+      }
+    }
+  } else {
+    T* out = (T*)rv.buf[out_role];
+    for (int t = threadIdx.x; t < nrows * n2; t += blockDim.x) {
+      const int r = t / n2;
+      const int z = t - r * n2;
+      const long long v = (long long)(row0 + r) * n2 + z;
+#pragma unroll
+      for (int pr = 0; pr < 3; ++pr) {
+        const cx<T> w = res[(3 * r + pr) * ld + z];
+        out[(2 * pr) * nvox + v] = w.re;
+        out[(2 * pr + 1) * nvox + v] = w.im;
+      }
+    }
+    return;
+  }
+  const double s = block_sum(dot, L.red);
+  double tot;
+  if (reduce_tiles(&s, 1, rv.partial, rv.tiles[P_ZI], tile, &rv.cg->counter[1], L.red, &tot)) {
+    if (threadIdx.x == 0) {
+      CgState* cg = rv.cg;
+      if (out_mode == OUT_CG) {
+        cg->pAp = tot;
+        if (!(tot > 0.0)) {
+          cg->done = 1;
+          cg->status = CG_BREAKDOWN;
+        } else {
+          cg->alpha = cg->rr / tot;
+        }
+      } else {
+        cg->rr = tot;
+        cg->bnorm2 = tot;
+        const double t1 = cg->eta2 * tot, t2 = cg->floor2 * cg->snorm2;
+        cg->target2 = t1 > t2 ? t1 : t2;
+        cg->iters = 0;
+        if (cg->force >= 0) {
+          cg->done = (cg->force == 0);
+          cg->status = cg->done ? CG_FORCED : CG_RUNNING;
+        } else {
+          cg->done = (tot <= cg->target2);
+          cg->status = cg->done ? CG_CONVERGED : CG_RUNNING;
+        }
+      }
+    }
+  }
+}
+
+// ------------------------------------------------------ CG vector updates
+// x += alpha p; r -= alpha Ap; rr' = r.r; convergence test; beta.
+template <class AT>
+__global__ void __launch_bounds__(256) k_cg_xr(const RveDev* __restrict__ rvs, int nrve, int vox_per_tile) {
+  __shared__ double red[16];
+  int tile;
+  const int ri = find_rve(rvs, nrve, P_VEC, tile);
+  if (ri < 0) return;
+  const RveDev& rv = rvs[ri];
+  if (rv.skip || rv.cg->done) return;
+  const long long nvox = rv.nvox;
+  const double alpha = rv.cg->alpha;
+  double* x = (double*)rv.buf[R_X];
+  double* r = (double*)rv.buf[R_R];
+  const double* p = (const double*)rv.buf[R_P];
+  const AT* ap = (const AT*)rv.buf[R_AP];
+  const long long v0 = (long long)tile * vox_per_tile;
+  const int nv = (int)min((long long)vox_per_tile, nvox - v0);
+  double acc = 0.0;
+  for (int c = 0; c < 6; ++c) {
+    const long long o = c * nvox + v0;
+    for (int t = threadIdx.x; t < nv; t += blockDim.x) {
+      x[o + t] += alpha * p[o + t];
+      const double rn = r[o + t] - alpha * double(ap[o + t]);
+      r[o + t] = rn;
+      acc += rn * rn;
+    }
+  }
+  const double s = block_sum(acc, red);
+  double tot;
+  if (reduce_tiles(&s, 1, rv.partial, rv.tiles[P_VEC], tile, &rv.cg->counter[2], red, &tot)) {
+    if (threadIdx.x == 0) {
+      CgState* cg = rv.cg;
+      cg->iters += 1;
+      cg->rr_new = tot;
+      int done = 0, st = CG_RUNNING;
+      if (cg->force >= 0) {
+        if (cg->iters >= cg->force) {
+          done = 1;
+          st = CG_FORCED;
+        }
+      } else if (tot <= cg->target2) {
+        done = 1;
+        st = CG_CONVERGED;
+      } else if (cg->iters >= cg->max_iter) {
+        done = 1;
+        st = CG_MAXITER;
+      }
+      cg->beta = tot / cg->rr;
+      cg->rr = tot;
+      cg->status = st;
+      cg->done = done;
+    }
+  }
+}
+
+__global__ void __launch_bounds__(256) k_cg_p(const RveDev* __restrict__ rvs, int nrve, int vox_per_tile) {
+  int tile;
+  const int ri = find_rve(rvs, nrve, P_VEC, tile);
+  if (ri < 0) return;
+  const RveDev& rv = rvs[ri];
+  if (rv.skip || rv.cg->done) return;
+  const long long nvox = rv.nvox;
+  const double beta = rv.cg->beta;
+  const double* r = (const double*)rv.buf[R_R];
+  double* p = (double*)rv.buf[R_P];
+  const long long v0 = (long long)tile * vox_per_tile;
+  const int nv = (int)min((long long)vox_per_tile, nvox - v0);
+  for (int c = 0; c < 6; ++c) {
+    const long long o = c * nvox + v0;
+    for (int t = threadIdx.x; t < nv; t += blockDim.x) p[o + t] = r[o + t] + beta * p[o + t];
+  }
+}
+
+// eps* += x (Algorithm 1, iterative update) and ||x||^2.
+__global__ void __launch_bounds__(256) k_newton_update(const RveDev* __restrict__ rvs, int nrve, int vox_per_tile) {
+  __shared__ double red[16];
+  int tile;
+  const int ri = find_rve(rvs, nrve, P_VEC, tile);
+  if (ri < 0) return;
+  const RveDev& rv = rvs[ri];
+  if (rv.skip) return;
+  const long long nvox = rv.nvox;
+  double* e = (double*)rv.buf[R_EPS_FL];
+  const double* x = (const double*)rv.buf[R_X];
+  const long long v0 = (long long)tile * vox_per_tile;
+  const int nv = (int)min((long long)vox_per_tile, nvox - v0);
+  double acc = 0.0;
+  for (int c = 0; c < 6; ++c) {
+    const long long o = c * nvox + v0;
+    for (int t = threadIdx.x; t < nv; t += blockDim.x) {
+      const double d = x[o + t];
+      e[o + t] += d;
+      acc += d * d;
+    }
+  }
+  const double s = block_sum(acc, red);
+  double tot;
+  if (reduce_tiles(&s, 1, rv.partial, rv.tiles[P_VEC], tile, &rv.cg->counter[3], red, &tot)) {
+    if (threadIdx.x == 0) rv.cg->dnorm2 = tot;
+  }
+}
+
+// ------------------------------------------------ J2 return map (Sec. 4.2)
+// Trial state from the committed history; elastic when Phi_tr <= 0, else
+// closed-form dgamma = Phi_tr / (3G + H) (n = 1) along N = 3/2 s_tr/seq_tr.
+// Writes sigma (Mandel), the compact tangent {2G', m = sqrt(-c) N} with
+// 2G' = 2G (1 - 3G dgamma/seq_tr), c = 4G^2 (dgamma/seq_tr - 1/(3G+H)),
+// and, when committing, the new history and per-tile sums of sigma.
+template <class TT>
+__global__ void __launch_bounds__(256) k_constitutive(const RveDev* __restrict__ rvs, int nrve, int vox_per_tile,
+                                                      int eps_role, int commit) {
+  __shared__ double red[16];
+  int tile;
+  const int ri = find_rve(rvs, nrve, P_VEC, tile);
+  if (ri < 0) return;
+  const RveDev& rv = rvs[ri];
+  if (rv.skip) return;
+  const long long nvox = rv.nvox;
+  const double* ein = (const double*)rv.buf[eps_role];
+  const bool add_E = (eps_role == R_EPS_FL);
+  double* ep = (double*)rv.buf[R_EPS_P];
+  double* eb = (double*)rv.buf[R_EPBAR];
+  double* sg = (double*)rv.buf[R_SIG];
+  TT* tg = (TT*)rv.tang;
+  const long long v0 = (long long)tile * vox_per_tile;
+  const int nv = (int)min((long long)vox_per_tile, nvox - v0);
+  double ssum[6] = {0, 0, 0, 0, 0, 0};
+  for (int t = threadIdx.x; t < nv; t += blockDim.x) {
+    const long long v = v0 + t;
+    const MatDev mt = rv.mats[rv.phase[v]];
+    double e[6], epv[6];
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+      e[c] = ein[c * nvox + v] + (add_E ? rv.E[c] : 0.0);
+      epv[c] = ep[c * nvox + v];
+    }
+    const double ebv = eb[v];
+    double d[6];
+#pragma unroll
+    for (int c = 0; c < 6; ++c) d[c] = e[c] - epv[c];
+    const double tr = d[0] + d[1] + d[2];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) d[c] -= tr * (1.0 / 3.0);
+    double dd = 0.0;
+#pragma unroll
+    for (int c = 0; c < 6; ++c) dd += d[c] * d[c];
+    const double G = mt.G, K = mt.K;
+    const double seq = 2.0 * G * sqrt(1.5 * dd);
+    const double phi = seq - (mt.sy0 + mt.H * ebv);
+    double sig[6], g2, m[6];
+    if (phi > 0.0) {
+      const double dg = phi / (3.0 * G + mt.H);
+      const double ns = 1.5 * 2.0 * G / seq;   // N = ns * d
+      double Nv[6];
+#pragma unroll
+      for (int c = 0; c < 6; ++c) Nv[c] = ns * d[c];
+      const double cc = 4.0 * G * G * (dg / seq - 1.0 / (3.0 * G + mt.H));
+      const double sm = sqrt(-cc);
+      g2 = 2.0 * G * (1.0 - 3.0 * G * dg / seq);
+#pragma unroll
+      for (int c = 0; c < 6; ++c) {
+        sig[c] = 2.0 * G * (d[c] - dg * Nv[c]) + (c < 3 ? K * tr : 0.0);
+        m[c] = sm * Nv[c];
+      }
+      if (commit) {
+#pragma unroll
+        for (int c = 0; c < 6; ++c) ep[c * nvox + v] = epv[c] + dg * Nv[c];
+        eb[v] = ebv + dg;
+      }
+    } else {
+      g2 = 2.0 * G;
+#pragma unroll
+      for (int c = 0; c < 6; ++c) {
+        sig[c] = 2.0 * G * d[c] + (c < 3 ? K * tr : 0.0);
+        m[c] = 0.0;
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+      sg[c * nvox + v] = sig[c];
+      ssum[c] += sig[c];
+    }
+    tg[v] = TT(g2);
+#pragma unroll
+    for (int c = 0; c < 6; ++c) tg[(c + 1) * nvox + v] = TT(m[c]);
+  }
+  if (commit) {
+    double s[6];
+    for (int c = 0; c < 6; ++c) s[c] = block_sum(ssum[c], red);
+    double tot[6];
+    if (reduce_tiles(s, 6, rv.partial, rv.tiles[P_VEC], tile, &rv.cg->counter[4], red, tot)) {
+      if (threadIdx.x == 0)
+        for (int c = 0; c < 6; ++c) rv.cg->Sigma[c] = tot[c] / double(nvox);
+    }
+  }
+}
+
+// CG configuration of every RVE of a launch before a linear solve.
+__global__ void k_cg_setup(RveDev* __restrict__ rvs, int nrve, double eta2, double floor2, int max_iter,
+                           int force) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= nrve) return;
+  CgState* cg = rvs[r].cg;
+  cg->eta2 = eta2;
+  cg->floor2 = floor2;
+  cg->max_iter = max_iter;
+  cg->force = force;
+  cg->iters = 0;
+  cg->done = 0;
+  cg->status = CG_RUNNING;
+}
+
+__global__ void k_add_const(double* __restrict__ f, long long nvox, double e0, double e1, double e2, double e3,
+                            double e4, double e5) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= 6 * nvox) return;
+  const int c = (int)(i / nvox);
+  const double e[6] = {e0, e1, e2, e3, e4, e5};
+  f[i] += e[c];
+}
+
+// ------------------------------------------------------------ launchers
+template <class T>
+static size_t tile_lds(int nl, int ld) {
+  return (size_t)2 * nl * ld * sizeof(cx<T>) + (size_t)(nl + 2) * sizeof(cx<T>) + 16 * sizeof(double) + 64;
+}
+
+size_t lds_z(int mixed, int rows, int n2) {
+  return mixed ? tile_lds<float>(3 * rows, n2) : tile_lds<double>(3 * rows, n2);
+}
+size_t lds_y(int mixed, int lines, int n1) {
+  return mixed ? tile_lds<float>(lines, n1) : tile_lds<double>(lines, n1);
+}
+size_t lds_x(int mixed, int lines, int n0) {
+  return mixed ? tile_lds<float>(6 * lines, n0) : tile_lds<double>(6 * lines, n0);
+}
+
+hipError_t launch_zfwd(int mixed, const RveDev* rv, int nrve, int tiles, const LaunchCfg& cfg, size_t lds,
+                       int in_mode, int in_role, int tan_mode, int want_norm, int check_done, hipStream_t s) {
+  if (tiles <= 0) return hipSuccess;
+  if (mixed)
+    hipLaunchKernelGGL(k_zfwd<float>, dim3(tiles), dim3(cfg.threads), lds, s, rv, nrve, cfg.rows_per_tile,
+                       in_mode, in_role, tan_mode, want_norm, check_done);
+  else
+    hipLaunchKernelGGL(k_zfwd<double>, dim3(tiles), dim3(cfg.threads), lds, s, rv, nrve, cfg.rows_per_tile,
+                       in_mode, in_role, tan_mode, want_norm, check_done);
+  return hipGetLastError();
+}
+
+hipError_t launch_ypass(int mixed, int dir, const RveDev* rv, int nrve, int tiles, const LaunchCfg& cfg,
+                        size_t lds, int check_done, hipStream_t s) {
+  if (tiles <= 0) return hipSuccess;
+  if (mixed) {
+    if (dir < 0)
+      hipLaunchKernelGGL((k_ypass<float, -1>), dim3(tiles), dim3(cfg.threads), lds, s, rv, nrve,
+                         cfg.lines_y, check_done);
+    else
+      hipLaunchKernelGGL((k_ypass<float, 1>), dim3(tiles), dim3(cfg.threads), lds, s, rv, nrve,
+                         cfg.lines_y, check_done);
+  } else {
+    if (dir < 0)
+      hipLaunchKernelGGL((k_ypass<double, -1>), dim3(tiles), dim3(cfg.threads), lds, s, rv, nrve,
+                         cfg.lines_y, check_done);
+    else
+      hipLaunchKernelGGL((k_ypass<double, 1>), dim3(tiles), dim3(cfg.threads), lds, s, rv, nrve,
+                         cfg.lines_y, check_done);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_xpass(int mixed, const RveDev* rv, int nrve, int tiles, const LaunchCfg& cfg, size_t lds,
+                        double scale, int check_done, hipStream_t s) {
+  if (tiles <= 0) return hipSuccess;
+  if (mixed)
+    hipLaunchKernelGGL(k_xpass<float>, dim3(tiles), dim3(cfg.threads), lds, s, rv, nrve, cfg.lines_x, scale,
+                       check_done);
+  else
+    hipLaunchKernelGGL(k_xpass<double>, dim3(tiles), dim3(cfg.threads), lds, s, rv, nrve, cfg.lines_x, scale,
+                       check_done);
+  return hipGetLastError();
+}
+
+hipError_t launch_zinv(int mixed, const RveDev* rv, int nrve, int tiles, const LaunchCfg& cfg, size_t lds,
+                       int out_mode, int out_role, int check_done, hipStream_t s) {
+  if (tiles <= 0) return hipSuccess;
+  if (mixed)
+    hipLaunchKernelGGL(k_zinv<float>, dim3(tiles), dim3(cfg.threads), lds, s, rv, nrve, cfg.rows_per_tile,
+                       out_mode, out_role, check_done);
+  else
+    hipLaunchKernelGGL(k_zinv<double>, dim3(tiles), dim3(cfg.threads), lds, s, rv, nrve, cfg.rows_per_tile,
+                       out_mode, out_role, check_done);
+  return hipGetLastError();
+}
+
+hipError_t launch_cg_xr(int mixed, const RveDev* rv, int nrve, int tiles, const LaunchCfg& cfg, hipStream_t s) {
+  if (tiles <= 0) return hipSuccess;
+  if (mixed)
+    hipLaunchKernelGGL(k_cg_xr<float>, dim3(tiles), dim3(cfg.threads), 0, s, rv, nrve, cfg.vec_per_tile);
+  else
+    hipLaunchKernelGGL(k_cg_xr<double>, dim3(tiles), dim3(cfg.threads), 0, s, rv, nrve, cfg.vec_per_tile);
+  return hipGetLastError();
+}
+
+hipError_t launch_cg_p(const RveDev* rv, int nrve, int tiles, const LaunchCfg& cfg, hipStream_t s) {
+  if (tiles <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_cg_p, dim3(tiles), dim3(cfg.threads), 0, s, rv, nrve, cfg.vec_per_tile);
+  return hipGetLastError();
+}
+
+hipError_t launch_newton_update(const RveDev* rv, int nrve, int tiles, const LaunchCfg& cfg, hipStream_t s) {
+  if (tiles <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_newton_update, dim3(tiles), dim3(cfg.threads), 0, s, rv, nrve, cfg.vec_per_tile);
+  return hipGetLastError();
+}
+
+hipError_t launch_constitutive(int mixed, const RveDev* rv, int nrve, int tiles, const LaunchCfg& cfg,
+                               int eps_role, int commit, hipStream_t s) {
+  if (tiles <= 0) return hipSuccess;
+  if (mixed)
+    hipLaunchKernelGGL(k_constitutive<float>, dim3(tiles), dim3(cfg.threads), 0, s, rv, nrve, cfg.vec_per_tile,
+                       eps_role, commit);
+  else
+    hipLaunchKernelGGL(k_constitutive<double>, dim3(tiles), dim3(cfg.threads), 0, s, rv, nrve,
+                       cfg.vec_per_tile, eps_role, commit);
+  return hipGetLastError();
+}
+
+hipError_t launch_cg_setup(const RveDev* rv, int nrve, double eta2, double floor2, int max_iter, int force,
+                           hipStream_t s) {
+  hipLaunchKernelGGL(k_cg_setup, dim3((nrve + 63) / 64), dim3(64), 0, s, (RveDev*)rv, nrve, eta2, floor2,
+                     max_iter, force);
+  return hipGetLastError();
+}
+
+}  // namespace fftg
+
+hipError_t fftg_add_const(double* f, long long nvox, const double* E, hipStream_t s) {
+  const long long n = 6 * nvox;
+  hipLaunchKernelGGL(fftg::k_add_const, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, f, nvox, E[0], E[1],
+                     E[2], E[3], E[4], E[5]);
+  return hipGetLastError();
+}

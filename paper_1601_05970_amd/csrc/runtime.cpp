@@ -1,0 +1,1153 @@
+// Host runtime of the Galerkin-FFT library: plans, histories, the Newton--CG
+// driver of Algorithm 1 and batched groups.  Everything below the C ABI in
+// include/fftg.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "../../include/fftg.h"
+#include "fftg_internal.h"
+
+using namespace fftg;
+
+namespace fftg {
+size_t lds_z(int mixed, int rows, int n2);
+size_t lds_y(int mixed, int lines, int n1);
+size_t lds_x(int mixed, int lines, int n0);
+hipError_t launch_zfwd(int mixed, const RveDev* rv, int nrve, int tiles, const LaunchCfg& cfg, size_t lds,
+                       int in_mode, int in_role, int tan_mode, int want_norm, int check_done, hipStream_t s);
+hipError_t launch_ypass(int mixed, int dir, const RveDev* rv, int nrve, int tiles, const LaunchCfg& cfg,
+                        size_t lds, int check_done, hipStream_t s);
+hipError_t launch_xpass(int mixed, const RveDev* rv, int nrve, int tiles, const LaunchCfg& cfg, size_t lds,
+                        double scale, int check_done, hipStream_t s);
+hipError_t launch_zinv(int mixed, const RveDev* rv, int nrve, int tiles, const LaunchCfg& cfg, size_t lds,
+                       int out_mode, int out_role, int check_done, hipStream_t s);
+hipError_t launch_cg_xr(int mixed, const RveDev* rv, int nrve, int tiles, const LaunchCfg& cfg, hipStream_t s);
+hipError_t launch_cg_p(const RveDev* rv, int nrve, int tiles, const LaunchCfg& cfg, hipStream_t s);
+hipError_t launch_newton_update(const RveDev* rv, int nrve, int tiles, const LaunchCfg& cfg, hipStream_t s);
+hipError_t launch_constitutive(int mixed, const RveDev* rv, int nrve, int tiles, const LaunchCfg& cfg,
+                               int eps_role, int commit, hipStream_t s);
+hipError_t launch_cg_setup(const RveDev* rv, int nrve, double eta2, double floor2, int max_iter, int force,
+                           hipStream_t s);
+}  // namespace fftg
+
+// ------------------------------------------------------------------ errors
+static thread_local std::string g_err;
+
+static fftg_status fail(fftg_status st, const std::string& msg) {
+  g_err = msg;
+  return st;
+}
+
+#define HIP_TRY(expr)                                                                       \
+  do {                                                                                      \
+    hipError_t e_ = (expr);                                                                 \
+    if (e_ != hipSuccess)                                                                   \
+      return fail(e_ == hipErrorOutOfMemory ? FFTG_E_NOMEM : FFTG_E_HIP,                    \
+                  std::string(#expr) + ": " + hipGetErrorString(e_));                       \
+  } while (0)
+
+static const double kSqrt2 = 1.41421356237309504880;
+
+static void tensor_to_mandel(const double t[6], double m[6]) {
+  for (int c = 0; c < 3; ++c) m[c] = t[c];
+  for (int c = 3; c < 6; ++c) m[c] = kSqrt2 * t[c];
+}
+static void mandel_to_tensor(const double m[6], double t[6]) {
+  for (int c = 0; c < 3; ++c) t[c] = m[c];
+  for (int c = 3; c < 6; ++c) t[c] = m[c] / kSqrt2;
+}
+
+// --------------------------------------------------------------- FFT plans
+static bool is_prime(int p) {
+  if (p < 2) return false;
+  for (int d = 2; d * d <= p; ++d)
+    if (p % d == 0) return false;
+  return true;
+}
+
+// Factor M into the direct radices; false when something is left over.
+static bool factor_chain(int M, std::vector<int>& rad) {
+  rad.clear();
+  int m = M;
+  while (m % 4 == 0) {
+    rad.push_back(4);
+    m /= 4;
+  }
+  if (m % 2 == 0) {
+    rad.push_back(2);
+    m /= 2;
+  }
+  const int odd[] = {9, 7, 5, 3, 11, 13, 17};
+  for (int r : odd)
+    while (m % r == 0) {
+      rad.push_back(r);
+      m /= r;
+    }
+  return m == 1 && (int)rad.size() <= kMaxStages;
+}
+
+static long long powmod(long long b, long long e, long long m) {
+  long long r = 1 % m;
+  b %= m;
+  while (e > 0) {
+    if (e & 1) r = r * b % m;
+    b = b * b % m;
+    e >>= 1;
+  }
+  return r;
+}
+
+static int primitive_root(int p) {
+  std::vector<int> f;
+  int m = p - 1;
+  for (int d = 2; d * d <= m; ++d)
+    if (m % d == 0) {
+      f.push_back(d);
+      while (m % d == 0) m /= d;
+    }
+  if (m > 1) f.push_back(m);
+  for (int g = 2; g < p; ++g) {
+    bool ok = true;
+    for (int q : f)
+      if (powmod(g, (p - 1) / q, p) == 1) {
+        ok = false;
+        break;
+      }
+    if (ok) return g;
+  }
+  return -1;
+}
+
+static const long double kPiL = 3.141592653589793238462643383279502884L;
+
+struct AxisHost {
+  AxisDev dev;
+  std::vector<void*> allocs;
+};
+
+template <class T>
+static hipError_t upload(const std::vector<T>& v, T** out, std::vector<void*>& allocs) {
+  *out = nullptr;
+  if (v.empty()) return hipSuccess;
+  hipError_t e = hipMalloc((void**)out, v.size() * sizeof(T));
+  if (e != hipSuccess) return e;
+  allocs.push_back(*out);
+  return hipMemcpy(*out, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice);
+}
+
+// Builds the transform of length N: direct chain or Rader.
+static fftg_status build_axis(int N, AxisHost& ax) {
+  AxisDev& d = ax.dev;
+  memset(&d, 0, sizeof(d));
+  d.N = N;
+  std::vector<int> rad;
+  if (N == 1) {
+    d.rader = 0;
+    d.M = 1;
+    d.nst = 0;
+  } else if (factor_chain(N, rad) && (N % 2 == 1)) {
+    d.rader = 0;
+    d.M = N;
+  } else if (is_prime(N) && factor_chain(N - 1, rad)) {
+    d.rader = 1;
+    d.M = N - 1;
+  } else {
+    return fail(FFTG_E_UNSUPPORTED, "grid extent " + std::to_string(N) +
+                                        " not supported (needs factors 3,5,7,11,13,17 or a prime p with smooth p-1)");
+  }
+  if (N > kMaxAxisLen) return fail(FFTG_E_UNSUPPORTED, "grid extent too large");
+  d.nst = (int)rad.size();
+  for (int i = 0; i < d.nst; ++i) d.radix[i] = rad[i];
+  const int M = d.M;
+  std::vector<cx<double>> tw64(M);
+  std::vector<cx<float>> tw32(M);
+  for (int m = 0; m < M; ++m) {
+    const long double a = -2.0L * kPiL * (long double)m / (long double)M;
+    tw64[m] = {(double)cosl(a), (double)sinl(a)};
+    tw32[m] = {(float)cosl(a), (float)sinl(a)};
+  }
+  cx<double>* p64;
+  cx<float>* p32;
+  hipError_t ue = upload(tw64, &p64, ax.allocs);
+  if (ue == hipSuccess) ue = upload(tw32, &p32, ax.allocs);
+  if (ue != hipSuccess)
+    return fail(ue == hipErrorOutOfMemory ? FFTG_E_NOMEM : FFTG_E_HIP,
+                std::string("twiddle upload: ") + hipGetErrorName(ue) + " " + hipGetErrorString(ue));
+  d.tw64 = p64;
+  d.tw32 = p32;
+  if (d.rader) {
+    const int p = N;
+    const int g = primitive_root(p);
+    const int ginv = (int)powmod(g, p - 2, p);
+    std::vector<int> pin(M), pout(M);
+    for (int q = 0; q < M; ++q) {
+      pin[q] = (int)powmod(g, q, p);
+      pout[q] = (int)powmod(ginv, q, p);
+    }
+    // b_j = exp(-+ 2 pi i g^-j / p); Bhat = DFT_M(b) / M
+    std::vector<cx<double>> bf64(M), bi64(M);
+    std::vector<cx<float>> bf32(M), bi32(M);
+    for (int k = 0; k < M; ++k) {
+      long double fr = 0, fi = 0, ir = 0, ii = 0;
+      for (int j = 0; j < M; ++j) {
+        const long double th = 2.0L * kPiL * (long double)pout[j] / (long double)p;
+        const long double ph = -2.0L * kPiL * (long double)((long long)j * k % M) / (long double)M;
+        const long double cb = cosl(th), sb = sinl(th), cp = cosl(ph), sp = sinl(ph);
+        // forward b = cb - i sb ; inverse b = cb + i sb ; times (cp + i sp)
+        fr += cb * cp + sb * sp;
+        fi += cb * sp - sb * cp;
+        ir += cb * cp - sb * sp;
+        ii += cb * sp + sb * cp;
+      }
+      bf64[k] = {(double)(fr / M), (double)(fi / M)};
+      bi64[k] = {(double)(ir / M), (double)(ii / M)};
+      bf32[k] = {(float)(fr / M), (float)(fi / M)};
+      bi32[k] = {(float)(ir / M), (float)(ii / M)};
+    }
+    int *dpin = nullptr, *dpout = nullptr;
+    cx<double>*a = nullptr, *b = nullptr;
+    cx<float>*c = nullptr, *e = nullptr;
+    hipError_t re = upload(pin, &dpin, ax.allocs);
+    if (re == hipSuccess) re = upload(pout, &dpout, ax.allocs);
+    if (re == hipSuccess) re = upload(bf64, &a, ax.allocs);
+    if (re == hipSuccess) re = upload(bi64, &b, ax.allocs);
+    if (re == hipSuccess) re = upload(bf32, &c, ax.allocs);
+    if (re == hipSuccess) re = upload(bi32, &e, ax.allocs);
+    if (re != hipSuccess)
+      return fail(re == hipErrorOutOfMemory ? FFTG_E_NOMEM : FFTG_E_HIP,
+                  std::string("Rader table upload: ") + hipGetErrorName(re) + " " + hipGetErrorString(re));
+    d.perm_in = dpin;
+    d.perm_out = dpout;
+    d.bf64 = a;
+    d.bi64 = b;
+    d.bf32 = c;
+    d.bi32 = e;
+  }
+  return FFTG_OK;
+}
+
+// ------------------------------------------------------------------- plan
+struct fftg_plan_s {
+  int n[3];
+  int H;
+  long long nvox, nspec;
+  fftg_options opt;
+  int mixed;
+  hipStream_t stream;
+  int n_phases;
+  MatDev mats[kMaxPhases];
+  std::vector<void*> allocs;
+  std::vector<AxisHost> axes;  // distinct lengths
+  AxisDev* d_ax[3];
+  uint8_t* d_phase;
+  void* spec;
+  double *sig, *x, *r, *p;
+  void* ap;
+  double* partial;
+  CgState* cg;
+  RveDev* d_rv;       // single-RVE descriptor slot
+  RveDev* h_stage;    // pinned staging ring for descriptor uploads
+  hipEvent_t stage_ev[4];
+  int stage_next;
+  CgState* h_cg;      // pinned
+  int max_tiles;
+};
+
+struct fftg_history_s {
+  fftg_plan plan;
+  double *eps_fl, *eps_p, *epbar;
+  void* tang;
+  double E[6];  // Mandel
+  int inc;
+};
+
+void fftg_options_default(fftg_options* o) {
+  o->precision = FFTG_FP64;
+  o->tol_newton = 1e-5;
+  o->tol_cg = 1e-8;
+  o->max_newton = 50;
+  o->max_cg = 2000;
+  o->predictor = FFTG_PREDICTOR_TANGENT;
+  o->rhs_floor = 1e-14;
+  o->mixed_cg_floor = 1e-5;
+  o->cg_chunk = 16;
+}
+
+// Tile sizes fit the FP64 passes in 64 KB of LDS (mixed plans also run the
+// FP64 residual with the same configuration).
+static LaunchCfg choose_cfg(int n0, int n1, int n2, long long nvox) {
+  LaunchCfg c;
+  c.threads = 256;
+  const size_t budget = 64 * 1024;
+  int R = 8;
+  while (R > 1 && lds_z(0, R, n2) > budget) --R;
+  c.rows_per_tile = R;
+  int L = 16;
+  while (L > 1 && lds_y(0, L, n1) > budget) --L;
+  c.lines_y = L;
+  int Lx = 8;
+  while (Lx > 1 && lds_x(0, Lx, n0) > budget) --Lx;
+  c.lines_x = Lx;
+  long long v = nvox / 2048;
+  v = std::max(256LL, std::min(4096LL, v));
+  c.vec_per_tile = (int)((v + 255) / 256 * 256);
+  return c;
+}
+
+static void compute_tiles(const LaunchCfg& c, int n0, int n1, int n2, long long nvox, int tiles[P_NPASS]) {
+  const int H = (n2 + 1) / 2;
+  const int rows = n0 * n1;
+  tiles[P_ZF] = (rows + c.rows_per_tile - 1) / c.rows_per_tile;
+  tiles[P_ZI] = tiles[P_ZF];
+  tiles[P_Y] = 6 * n0 * ((H + c.lines_y - 1) / c.lines_y);
+  tiles[P_X] = n1 * ((H + c.lines_x - 1) / c.lines_x);
+  tiles[P_VEC] = (int)((nvox + c.vec_per_tile - 1) / c.vec_per_tile);
+}
+
+static int max_tiles_any(int n0, int n1, int n2, long long nvox) {
+  // worst case over configurations with >= 1 row / line / 256 voxels per tile
+  const int H = (n2 + 1) / 2;
+  long long a = (long long)n0 * n1;
+  long long b = 6LL * n0 * H;
+  long long c = (long long)n1 * H;
+  long long d = (nvox + 255) / 256;
+  return (int)std::max(std::max(a, b), std::max(c, d));
+}
+
+static size_t plan_bytes(int n0, int n1, int n2, int mixed) {
+  const long long nvox = (long long)n0 * n1 * n2;
+  const long long nspec = (long long)n0 * n1 * ((n2 + 1) / 2);
+  size_t b = 0;
+  b += 6 * nspec * 16;                   // spectrum (complex double)
+  b += 4 * 6 * nvox * 8;                 // sig, x, r, p
+  b += 6 * nvox * (mixed ? 4 : 8);       // Ap
+  b += nvox;                             // phase
+  b += 6 * (size_t)max_tiles_any(n0, n1, n2, nvox) * 8 + 4096;
+  return b;
+}
+
+static size_t history_bytes(int n0, int n1, int n2, int mixed) {
+  const long long nvox = (long long)n0 * n1 * n2;
+  return (size_t)nvox * (13 * 8 + 7 * (mixed ? 4 : 8));
+}
+
+size_t fftg_footprint_bytes(int n0, int n1, int n2, int precision) {
+  if (n0 <= 0 || n1 <= 0 || n2 <= 0) return 0;
+  const int mixed = precision == FFTG_MIXED;
+  return plan_bytes(n0, n1, n2, mixed) + history_bytes(n0, n1, n2, mixed);
+}
+
+template <class T>
+static hipError_t dalloc(fftg_plan pl, T** p, size_t bytes) {
+  hipError_t e = hipMalloc((void**)p, bytes);
+  if (e == hipSuccess) pl->allocs.push_back(*p);
+  return e;
+}
+
+static void plan_free(fftg_plan pl) {
+  if (!pl) return;
+  hipStreamSynchronize(pl->stream);
+  for (void* p : pl->allocs) hipFree(p);
+  for (auto& a : pl->axes)
+    for (void* p : a.allocs) hipFree(p);
+  if (pl->h_stage) hipHostFree(pl->h_stage);
+  if (pl->h_cg) hipHostFree(pl->h_cg);
+  for (int i = 0; i < 4; ++i)
+    if (pl->stage_ev[i]) hipEventDestroy(pl->stage_ev[i]);
+  delete pl;
+}
+
+fftg_status fftg_plan_create(fftg_plan* out, int n0, int n1, int n2, const uint8_t* phase, int n_phases,
+                             const fftg_material* mats, const fftg_options* opt, void* hip_stream) {
+  if (!out) return fail(FFTG_E_INVALID, "out is NULL");
+  *out = nullptr;
+  const int ns[3] = {n0, n1, n2};
+  for (int i = 0; i < 3; ++i)
+    if (ns[i] < 1 || ns[i] % 2 == 0) return fail(FFTG_E_INVALID, "grid extents must be odd and >= 1");
+  if (!phase || !mats) return fail(FFTG_E_INVALID, "phase / mats is NULL");
+  if (n_phases < 1 || n_phases > kMaxPhases) return fail(FFTG_E_INVALID, "n_phases must be in 1..16");
+  for (int i = 0; i < n_phases; ++i) {
+    const fftg_material& m = mats[i];
+    if (!(m.K > 0) || !(m.G > 0) || !(m.sigma_y0 > 0) || !(m.H >= 0))
+      return fail(FFTG_E_INVALID, "material " + std::to_string(i) + ": need K > 0, G > 0, sigma_y0 > 0, H >= 0");
+    if (m.n != 1.0) return fail(FFTG_E_UNSUPPORTED, "only linear hardening (n = 1) is implemented");
+  }
+  const long long nvox = (long long)n0 * n1 * n2;
+  for (long long v = 0; v < nvox; ++v)
+    if (phase[v] >= n_phases) return fail(FFTG_E_INVALID, "phase id out of range");
+  fftg_options o;
+  fftg_options_default(&o);
+  if (opt) o = *opt;
+  if (o.precision != FFTG_FP64 && o.precision != FFTG_MIXED) return fail(FFTG_E_INVALID, "bad precision");
+  if (o.max_newton < 1 || o.max_newton > FFTG_MAX_NEWTON) return fail(FFTG_E_INVALID, "max_newton out of range");
+  if (o.max_cg < 1 || !(o.tol_cg >= 0) || !(o.tol_newton >= 0) || o.cg_chunk < 1)
+    return fail(FFTG_E_INVALID, "bad tolerances / iteration caps");
+
+  fftg_plan pl = new fftg_plan_s();
+  memset(pl->stage_ev, 0, sizeof(pl->stage_ev));
+  pl->n[0] = n0;
+  pl->n[1] = n1;
+  pl->n[2] = n2;
+  pl->H = (n2 + 1) / 2;
+  pl->nvox = nvox;
+  pl->nspec = (long long)n0 * n1 * pl->H;
+  pl->opt = o;
+  pl->mixed = o.precision == FFTG_MIXED;
+  pl->stream = (hipStream_t)hip_stream;
+  pl->n_phases = n_phases;
+  for (int i = 0; i < n_phases; ++i) pl->mats[i] = {mats[i].K, mats[i].G, mats[i].sigma_y0, mats[i].H};
+  fftg_status st = FFTG_OK;
+  // transforms
+  std::map<int, int> idx;
+  for (int i = 0; i < 3; ++i) {
+    if (idx.count(ns[i])) continue;
+    pl->axes.emplace_back();
+    st = build_axis(ns[i], pl->axes.back());
+    if (st != FFTG_OK) {
+      plan_free(pl);
+      return st;
+    }
+    idx[ns[i]] = (int)pl->axes.size() - 1;
+  }
+  hipError_t e = hipSuccess;
+#define PLAN_TRY(expr)                                                            \
+  do {                                                                            \
+    e = (expr);                                                                   \
+    if (e != hipSuccess) {                                                        \
+      plan_free(pl);                                                              \
+      return fail(e == hipErrorOutOfMemory ? FFTG_E_NOMEM : FFTG_E_HIP,           \
+                  std::string(#expr) + ": " + hipGetErrorString(e));              \
+    }                                                                             \
+  } while (0)
+  for (int i = 0; i < 3; ++i) {
+    PLAN_TRY(dalloc(pl, &pl->d_ax[i], sizeof(AxisDev)));
+    PLAN_TRY(hipMemcpy(pl->d_ax[i], &pl->axes[idx[ns[i]]].dev, sizeof(AxisDev), hipMemcpyHostToDevice));
+  }
+  PLAN_TRY(dalloc(pl, &pl->d_phase, (size_t)nvox));
+  PLAN_TRY(hipMemcpy(pl->d_phase, phase, (size_t)nvox, hipMemcpyHostToDevice));
+  PLAN_TRY(dalloc(pl, &pl->spec, (size_t)6 * pl->nspec * 16));
+  PLAN_TRY(dalloc(pl, &pl->sig, (size_t)6 * nvox * 8));
+  PLAN_TRY(dalloc(pl, &pl->x, (size_t)6 * nvox * 8));
+  PLAN_TRY(dalloc(pl, &pl->r, (size_t)6 * nvox * 8));
+  PLAN_TRY(dalloc(pl, &pl->p, (size_t)6 * nvox * 8));
+  PLAN_TRY(dalloc(pl, &pl->ap, (size_t)6 * nvox * (pl->mixed ? 4 : 8)));
+  pl->max_tiles = max_tiles_any(n0, n1, n2, nvox);
+  PLAN_TRY(dalloc(pl, &pl->partial, (size_t)6 * pl->max_tiles * 8 + 64));
+  PLAN_TRY(dalloc(pl, &pl->cg, sizeof(CgState)));
+  PLAN_TRY(hipMemset(pl->cg, 0, sizeof(CgState)));
+  PLAN_TRY(dalloc(pl, &pl->d_rv, sizeof(RveDev)));
+  PLAN_TRY(hipHostMalloc((void**)&pl->h_stage, 4 * sizeof(RveDev), hipHostMallocDefault));
+  PLAN_TRY(hipHostMalloc((void**)&pl->h_cg, sizeof(CgState), hipHostMallocDefault));
+  for (int i = 0; i < 4; ++i) PLAN_TRY(hipEventCreateWithFlags(&pl->stage_ev[i], hipEventDisableTiming));
+  pl->stage_next = 0;
+#undef PLAN_TRY
+  *out = pl;
+  return FFTG_OK;
+}
+
+void fftg_plan_destroy(fftg_plan plan) { plan_free(plan); }
+
+static fftg_status eval_elastic_tangent(fftg_plan pl, fftg_history h);
+hipError_t fftg_add_const(double* f, long long nvox, const double* E, hipStream_t s);
+
+fftg_status fftg_history_create(fftg_plan pl, fftg_history* out) {
+  if (!pl || !out) return fail(FFTG_E_INVALID, "NULL argument");
+  *out = nullptr;
+  fftg_history h = new fftg_history_s();
+  h->plan = pl;
+  const long long nvox = pl->nvox;
+  const size_t ts = pl->mixed ? 4 : 8;
+  hipError_t e;
+  if ((e = hipMalloc((void**)&h->eps_fl, 6 * nvox * 8)) != hipSuccess ||
+      (e = hipMalloc((void**)&h->eps_p, 6 * nvox * 8)) != hipSuccess ||
+      (e = hipMalloc((void**)&h->epbar, nvox * 8)) != hipSuccess ||
+      (e = hipMalloc(&h->tang, 7 * nvox * ts)) != hipSuccess) {
+    hipFree(h->eps_fl);
+    hipFree(h->eps_p);
+    hipFree(h->epbar);
+    hipFree(h->tang);
+    delete h;
+    return fail(FFTG_E_NOMEM, std::string("history allocation: ") + hipGetErrorString(e));
+  }
+  HIP_TRY(hipMemsetAsync(h->eps_fl, 0, 6 * nvox * 8, pl->stream));
+  HIP_TRY(hipMemsetAsync(h->eps_p, 0, 6 * nvox * 8, pl->stream));
+  HIP_TRY(hipMemsetAsync(h->epbar, 0, nvox * 8, pl->stream));
+  for (int c = 0; c < 6; ++c) h->E[c] = 0.0;
+  h->inc = 0;
+  *out = h;
+  // elastic tangent of the virgin state: the return map at zero strain
+  const fftg_status st = eval_elastic_tangent(pl, h);
+  if (st != FFTG_OK) {
+    fftg_history_destroy(h);
+    *out = nullptr;
+  }
+  return st;
+}
+
+void fftg_history_destroy(fftg_history h) {
+  if (!h) return;
+  hipStreamSynchronize(h->plan->stream);
+  hipFree(h->eps_fl);
+  hipFree(h->eps_p);
+  hipFree(h->epbar);
+  hipFree(h->tang);
+  delete h;
+}
+
+// ------------------------------------------------------------- profiler
+// Brackets launches of one kernel kind with HIP events (process-wide).
+struct Profiler {
+  int kid = -1;
+  std::vector<hipEvent_t> pool;   // 2 per recorded launch
+  size_t used = 0;
+  double voxels = 0.0;
+  long long launches = 0;
+};
+static Profiler g_prof;
+
+static int prof_begin(int kid, hipStream_t s) {
+  if (g_prof.kid != kid) return -1;
+  if (g_prof.used + 2 > g_prof.pool.size()) {
+    for (int i = 0; i < 64; ++i) {
+      hipEvent_t e;
+      if (hipEventCreate(&e) != hipSuccess) return -1;
+      g_prof.pool.push_back(e);
+    }
+  }
+  const int idx = (int)g_prof.used;
+  g_prof.used += 2;
+  hipEventRecord(g_prof.pool[idx], s);
+  return idx;
+}
+
+static void prof_end(int idx, hipStream_t s, double voxels) {
+  if (idx < 0) return;
+  hipEventRecord(g_prof.pool[idx + 1], s);
+  g_prof.launches += 1;
+  g_prof.voxels += voxels;
+}
+
+fftg_status fftg_profiler_start(int kernel_id) {
+  if (kernel_id < 0 || kernel_id >= FFTG_KERNEL_COUNT) return fail(FFTG_E_INVALID, "bad kernel id");
+  g_prof.kid = kernel_id;
+  g_prof.used = 0;
+  g_prof.voxels = 0.0;
+  g_prof.launches = 0;
+  return FFTG_OK;
+}
+
+fftg_status fftg_profiler_stop(double* total_ms, long long* launches, double* voxels) {
+  double tot = 0.0;
+  for (size_t i = 0; i + 1 < g_prof.used; i += 2) {
+    HIP_TRY(hipEventSynchronize(g_prof.pool[i + 1]));
+    float ms = 0.f;
+    HIP_TRY(hipEventElapsedTime(&ms, g_prof.pool[i], g_prof.pool[i + 1]));
+    tot += ms;
+  }
+  if (total_ms) *total_ms = tot;
+  if (launches) *launches = g_prof.launches;
+  if (voxels) *voxels = g_prof.voxels;
+  g_prof.kid = -1;
+  g_prof.used = 0;
+  return FFTG_OK;
+}
+
+// ------------------------------------------------------ descriptor groups
+struct Group {
+  int mixed;
+  hipStream_t stream;
+  LaunchCfg cfg;
+  size_t lds_zf, lds_y, lds_x;
+  int total[P_NPASS];
+  std::vector<RveDev> h;         // host copies
+  RveDev* d;                     // device array
+  RveDev* h_pinned;              // staging ring (4 slots x count)
+  hipEvent_t ev[4];
+  int next;
+  CgState* h_cg;                 // pinned per-member CG states
+  CgState* d_cg;                 // device CG states, contiguous (one per member)
+  std::vector<fftg_plan> plans;
+  std::vector<fftg_history> hists;
+  bool own;                      // device arrays owned by the group
+  double active_vox;             // voxels of the members not skipped
+};
+
+static void fill_desc(RveDev& rv, fftg_plan pl, fftg_history h, const LaunchCfg& cfg) {
+  memset(&rv, 0, sizeof(rv));
+  rv.n0 = pl->n[0];
+  rv.n1 = pl->n[1];
+  rv.n2 = pl->n[2];
+  rv.H = pl->H;
+  rv.nvox = pl->nvox;
+  rv.nspec = pl->nspec;
+  for (int i = 0; i < 3; ++i) rv.ax[i] = pl->d_ax[i];
+  rv.buf[R_SIG] = pl->sig;
+  rv.buf[R_X] = pl->x;
+  rv.buf[R_R] = pl->r;
+  rv.buf[R_P] = pl->p;
+  rv.buf[R_AP] = pl->ap;
+  if (h) {
+    rv.buf[R_EPS_FL] = h->eps_fl;
+    rv.buf[R_EPS_P] = h->eps_p;
+    rv.buf[R_EPBAR] = h->epbar;
+    rv.tang = h->tang;
+    for (int c = 0; c < 6; ++c) rv.E[c] = h->E[c];
+  }
+  rv.spec = pl->spec;
+  rv.phase = pl->d_phase;
+  for (int i = 0; i < pl->n_phases; ++i) rv.mats[i] = pl->mats[i];
+  rv.n_phases = pl->n_phases;
+  rv.mixed = pl->mixed;
+  rv.cg = pl->cg;
+  rv.partial = pl->partial;
+  compute_tiles(cfg, rv.n0, rv.n1, rv.n2, rv.nvox, rv.tiles);
+}
+
+static void group_config(Group& g) {
+  int n0 = 1, n1 = 1, n2 = 1;
+  long long nv = 0;
+  for (auto* pl : g.plans) {
+    n0 = std::max(n0, pl->n[0]);
+    n1 = std::max(n1, pl->n[1]);
+    n2 = std::max(n2, pl->n[2]);
+    nv = std::max(nv, pl->nvox);
+  }
+  g.cfg = choose_cfg(n0, n1, n2, nv);
+  g.lds_zf = lds_z(0, g.cfg.rows_per_tile, n2);
+  g.lds_y = lds_y(0, g.cfg.lines_y, n1);
+  g.lds_x = lds_x(0, g.cfg.lines_x, n0);
+}
+
+static void group_totals(Group& g) {
+  for (int p = 0; p < P_NPASS; ++p) {
+    g.total[p] = 0;
+    for (auto& rv : g.h)
+      if (!rv.skip) g.total[p] += rv.tiles[p];
+  }
+  g.active_vox = 0.0;
+  for (auto& rv : g.h)
+    if (!rv.skip) g.active_vox += (double)rv.nvox;
+}
+
+#define PROF_LAUNCH(kid, expr)                       \
+  do {                                               \
+    const int pi_ = prof_begin((kid), g.stream);     \
+    HIP_TRY(expr);                                   \
+    prof_end(pi_, g.stream, g.active_vox);           \
+  } while (0)
+
+// Uploads the host descriptors (stream-ordered, through a pinned slot).
+static fftg_status group_upload(Group& g) {
+  const size_t n = g.h.size();
+  const int slot = g.next;
+  g.next = (g.next + 1) & 3;
+  HIP_TRY(hipEventSynchronize(g.ev[slot]));
+  RveDev* st = g.h_pinned + slot * n;
+  memcpy(st, g.h.data(), n * sizeof(RveDev));
+  HIP_TRY(hipMemcpyAsync(g.d, st, n * sizeof(RveDev), hipMemcpyHostToDevice, g.stream));
+  HIP_TRY(hipEventRecord(g.ev[slot], g.stream));
+  group_totals(g);
+  return FFTG_OK;
+}
+
+// Descriptors of members that are skipped are kept in the array but have
+// tiles == 0 for the kernels' tile search; tiles are restored on unskip.
+static void set_skip(Group& g, size_t i, bool skip) {
+  RveDev& rv = g.h[i];
+  rv.skip = skip ? 1 : 0;
+  if (skip) {
+    for (int p = 0; p < P_NPASS; ++p) rv.tiles[p] = 0;
+  } else {
+    compute_tiles(g.cfg, rv.n0, rv.n1, rv.n2, rv.nvox, rv.tiles);
+  }
+}
+
+// -------------------------------------------------------- apply sequences
+// G:(C:in) into the out mode; in_role / const dE input.
+static fftg_status enqueue_apply(Group& g, int mixed, int in_mode, int in_role, int tan_mode, int want_norm,
+                                 int out_mode, int out_role, double scale, int check_done) {
+  const int nr = (int)g.h.size();
+  PROF_LAUNCH(FFTG_KERNEL_ZFWD, launch_zfwd(mixed, g.d, nr, g.total[P_ZF], g.cfg, g.lds_zf, in_mode, in_role,
+                                            tan_mode, want_norm, check_done, g.stream));
+  PROF_LAUNCH(FFTG_KERNEL_Y_FWD,
+              launch_ypass(mixed, -1, g.d, nr, g.total[P_Y], g.cfg, g.lds_y, check_done, g.stream));
+  PROF_LAUNCH(FFTG_KERNEL_X_PROJ,
+              launch_xpass(mixed, g.d, nr, g.total[P_X], g.cfg, g.lds_x, scale, check_done, g.stream));
+  PROF_LAUNCH(FFTG_KERNEL_Y_INV,
+              launch_ypass(mixed, 1, g.d, nr, g.total[P_Y], g.cfg, g.lds_y, check_done, g.stream));
+  PROF_LAUNCH(FFTG_KERNEL_ZINV, launch_zinv(mixed, g.d, nr, g.total[P_ZI], g.cfg, g.lds_zf, out_mode, out_role,
+                                            check_done, g.stream));
+  return FFTG_OK;
+}
+
+static fftg_status enqueue_cg_iters(Group& g, int iters) {
+  const int nr = (int)g.h.size();
+  for (int i = 0; i < iters; ++i) {
+    fftg_status st = enqueue_apply(g, g.mixed, IN_ROLE, R_P, TAN_CURRENT, 0, OUT_CG, R_AP, 1.0, 1);
+    if (st != FFTG_OK) return st;
+    PROF_LAUNCH(FFTG_KERNEL_CG_XR, launch_cg_xr(g.mixed, g.d, nr, g.total[P_VEC], g.cfg, g.stream));
+    PROF_LAUNCH(FFTG_KERNEL_CG_P, launch_cg_p(g.d, nr, g.total[P_VEC], g.cfg, g.stream));
+  }
+  return FFTG_OK;
+}
+
+static fftg_status read_states(Group& g) {
+  const size_t n = g.h.size();
+  HIP_TRY(hipMemcpyAsync(g.h_cg, g.d_cg, n * sizeof(CgState), hipMemcpyDeviceToHost, g.stream));
+  HIP_TRY(hipStreamSynchronize(g.stream));
+  return FFTG_OK;
+}
+
+// Runs CG on the active members until every one is done.  Iterations are
+// enqueued in chunks between host checks of the device flags; after the
+// first chunk the next chunk is sized from the observed residual decay so
+// that few launches run past convergence (they exit at once when they do).
+static fftg_status run_cg(Group& g, int chunk_max) {
+  int chunk = chunk_max;
+  for (;;) {
+    fftg_status st = enqueue_cg_iters(g, chunk);
+    if (st != FFTG_OK) return st;
+    st = read_states(g);
+    if (st != FFTG_OK) return st;
+    bool all = true;
+    double need = 1.0;
+    for (size_t i = 0; i < g.h.size(); ++i) {
+      if (g.h[i].skip || g.h_cg[i].done) continue;
+      all = false;
+      const CgState& c = g.h_cg[i];
+      if (c.force >= 0) {
+        need = std::max(need, (double)(c.force - c.iters));
+      } else if (c.iters > 0 && c.rr > 0 && c.rr < c.bnorm2 && c.target2 > 0) {
+        const double rate = std::log(c.rr / c.bnorm2) / c.iters;  // per iteration, < 0
+        need = std::max(need, std::ceil(std::log(c.target2 / c.rr) / rate));
+      } else {
+        need = std::max(need, (double)chunk_max);
+      }
+    }
+    if (all) return FFTG_OK;
+    chunk = (int)std::min<double>(chunk_max, std::max(1.0, need));
+  }
+}
+
+static void set_E(Group& g, size_t i, const double E[6], const double dE[6]) {
+  for (int c = 0; c < 6; ++c) {
+    g.h[i].E[c] = E[c];
+    g.h[i].dE[c] = dE[c];
+  }
+}
+
+struct MemberRun {
+  int newton;
+  int first_full;
+  bool active;
+  bool converged;
+  int err;
+  double Enorm;
+  fftg_stats* stats;
+};
+
+// One increment of Algorithm 1 for every member of the group.
+static fftg_status group_increment(Group& g, const double* dE_tensor, const int* lockstep, int n_lockstep,
+                                   fftg_stats* stats) {
+  const size_t n = g.h.size();
+  const fftg_options& o = g.plans[0]->opt;
+  auto t0 = std::chrono::steady_clock::now();
+  std::vector<MemberRun> mr(n);
+  int nr = (int)n;
+  for (size_t i = 0; i < n; ++i) {
+    fftg_history h = g.hists[i];
+    double dEm[6];
+    tensor_to_mandel(dE_tensor + 6 * i, dEm);
+    for (int c = 0; c < 6; ++c) h->E[c] += dEm[c];
+    set_E(g, i, h->E, dEm);
+    set_skip(g, i, false);
+    double en = 0;
+    for (int c = 0; c < 6; ++c) en += h->E[c] * h->E[c];
+    en = std::sqrt(en) * std::sqrt((double)g.plans[i]->nvox);
+    mr[i] = {0, 0, true, false, FFTG_OK, en > 0 ? en : 1.0, stats ? stats + i : nullptr};
+    if (mr[i].stats) memset(mr[i].stats, 0, sizeof(fftg_stats));
+  }
+  fftg_status st = group_upload(g);
+  if (st != FFTG_OK) return st;
+  const double eta = g.mixed ? std::max(o.tol_cg, o.mixed_cg_floor) : o.tol_cg;
+  const double eta2 = eta * eta, floor2 = o.rhs_floor * o.rhs_floor;
+  const int max_newton = lockstep ? std::min(n_lockstep, FFTG_MAX_NEWTON) : o.max_newton;
+  const bool predictor = o.predictor == FFTG_PREDICTOR_TANGENT;
+
+  for (int it = 0;; ++it) {
+    bool any = false;
+    for (size_t i = 0; i < n; ++i) any = any || mr[i].active;
+    if (!any || it >= max_newton) break;
+    const bool pred_step = predictor && it == 0;
+    const int force = lockstep ? lockstep[it] : -1;
+    HIP_TRY(launch_cg_setup(g.d, nr, eta2, floor2, o.max_cg, force, g.stream));
+    if (pred_step) {
+      // G C_last dE: constant input, CURRENT tangent, FP64 or mixed apply
+      st = enqueue_apply(g, g.mixed, IN_CONST_DE, R_P, TAN_CURRENT, 1, OUT_RESIDUAL, R_R, -1.0, 0);
+    } else {
+      PROF_LAUNCH(FFTG_KERNEL_CONSTITUTIVE,
+                  launch_constitutive(g.mixed, g.d, nr, g.total[P_VEC], g.cfg, R_EPS_FL, 0, g.stream));
+      st = enqueue_apply(g, 0, IN_ROLE, R_SIG, TAN_IDENTITY, 1, OUT_RESIDUAL, R_R, -1.0, 0);
+    }
+    if (st != FFTG_OK) return st;
+    st = run_cg(g, o.cg_chunk);
+    if (st != FFTG_OK) return st;
+    if (g.mixed) {
+      // The FP32 product leaves rounding noise outside the compatible
+      // subspace in the CG iterate; project the update with the FP64 G so
+      // that eps* stays in E_N (the Newton residual cannot see that noise).
+      st = enqueue_apply(g, 0, IN_ROLE, R_X, TAN_IDENTITY, 0, OUT_PLAIN, R_X, 1.0, 0);
+      if (st != FFTG_OK) return st;
+    }
+    PROF_LAUNCH(FFTG_KERNEL_NEWTON, launch_newton_update(g.d, nr, g.total[P_VEC], g.cfg, g.stream));
+    st = read_states(g);
+    if (st != FFTG_OK) return st;
+    bool changed = false;
+    for (size_t i = 0; i < n; ++i) {
+      if (!mr[i].active) continue;
+      const CgState& c = g.h_cg[i];
+      const double res = std::sqrt(c.dnorm2) / mr[i].Enorm;
+      if (mr[i].stats && mr[i].newton < FFTG_MAX_NEWTON) {
+        mr[i].stats->cg_iters[mr[i].newton] = c.iters;
+        mr[i].stats->newton_res[mr[i].newton] = res;
+        mr[i].stats->total_cg += c.iters;
+      }
+      mr[i].newton += 1;
+      if (c.status == CG_BREAKDOWN) {
+        mr[i].err = FFTG_E_BREAKDOWN;
+        mr[i].active = false;
+      } else if (!lockstep && !pred_step && res <= o.tol_newton) {
+        mr[i].converged = true;
+        mr[i].active = false;
+      } else if (lockstep && mr[i].newton >= n_lockstep) {
+        mr[i].converged = true;
+        mr[i].active = false;
+      }
+      if (!mr[i].active) {
+        set_skip(g, i, true);
+        changed = true;
+      }
+    }
+    if (changed) {
+      st = group_upload(g);
+      if (st != FFTG_OK) return st;
+    }
+  }
+  // commit every member at its last iterate
+  for (size_t i = 0; i < n; ++i) set_skip(g, i, false);
+  st = group_upload(g);
+  if (st != FFTG_OK) return st;
+  PROF_LAUNCH(FFTG_KERNEL_CONSTITUTIVE,
+              launch_constitutive(g.mixed, g.d, nr, g.total[P_VEC], g.cfg, R_EPS_FL, 1, g.stream));
+  st = read_states(g);
+  if (st != FFTG_OK) return st;
+  const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  fftg_status ret = FFTG_OK;
+  for (size_t i = 0; i < n; ++i) {
+    g.hists[i]->inc += 1;
+    if (mr[i].stats) {
+      mr[i].stats->newton_iters = mr[i].newton;
+      mandel_to_tensor(g.h_cg[i].Sigma, mr[i].stats->Sigma);
+      mr[i].stats->converged = mr[i].converged ? 1 : 0;
+      mr[i].stats->seconds = secs;
+    }
+    if (ret == FFTG_OK) {
+      if (mr[i].err != FFTG_OK)
+        ret = (fftg_status)mr[i].err;
+      else if (!mr[i].converged)
+        ret = FFTG_E_NOT_CONVERGED;
+    }
+  }
+  if (ret == FFTG_E_BREAKDOWN) g_err = "CG breakdown (p.Ap <= 0)";
+  if (ret == FFTG_E_NOT_CONVERGED) g_err = "Newton iteration cap reached";
+  return ret;
+}
+
+// Single-member group view on a plan (uses the plan's own descriptor slot).
+static fftg_status single_group(fftg_plan pl, fftg_history h, Group& g) {
+  g.mixed = pl->mixed;
+  g.stream = pl->stream;
+  g.plans = {pl};
+  g.hists = {h};
+  group_config(g);
+  g.h.resize(1);
+  fill_desc(g.h[0], pl, h, g.cfg);
+  g.d = pl->d_rv;
+  g.h_pinned = pl->h_stage;
+  for (int i = 0; i < 4; ++i) g.ev[i] = pl->stage_ev[i];
+  g.next = pl->stage_next;
+  g.h_cg = pl->h_cg;
+  g.d_cg = pl->cg;
+  g.own = false;
+  return FFTG_OK;
+}
+
+static void single_group_done(fftg_plan pl, Group& g) { pl->stage_next = g.next; }
+
+static fftg_status eval_elastic_tangent(fftg_plan pl, fftg_history h) {
+  // constitutive at zero strain from the virgin history gives Ce everywhere
+  Group g;
+  single_group(pl, h, g);
+  fftg_status st = group_upload(g);
+  if (st == FFTG_OK) {
+    hipError_t e = launch_constitutive(g.mixed, g.d, 1, g.total[P_VEC], g.cfg, R_EPS_FL, 0, g.stream);
+    if (e != hipSuccess) st = fail(FFTG_E_HIP, hipGetErrorString(e));
+  }
+  single_group_done(pl, g);
+  return st;
+}
+
+fftg_status fftg_solve_increment(fftg_plan pl, fftg_history h, const double dE[6], const int* lockstep,
+                                 int n_lockstep, fftg_stats* stats) {
+  if (!pl || !h || !dE) return fail(FFTG_E_INVALID, "NULL argument");
+  if (h->plan != pl) return fail(FFTG_E_INVALID, "history belongs to another plan");
+  if (lockstep && (n_lockstep < 1 || n_lockstep > FFTG_MAX_NEWTON))
+    return fail(FFTG_E_INVALID, "n_lockstep out of range");
+  if (lockstep)
+    for (int i = 0; i < n_lockstep; ++i)
+      if (lockstep[i] < 0) return fail(FFTG_E_INVALID, "negative lockstep count");
+  Group g;
+  single_group(pl, h, g);
+  fftg_status st = group_increment(g, dE, lockstep, n_lockstep, stats);
+  single_group_done(pl, g);
+  return st;
+}
+
+fftg_status fftg_apply_GK(fftg_plan pl, fftg_history h, const double* d_in, void* d_out, fftg_tangent_mode mode) {
+  if (!pl || !d_in || !d_out) return fail(FFTG_E_INVALID, "NULL argument");
+  if (mode != FFTG_TANGENT_CURRENT && mode != FFTG_TANGENT_IDENTITY && mode != FFTG_TANGENT_ELASTIC)
+    return fail(FFTG_E_INVALID, "bad tangent mode");
+  if (mode == FFTG_TANGENT_CURRENT && !h) return fail(FFTG_E_INVALID, "CURRENT tangent needs a history");
+  if (h && h->plan != pl) return fail(FFTG_E_INVALID, "history belongs to another plan");
+  Group g;
+  single_group(pl, h, g);
+  g.h[0].buf[R_USER_IN] = (void*)d_in;
+  g.h[0].buf[R_USER_OUT] = d_out;
+  fftg_status st = group_upload(g);
+  if (st == FFTG_OK)
+    st = enqueue_apply(g, pl->mixed, IN_ROLE, R_USER_IN, (int)mode, 0, OUT_PLAIN, R_USER_OUT, 1.0, 0);
+  single_group_done(pl, g);
+  return st;
+}
+
+fftg_status fftg_eval_constitutive(fftg_plan pl, fftg_history h, const double* d_eps, double* d_sigma) {
+  if (!pl || !h || !d_eps || !d_sigma) return fail(FFTG_E_INVALID, "NULL argument");
+  if (h->plan != pl) return fail(FFTG_E_INVALID, "history belongs to another plan");
+  Group g;
+  single_group(pl, h, g);
+  g.h[0].buf[R_USER_IN] = (void*)d_eps;
+  fftg_status st = group_upload(g);
+  if (st == FFTG_OK) {
+    hipError_t e = launch_constitutive(g.mixed, g.d, 1, g.total[P_VEC], g.cfg, R_USER_IN, 0, g.stream);
+    if (e != hipSuccess) st = fail(FFTG_E_HIP, hipGetErrorString(e));
+  }
+  single_group_done(pl, g);
+  if (st != FFTG_OK) return st;
+  HIP_TRY(hipMemcpyAsync(d_sigma, pl->sig, 6 * pl->nvox * 8, hipMemcpyDeviceToDevice, pl->stream));
+  HIP_TRY(hipStreamSynchronize(pl->stream));
+  return FFTG_OK;
+}
+
+fftg_status fftg_get_field(fftg_plan pl, fftg_history h, int which, void* d_out) {
+  if (!pl || !h || !d_out) return fail(FFTG_E_INVALID, "NULL argument");
+  if (h->plan != pl) return fail(FFTG_E_INVALID, "history belongs to another plan");
+  const long long nv = pl->nvox;
+  switch (which) {
+    case FFTG_FIELD_FLUCT:
+      HIP_TRY(hipMemcpyAsync(d_out, h->eps_fl, 6 * nv * 8, hipMemcpyDeviceToDevice, pl->stream));
+      break;
+    case FFTG_FIELD_STRAIN: {
+      HIP_TRY(hipMemcpyAsync(d_out, h->eps_fl, 6 * nv * 8, hipMemcpyDeviceToDevice, pl->stream));
+      HIP_TRY(fftg_add_const((double*)d_out, nv, h->E, pl->stream));
+      break;
+    }
+    case FFTG_FIELD_STRESS:
+      HIP_TRY(hipMemcpyAsync(d_out, pl->sig, 6 * nv * 8, hipMemcpyDeviceToDevice, pl->stream));
+      break;
+    case FFTG_FIELD_EPS_P:
+      HIP_TRY(hipMemcpyAsync(d_out, h->eps_p, 6 * nv * 8, hipMemcpyDeviceToDevice, pl->stream));
+      break;
+    case FFTG_FIELD_EPBAR:
+      HIP_TRY(hipMemcpyAsync(d_out, h->epbar, nv * 8, hipMemcpyDeviceToDevice, pl->stream));
+      break;
+    case FFTG_FIELD_TANGENT:
+      HIP_TRY(hipMemcpyAsync(d_out, h->tang, 7 * nv * (pl->mixed ? 4 : 8), hipMemcpyDeviceToDevice, pl->stream));
+      break;
+    default:
+      return fail(FFTG_E_INVALID, "unknown field");
+  }
+  HIP_TRY(hipStreamSynchronize(pl->stream));
+  return FFTG_OK;
+}
+
+fftg_status fftg_set_field(fftg_plan pl, fftg_history h, int which, const void* d_in) {
+  if (!pl || !h || !d_in) return fail(FFTG_E_INVALID, "NULL argument");
+  if (h->plan != pl) return fail(FFTG_E_INVALID, "history belongs to another plan");
+  const long long nv = pl->nvox;
+  switch (which) {
+    case FFTG_FIELD_FLUCT:
+      HIP_TRY(hipMemcpyAsync(h->eps_fl, d_in, 6 * nv * 8, hipMemcpyDeviceToDevice, pl->stream));
+      break;
+    case FFTG_FIELD_EPS_P:
+      HIP_TRY(hipMemcpyAsync(h->eps_p, d_in, 6 * nv * 8, hipMemcpyDeviceToDevice, pl->stream));
+      break;
+    case FFTG_FIELD_EPBAR:
+      HIP_TRY(hipMemcpyAsync(h->epbar, d_in, nv * 8, hipMemcpyDeviceToDevice, pl->stream));
+      break;
+    default:
+      return fail(FFTG_E_INVALID, "field not settable");
+  }
+  HIP_TRY(hipStreamSynchronize(pl->stream));
+  return FFTG_OK;
+}
+
+fftg_status fftg_history_get_E(fftg_history h, double E[6], int* increments) {
+  if (!h || !E) return fail(FFTG_E_INVALID, "NULL argument");
+  mandel_to_tensor(h->E, E);
+  if (increments) *increments = h->inc;
+  return FFTG_OK;
+}
+
+// checkpoint layout: header {magic, n0, n1, n2, mixed, inc, E[6]} then
+// eps_fl (6 nvox f64), eps_p (6 nvox f64), epbar (nvox f64), tangent (7 nvox)
+struct CkptHeader {
+  uint64_t magic;
+  int32_t n[3];
+  int32_t mixed;
+  int32_t inc;
+  int32_t pad;
+  double E[6];
+};
+static const uint64_t kCkptMagic = 0x31475446'46544731ULL;
+
+fftg_status fftg_history_save(fftg_plan pl, fftg_history h, void* buf, size_t* bytes) {
+  if (!pl || !h || !bytes) return fail(FFTG_E_INVALID, "NULL argument");
+  if (h->plan != pl) return fail(FFTG_E_INVALID, "history belongs to another plan");
+  const long long nv = pl->nvox;
+  const size_t ts = pl->mixed ? 4 : 8;
+  const size_t need = sizeof(CkptHeader) + (size_t)nv * (13 * 8 + 7 * ts);
+  if (!buf) {
+    *bytes = need;
+    return FFTG_OK;
+  }
+  if (*bytes < need) return fail(FFTG_E_INVALID, "checkpoint buffer too small");
+  CkptHeader hd;
+  memset(&hd, 0, sizeof(hd));
+  hd.magic = kCkptMagic;
+  for (int i = 0; i < 3; ++i) hd.n[i] = pl->n[i];
+  hd.mixed = pl->mixed;
+  hd.inc = h->inc;
+  for (int c = 0; c < 6; ++c) hd.E[c] = h->E[c];
+  char* p = (char*)buf;
+  memcpy(p, &hd, sizeof(hd));
+  p += sizeof(hd);
+  HIP_TRY(hipStreamSynchronize(pl->stream));
+  HIP_TRY(hipMemcpy(p, h->eps_fl, 6 * nv * 8, hipMemcpyDeviceToHost));
+  p += 6 * nv * 8;
+  HIP_TRY(hipMemcpy(p, h->eps_p, 6 * nv * 8, hipMemcpyDeviceToHost));
+  p += 6 * nv * 8;
+  HIP_TRY(hipMemcpy(p, h->epbar, nv * 8, hipMemcpyDeviceToHost));
+  p += nv * 8;
+  HIP_TRY(hipMemcpy(p, h->tang, 7 * nv * ts, hipMemcpyDeviceToHost));
+  *bytes = need;
+  return FFTG_OK;
+}
+
+fftg_status fftg_history_restore(fftg_plan pl, fftg_history h, const void* buf, size_t bytes) {
+  if (!pl || !h || !buf) return fail(FFTG_E_INVALID, "NULL argument");
+  if (h->plan != pl) return fail(FFTG_E_INVALID, "history belongs to another plan");
+  const long long nv = pl->nvox;
+  const size_t ts = pl->mixed ? 4 : 8;
+  const size_t need = sizeof(CkptHeader) + (size_t)nv * (13 * 8 + 7 * ts);
+  if (bytes < need) return fail(FFTG_E_INVALID, "checkpoint too short");
+  CkptHeader hd;
+  memcpy(&hd, buf, sizeof(hd));
+  if (hd.magic != kCkptMagic || hd.n[0] != pl->n[0] || hd.n[1] != pl->n[1] || hd.n[2] != pl->n[2] ||
+      hd.mixed != pl->mixed)
+    return fail(FFTG_E_INVALID, "checkpoint does not match this plan");
+  const char* p = (const char*)buf + sizeof(hd);
+  HIP_TRY(hipStreamSynchronize(pl->stream));
+  HIP_TRY(hipMemcpy(h->eps_fl, p, 6 * nv * 8, hipMemcpyHostToDevice));
+  p += 6 * nv * 8;
+  HIP_TRY(hipMemcpy(h->eps_p, p, 6 * nv * 8, hipMemcpyHostToDevice));
+  p += 6 * nv * 8;
+  HIP_TRY(hipMemcpy(h->epbar, p, nv * 8, hipMemcpyHostToDevice));
+  p += nv * 8;
+  HIP_TRY(hipMemcpy(h->tang, p, 7 * nv * ts, hipMemcpyHostToDevice));
+  h->inc = hd.inc;
+  for (int c = 0; c < 6; ++c) h->E[c] = hd.E[c];
+  return FFTG_OK;
+}
+
+// ------------------------------------------------------------------ batch
+struct fftg_batch_s {
+  Group g;
+};
+
+fftg_status fftg_batch_create(fftg_batch* out, int count, const fftg_plan* plans, const fftg_history* hists) {
+  if (!out || count < 1 || !plans || !hists) return fail(FFTG_E_INVALID, "bad batch arguments");
+  *out = nullptr;
+  for (int i = 0; i < count; ++i) {
+    if (!plans[i] || !hists[i] || hists[i]->plan != plans[i]) return fail(FFTG_E_INVALID, "bad batch member");
+    if (plans[i]->mixed != plans[0]->mixed) return fail(FFTG_E_INVALID, "batch members must share precision");
+    for (int j = 0; j < i; ++j)
+      if (plans[j] == plans[i]) return fail(FFTG_E_INVALID, "a plan may appear once per batch");
+  }
+  fftg_batch b = new fftg_batch_s();
+  Group& g = b->g;
+  g.mixed = plans[0]->mixed;
+  g.stream = plans[0]->stream;
+  g.plans.assign(plans, plans + count);
+  g.hists.assign(hists, hists + count);
+  group_config(g);
+  g.h.resize(count);
+  for (int i = 0; i < count; ++i) fill_desc(g.h[i], plans[i], hists[i], g.cfg);
+  g.own = true;
+  g.next = 0;
+  g.d = nullptr;
+  g.h_pinned = nullptr;
+  g.h_cg = nullptr;
+  g.d_cg = nullptr;
+  memset(g.ev, 0, sizeof(g.ev));
+  hipError_t e = hipMalloc((void**)&g.d, count * sizeof(RveDev));
+  if (e == hipSuccess) e = hipMalloc((void**)&g.d_cg, count * sizeof(CgState));
+  if (e == hipSuccess) e = hipMemset(g.d_cg, 0, count * sizeof(CgState));
+  for (int i = 0; i < count && e == hipSuccess; ++i) g.h[i].cg = g.d_cg + i;
+  if (e == hipSuccess) e = hipHostMalloc((void**)&g.h_pinned, 4 * count * sizeof(RveDev), hipHostMallocDefault);
+  if (e == hipSuccess) e = hipHostMalloc((void**)&g.h_cg, count * sizeof(CgState), hipHostMallocDefault);
+  for (int i = 0; i < 4 && e == hipSuccess; ++i) e = hipEventCreateWithFlags(&g.ev[i], hipEventDisableTiming);
+  if (e != hipSuccess) {
+    fftg_batch_destroy(b);
+    return fail(FFTG_E_NOMEM, std::string("batch allocation: ") + hipGetErrorString(e));
+  }
+  *out = b;
+  return FFTG_OK;
+}
+
+void fftg_batch_destroy(fftg_batch b) {
+  if (!b) return;
+  Group& g = b->g;
+  hipStreamSynchronize(g.stream);
+  if (g.d) hipFree(g.d);
+  if (g.d_cg) hipFree(g.d_cg);
+  if (g.h_pinned) hipHostFree(g.h_pinned);
+  if (g.h_cg) hipHostFree(g.h_cg);
+  for (int i = 0; i < 4; ++i)
+    if (g.ev[i]) hipEventDestroy(g.ev[i]);
+  delete b;
+}
+
+fftg_status fftg_batch_solve_increment(fftg_batch b, const double* dE, fftg_stats* stats) {
+  if (!b || !dE) return fail(FFTG_E_INVALID, "NULL argument");
+  return group_increment(b->g, dE, nullptr, 0, stats);
+}
+
+const char* fftg_last_error(void) { return g_err.c_str(); }

@@ -1,0 +1,140 @@
+"""GPU parity of the matrix-free product G:(C:p) against the FP64 oracle.
+
+The library is called through its C ABI (ctypes binding); the oracle applies
+G with numpy FFTs and the explicit four-index G^ of Appendix A.
+"""
+import numpy as np
+import pytest
+
+import synth
+from oracle import j2
+from oracle.projection import apply_G
+from tests.gpu_util import m2t, rel_err, t2m, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+SHAPES = [(3, 3, 3), (1, 5, 7), (7, 5, 1), (3, 5, 7), (5, 7, 9), (11, 11, 11), (13, 17, 11),
+          (15, 15, 15), (21, 25, 27), (31, 31, 31), (63, 31, 15), (19, 23, 29), (61, 9, 5)]
+
+
+def _plan(shape, phase=None, mats=None, precision=0):
+    from paper_1601_05970_amd import fftg
+    if phase is None:
+        phase = synth.bernoulli(shape, 0.4, 1)
+    opt = fftg.fftg_options_default()
+    opt.precision = precision
+    p = fftg.Plan(phase, mats or [synth.SOFT, synth.HARD], opt)
+    return p
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+def test_projection_matches_oracle(shape):
+    from paper_1601_05970_amd import fftg
+    print("apply IDENTITY", shape, flush=True)
+    pl = _plan(shape)
+    tau = synth.random_sym_tensor_field(shape, 3)
+    d_in = to_dev(t2m(tau))
+    d_out = pl.field()
+    pl.apply_GK(d_in, d_out, fftg.FFTG_TANGENT_IDENTITY)
+    got = to_host(d_out)
+    ref = t2m(apply_G(tau))
+    assert rel_err(got, ref) < 1e-12
+
+
+@pytest.mark.parametrize("shape", [(5, 7, 9), (15, 15, 15), (31, 31, 31)])
+def test_elastic_tangent_product_matches_oracle(shape):
+    from paper_1601_05970_amd import fftg
+    print("apply ELASTIC", shape, flush=True)
+    ph = synth.bernoulli(shape, 0.5, 2)
+    mats = [(0.833, 0.386, 0.003, 0.004, 1.0), (2.0, 1.3, 0.006, 0.008, 1.0)]
+    pl = _plan(shape, ph, mats)
+    p = synth.random_sym_tensor_field(shape, 4)
+    d_out = pl.field()
+    pl.apply_GK(to_dev(t2m(p)), d_out, fftg.FFTG_TANGENT_ELASTIC)
+    K, G, _, _, _ = j2.material_fields(ph, mats)
+    ref = t2m(apply_G(j2.ddot42(j2.elastic_stiffness(K, G), p)))
+    assert rel_err(to_host(d_out), ref) < 1e-12
+
+
+def _plastic_state(shape, seed):
+    rng = np.random.default_rng(seed)
+    eps = synth.random_sym_tensor_field(shape, seed, 4e-3)
+    ep = synth.random_sym_tensor_field(shape, seed + 1, 1e-3)
+    tr = np.einsum("ii...->...", ep)
+    for i in range(3):
+        ep[i, i] -= tr / 3.0
+    eb = rng.uniform(0.0, 3e-3, shape)
+    return eps, ep, eb
+
+
+@pytest.mark.parametrize("shape", [(5, 7, 9), (15, 15, 15), (31, 31, 31)])
+def test_consistent_tangent_product_matches_oracle(shape):
+    from paper_1601_05970_amd import fftg
+    print("apply CURRENT", shape, flush=True)
+    ph = synth.bernoulli(shape, 0.4, 5)
+    mats = [synth.SOFT, synth.HARD]
+    pl = _plan(shape, ph, mats)
+    h = fftg.History(pl)
+    eps, ep, eb = _plastic_state(shape, 7)
+    h.set_field(fftg.FFTG_FIELD_EPS_P, to_dev(t2m(ep)))
+    h.set_field(fftg.FFTG_FIELD_EPBAR, to_dev(eb[None]))
+    sig = pl.field()
+    h.eval_constitutive(to_dev(t2m(eps)), sig)
+    K, G, s0, H, _ = j2.material_fields(ph, mats)
+    s_ref, C_ref, _, _, plastic = j2.return_map(eps, ep, eb, K, G, s0, H)
+    assert 0.05 < plastic.mean() < 0.98
+    assert rel_err(to_host(sig), t2m(s_ref)) < 1e-13
+    p = synth.random_sym_tensor_field(shape, 8)
+    d_out = pl.field()
+    pl.apply_GK(to_dev(t2m(p)), d_out, fftg.FFTG_TANGENT_CURRENT, h)
+    ref = t2m(apply_G(j2.ddot42(C_ref, p)))
+    assert rel_err(to_host(d_out), ref) < 1e-12
+
+
+@pytest.mark.parametrize("shape", [(15, 15, 15), (31, 31, 31), (63, 63, 63)])
+def test_mixed_precision_product_matches_oracle(shape):
+    from paper_1601_05970_amd import fftg
+    import torch
+    print("apply MIXED", shape, flush=True)
+    ph = synth.bernoulli(shape, 0.5, 2)
+    mats = [synth.SOFT, synth.HARD]
+    pl = _plan(shape, ph, mats, precision=fftg.FFTG_MIXED)
+    p = synth.random_sym_tensor_field(shape, 4)
+    d_out = pl.field(dtype=torch.float32)
+    pl.apply_GK(to_dev(t2m(p)), d_out, fftg.FFTG_TANGENT_ELASTIC)
+    K, G, _, _, _ = j2.material_fields(ph, mats)
+    ref = t2m(apply_G(j2.ddot42(j2.elastic_stiffness(K, G), p)))
+    assert rel_err(to_host(d_out), ref) < 2e-6
+
+
+def _compatible(shape, seed):
+    """Symmetric gradient of a random periodic displacement (L_i = n_i)."""
+    rng = np.random.default_rng(seed)
+    k = [np.fft.fftfreq(n) * n for n in shape]
+    out = np.zeros((3, 3) + tuple(shape))
+    uh = [np.fft.fftn(rng.standard_normal(shape)) for _ in range(3)]
+    for i in range(3):
+        for j in range(i, 3):
+            gi = (2j * np.pi * k[i] / shape[i]).reshape([-1 if a == i else 1 for a in range(3)])
+            gj = (2j * np.pi * k[j] / shape[j]).reshape([-1 if a == j else 1 for a in range(3)])
+            e = np.fft.ifftn(0.5 * (gi * uh[j] + gj * uh[i])).real
+            out[i, j] = out[j, i] = e
+    return out
+
+
+@pytest.mark.parametrize("shape", [(127, 127, 127), (255, 255, 255)])
+def test_full_size_projection_keeps_compatible_fields(shape):
+    """At the large grid sizes the oracle is replaced by a property that
+    holds at any size: G leaves a compatible field unchanged, in FP64 and
+    in the FP32 apply."""
+    from paper_1601_05970_amd import fftg
+    import torch
+    print("apply compatible", shape, flush=True)
+    e = t2m(_compatible(shape, 11))
+    for prec, tol, dt in ((fftg.FFTG_FP64, 1e-11, torch.float64), (fftg.FFTG_MIXED, 3e-6, torch.float32)):
+        pl = _plan(shape, np.zeros(shape, np.uint8), precision=prec)
+        d_out = pl.field(dtype=dt)
+        pl.apply_GK(to_dev(e), d_out, fftg.FFTG_TANGENT_IDENTITY)
+        assert rel_err(to_host(d_out), e) < tol
+        del d_out, pl
+        torch.cuda.empty_cache()

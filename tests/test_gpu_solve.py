@@ -1,0 +1,229 @@
+"""GPU parity of the full Newton--CG increment (Algorithm 1) against the FP64
+oracle, closed forms and invariants; checkpoint, batch and error paths."""
+import math
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import j2, solver as S
+from tests.gpu_util import m2t, rel_err, t2m, tensor6, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+
+def _opts(w=None, precision=0, predictor=0, tol_newton=None, tol_cg=None):
+    from paper_1601_05970_amd import fftg
+    o = fftg.fftg_options_default()
+    o.precision = precision
+    o.predictor = predictor
+    if w is not None:
+        o.tol_newton, o.tol_cg = w.tol_newton, w.tol_cg
+    if tol_newton is not None:
+        o.tol_newton = tol_newton
+    if tol_cg is not None:
+        o.tol_cg = tol_cg
+    return o
+
+
+def _run_gpu(w, opts, lockstep=None, n_inc=None):
+    from paper_1601_05970_amd import fftg
+    pl = fftg.Plan(w.phase, w.materials, opts)
+    h = fftg.History(pl)
+    stats = []
+    for n in range(1, (n_inc or w.n_inc) + 1):
+        ls = None if lockstep is None else lockstep[n - 1]
+        stats.append(h.solve_increment(tensor6(w.dE(n)), ls))
+    return pl, h, stats
+
+
+def _fields(h):
+    from paper_1601_05970_amd import fftg
+    return {
+        "strain": to_host(h.get_field(fftg.FFTG_FIELD_STRAIN)),
+        "stress": to_host(h.get_field(fftg.FFTG_FIELD_STRESS)),
+        "eps_p": to_host(h.get_field(fftg.FFTG_FIELD_EPS_P)),
+        "epbar": to_host(h.get_field(fftg.FFTG_FIELD_EPBAR))[0],
+    }
+
+
+def _compare(h, s, tol, stats=None, st_ref=None):
+    f = _fields(h)
+    assert rel_err(f["strain"], t2m(s.strain())) < tol
+    assert rel_err(f["stress"], t2m(s.sigma)) < tol
+    if np.max(s.epbar) > 0:
+        assert rel_err(f["epbar"], s.epbar) < tol
+        assert rel_err(f["eps_p"], t2m(s.eps_p)) < tol
+    else:
+        assert np.max(np.abs(f["epbar"])) == 0.0
+    if stats is not None:
+        Sg = np.array(stats["Sigma"])
+        Sr = np.array(tensor6(st_ref.Sigma))
+        assert np.max(np.abs(Sg - Sr)) <= tol * np.max(np.abs(Sr))
+
+
+def test_homogeneous_returns_applied_strain():
+    print("solve homogeneous", flush=True)
+    ph = synth.bernoulli((9, 7, 5), 0.5, 11)
+    w = synth.Workload("homog", ph, [synth.SOFT, synth.SOFT], synth.pure_shear_eq(0.02), 5)
+    pl, h, stats = _run_gpu(w, _opts(w))
+    from paper_1601_05970_amd import fftg
+    assert np.max(np.abs(to_host(h.get_field(fftg.FFTG_FIELD_FLUCT)))) == 0.0
+    ep, eb = np.zeros((3, 3)), 0.0
+    for n, st in enumerate(stats, start=1):
+        sig, _, ep, eb, _ = j2.point_response(w.E_at(n), ep, eb, synth.SOFT)
+        assert np.max(np.abs(np.array(st["Sigma"]) - np.array(tensor6(sig)))) <= 1e-15
+        assert st["cg_iters"] == [0, 0]
+
+
+def test_laminate_matches_closed_form_and_oracle():
+    print("solve laminate 11^3", flush=True)
+    from tests.test_oracle_solver import laminate_closed_form
+    w = synth.laminate_11()
+    s, st_ref = S.run_workload(w)
+    pl, h, stats = _run_gpu(w, _opts(w))
+    for n, st in enumerate(stats, start=1):
+        tau, es, eh = laminate_closed_form(w.E_at(n)[0, 1])
+        assert abs(st["Sigma"][5] - tau) <= 1e-10 * tau
+        assert st["cg_iters"] == st_ref[n - 1].cg_iters
+    eps = m2t(_fields(h)["strain"])
+    soft = w.phase == 0
+    assert np.max(np.abs(eps[0, 1][soft] - es)) <= 1e-10 * es
+    assert np.max(np.abs(eps[0, 1][~soft] - eh)) <= 1e-10 * eh
+    _compare(h, s, 1e-10, stats[-1], st_ref[-1])
+
+
+@pytest.mark.parametrize("shape,seed", [((9, 7, 5), 21), ((15, 15, 15), 3), ((11, 13, 7), 5)])
+def test_lockstep_parity_with_oracle(shape, seed):
+    print("solve lockstep", shape, flush=True)
+    w = synth.small_random(shape, 0.35, seed, E_eq=0.01, n_inc=4)
+    s = S.Solver(w.phase, w.materials, w.tol_newton, w.tol_cg)
+    from paper_1601_05970_amd import fftg
+    pl = fftg.Plan(w.phase, w.materials, _opts(w))
+    h = fftg.History(pl)
+    for n in range(1, w.n_inc + 1):
+        st_ref = s.solve_increment(w.E_at(n))
+        st = h.solve_increment(tensor6(w.dE(n)), st_ref.cg_iters)
+        assert st["cg_iters"] == st_ref.cg_iters
+        for a, b in zip(st["newton_res"], st_ref.newton_res):
+            assert abs(a - b) <= 1e-8 * max(b, 1e-12) + 1e-14
+        _compare(h, s, 1e-10, st, st_ref)
+
+
+def test_natural_stopping_agrees_with_oracle():
+    print("solve natural", flush=True)
+    w = synth.small_random((15, 15, 15), 0.35, 9, E_eq=0.01, n_inc=4)
+    s, st_ref = S.run_workload(w)
+    pl, h, stats = _run_gpu(w, _opts(w))
+    for a, b in zip(stats, st_ref):
+        assert a["newton_iters"] == b.newton_iters
+        assert all(abs(x - y) <= 1 for x, y in zip(a["cg_iters"], b.cg_iters))
+    # both stop inside the same tolerances; agreement is at that level
+    _compare(h, s, 1e-6, stats[-1], st_ref[-1])
+
+
+def test_literal_algorithm_without_predictor():
+    print("solve predictor NONE", flush=True)
+    ph = synth.laminate(11, 4)
+    elastic = (0.833, 0.386, 1e30, 0.0, 1.0)
+    plastic = (0.833, 0.386, 0.01 * 0.386, 0.05 * 0.386, 1.0)
+    w = synth.Workload("lam_lit", ph, [elastic, plastic], synth.shear_xy(0.05), 1, 1e-6, 1e-12)
+    s = S.Solver(ph, w.materials, 1e-6, 1e-12, predictor="none")
+    st_ref = s.solve_increment(w.E_at(1))
+    from paper_1601_05970_amd import fftg
+    pl, h, stats = _run_gpu(w, _opts(w, predictor=fftg.FFTG_PREDICTOR_NONE))
+    assert stats[0]["newton_iters"] == st_ref.newton_iters
+    _compare(h, s, 1e-10, stats[0], st_ref)
+
+
+def test_mixed_precision_agrees_with_fp64_oracle():
+    print("solve mixed", flush=True)
+    from paper_1601_05970_amd import fftg
+    w = synth.small_random((15, 15, 15), 0.35, 9, E_eq=0.01, n_inc=4)
+    s = S.Solver(w.phase, w.materials, 1e-10, 1e-10)
+    st_ref = [s.solve_increment(w.E_at(n)) for n in range(1, w.n_inc + 1)]
+    pl, h, stats = _run_gpu(w, _opts(w, precision=fftg.FFTG_MIXED, tol_newton=1e-10, tol_cg=1e-10))
+    f = _fields(h)
+    assert rel_err(np.array(stats[-1]["Sigma"]), np.array(tensor6(st_ref[-1].Sigma))) < 1e-6
+    assert rel_err(f["strain"], t2m(s.strain())) < 1e-6
+
+
+def test_checkpoint_restore_is_bitwise():
+    print("checkpoint", flush=True)
+    from paper_1601_05970_amd import fftg
+    w = synth.small_random((9, 11, 7), 0.4, 2, E_eq=0.01, n_inc=4)
+    pl = fftg.Plan(w.phase, w.materials, _opts(w))
+    h = fftg.History(pl)
+    for n in (1, 2):
+        h.solve_increment(tensor6(w.dE(n)))
+    blob = h.save()
+    for n in (3, 4):
+        h.solve_increment(tensor6(w.dE(n)))
+    a = _fields(h)
+    h2 = fftg.History(pl)
+    h2.restore(blob)
+    assert h2.get_E()[1] == 2
+    for n in (3, 4):
+        h2.solve_increment(tensor6(w.dE(n)))
+    b = _fields(h2)
+    for k in a:
+        assert np.array_equal(a[k], b[k]), k
+
+
+def test_batch_equals_alone():
+    print("batch vs alone", flush=True)
+    from paper_1601_05970_amd import fftg
+    ws = [synth.small_random(sh, 0.35, i, E_eq=0.01, n_inc=3)
+          for i, sh in enumerate([(9, 9, 9), (15, 15, 15), (11, 13, 7)])]
+    alone = []
+    for w in ws:
+        _, h, st = _run_gpu(w, _opts(w))
+        alone.append((_fields(h), st))
+    plans = [fftg.Plan(w.phase, w.materials, _opts(w)) for w in ws]
+    hists = [fftg.History(p) for p in plans]
+    b = fftg.Batch(plans, hists)
+    for n in range(1, 4):
+        dE = np.array([tensor6(w.dE(n)) for w in ws])
+        st = b.solve_increment(dE)
+        for i in range(3):
+            assert st[i]["cg_iters"] == alone[i][1][n - 1]["cg_iters"]
+    for i, h in enumerate(hists):
+        f = _fields(h)
+        for k in f:
+            assert rel_err(f[k], alone[i][0][k]) < 1e-12, k
+
+
+def test_error_paths():
+    print("errors", flush=True)
+    from paper_1601_05970_amd import fftg
+    with pytest.raises(fftg.FFTGError) as e:
+        fftg.Plan(np.zeros((4, 5, 5), np.uint8), [synth.SOFT])
+    assert e.value.status == fftg.FFTG_E_INVALID
+    with pytest.raises(fftg.FFTGError) as e:
+        fftg.Plan(np.zeros((69, 5, 5), np.uint8), [synth.SOFT])
+    assert e.value.status == fftg.FFTG_E_UNSUPPORTED
+    with pytest.raises(fftg.FFTGError) as e:
+        fftg.Plan(np.zeros((5, 5, 5), np.uint8), [(0.833, 0.386, 0.003, 0.004, 0.5)])
+    assert e.value.status == fftg.FFTG_E_UNSUPPORTED
+    with pytest.raises(fftg.FFTGError) as e:
+        fftg.Plan(np.full((5, 5, 5), 2, np.uint8), [synth.SOFT, synth.HARD])
+    assert e.value.status == fftg.FFTG_E_INVALID
+    pl = fftg.Plan(np.zeros((5, 5, 5), np.uint8), [synth.SOFT])
+    h = fftg.History(pl)
+    with pytest.raises(fftg.FFTGError) as e:
+        h.solve_increment([0, 0, 0, 0, 0, 1e-3], lockstep=[-1])
+    assert e.value.status == fftg.FFTG_E_INVALID
+
+
+def test_newton_cap_reports_not_converged():
+    print("newton cap", flush=True)
+    from paper_1601_05970_amd import fftg
+    w = synth.small_random((9, 9, 9), 0.4, 1, E_eq=0.01, n_inc=4)   # increment 1 stays elastic
+    o = _opts(w)
+    o.max_newton = 2
+    pl = fftg.Plan(w.phase, w.materials, o)
+    h = fftg.History(pl)
+    h.solve_increment(tensor6(w.dE(1)))
+    st = h.solve_increment(tensor6(w.dE(2)), raise_on_error=False)
+    assert st["status"] == fftg.FFTG_E_NOT_CONVERGED
+    assert st["newton_iters"] == 2 and not st["converged"]

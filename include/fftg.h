@@ -190,13 +190,13 @@ fftg_status fftg_batch_solve_increment(fftg_batch batch, const double* dE, fftg_
  * covered (sum over the RVEs each launch processed); any output may be
  * NULL.  Not thread-safe with concurrent solves on other threads. */
 typedef enum {
-  FFTG_KERNEL_ZFWD = 0,        /* tangent contraction + real-to-complex DFT along z */
+  FFTG_KERNEL_ZFWD = 0,        /* p update, tangent contraction, real-to-complex DFT along z */
   FFTG_KERNEL_Y_FWD = 1,       /* DFT along y */
   FFTG_KERNEL_X_PROJ = 2,      /* DFT along x, G^(k) projection, inverse DFT along x */
   FFTG_KERNEL_Y_INV = 3,       /* inverse DFT along y */
   FFTG_KERNEL_ZINV = 4,        /* complex-to-real inverse DFT along z + CG dot */
   FFTG_KERNEL_CG_XR = 5,       /* x += alpha p, r -= alpha Ap, r.r */
-  FFTG_KERNEL_CG_P = 6,        /* p = r + beta p */
+  FFTG_KERNEL_CG_P = 6,        /* unused: p = r + beta p runs inside ZFWD */
   FFTG_KERNEL_CONSTITUTIVE = 7,/* J2 return map + consistent tangent */
   FFTG_KERNEL_NEWTON = 8,      /* eps* += d eps, ||d eps|| */
   FFTG_KERNEL_COUNT = 9

@@ -134,7 +134,9 @@ template <>
 __device__ __forceinline__ const cx<float>* axis_tw<float>(const AxisDev& P) { return P.tw32; }
 
 // Runs the Stockham chain of P on a (result ends in a; buffers are swapped).
-template <int DIR, class T>
+// BIG = 0 compiles only the radix 2, 3, 4, 5, 7, 9 codelets (lower register
+// use); BIG = 1 adds 11, 13, 17.
+template <int DIR, class T, int BIG>
 __device__ void run_chain(cx<T>*& a, cx<T>*& b, int ld, int nl, const AxisDev& P) {
   const cx<T>* tw = axis_tw<T>(P);
   int Ns = 1;
@@ -147,9 +149,9 @@ __device__ void run_chain(cx<T>*& a, cx<T>*& b, int ld, int nl, const AxisDev& P
       case 5: stockham_stage<5, DIR, T>(a, b, ld, nl, P.M, Ns, tw); break;
       case 7: stockham_stage<7, DIR, T>(a, b, ld, nl, P.M, Ns, tw); break;
       case 9: stockham_stage<9, DIR, T>(a, b, ld, nl, P.M, Ns, tw); break;
-      case 11: stockham_stage<11, DIR, T>(a, b, ld, nl, P.M, Ns, tw); break;
-      case 13: stockham_stage<13, DIR, T>(a, b, ld, nl, P.M, Ns, tw); break;
-      case 17: stockham_stage<17, DIR, T>(a, b, ld, nl, P.M, Ns, tw); break;
+      case 11: if (BIG) stockham_stage<11, DIR, T>(a, b, ld, nl, P.M, Ns, tw); break;
+      case 13: if (BIG) stockham_stage<13, DIR, T>(a, b, ld, nl, P.M, Ns, tw); break;
+      case 17: if (BIG) stockham_stage<17, DIR, T>(a, b, ld, nl, P.M, Ns, tw); break;
       default: break;  // rejected at plan creation
     }
     __syncthreads();
@@ -175,12 +177,12 @@ __device__ __forceinline__ const cx<float>* rader_bhat<float>(const AxisDev& P, 
 // (unnormalised).  line and scratch each hold nl lines of stride ld >= N;
 // dc holds nl scratch slots (Rader only).  Returns the buffer holding the
 // result (line or scratch).  Must be called by the whole workgroup.
-template <int DIR, class T>
+template <int DIR, class T, int BIG>
 __device__ cx<T>* line_fft(cx<T>* line, cx<T>* scratch, int ld, int nl, const AxisDev& P, cx<T>* dc) {
   if (!P.rader) {
     cx<T>* a = line;
     cx<T>* b = scratch;
-    run_chain<DIR, T>(a, b, ld, nl, P);
+    run_chain<DIR, T, BIG>(a, b, ld, nl, P);
     return a;
   }
   const int M = P.M;
@@ -193,7 +195,7 @@ __device__ cx<T>* line_fft(cx<T>* line, cx<T>* scratch, int ld, int nl, const Ax
   __syncthreads();
   cx<T>* a = scratch;
   cx<T>* b = line + 1;
-  run_chain<-1, T>(a, b, ld, nl, P);
+  run_chain<-1, T, BIG>(a, b, ld, nl, P);
   const cx<T>* bh = rader_bhat<T>(P, DIR);
   for (int t = threadIdx.x; t < total; t += blockDim.x) {
     const int l = t / M;
@@ -203,7 +205,7 @@ __device__ cx<T>* line_fft(cx<T>* line, cx<T>* scratch, int ld, int nl, const Ax
     a[l * ld + q] = cmul(v, bh[q]);
   }
   __syncthreads();
-  run_chain<1, T>(a, b, ld, nl, P);
+  run_chain<1, T, BIG>(a, b, ld, nl, P);
   // a == scratch here (2 * nst swaps); scatter back, x_0 still in line[0]
   for (int t = threadIdx.x; t < total; t += blockDim.x) {
     const int l = t / M;

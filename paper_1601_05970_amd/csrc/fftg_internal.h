@@ -101,8 +101,9 @@ struct LaunchCfg {
   int rows_per_tile;   // z passes
   int lines_y;         // y pass: h-block width
   int lines_x;         // x pass: h-block width (x 6 components)
-  int vec_per_tile;    // elementwise kernels
-  int threads;
+  int vec_per_tile;    // elementwise kernels (voxels per tile)
+  int threads_z, threads_y, threads_x, threads_v;
+  int big_radix;       // 1 when some axis needs the radix-11/13/17 codelets
 };
 
 }  // namespace fftg

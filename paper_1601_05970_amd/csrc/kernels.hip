@@ -146,10 +146,10 @@ struct TileLds {
 
 // ------------------------------------------------------------- z forward
 // tau = C(x):p(x) (or p, or Ce:p, or C(x):dE) for a tile of rows, R2C along z.
-template <class T>
+template <class T, int BIG>
 __global__ void __launch_bounds__(256) k_zfwd(const RveDev* __restrict__ rvs, int nrve, int rows_per_tile,
                                               int in_mode, int in_role, int tan_mode, int want_norm,
-                                              int check_done) {
+                                              int check_done, int update_p) {
   extern __shared__ __align__(16) char smem[];
   int tile;
   const int ri = find_rve(rvs, nrve, P_ZF, tile);
@@ -166,6 +166,11 @@ __global__ void __launch_bounds__(256) k_zfwd(const RveDev* __restrict__ rvs, in
 
   const double* in = (const double*)rv.buf[in_role];
   const T* tg = (const T*)rv.tang;
+  // CG search direction update fused here: p <- r + beta p (beta = 0 on the
+  // first iteration, where the residual pass has set p = r)
+  const double beta = update_p ? rv.cg->beta : 0.0;
+  const double* rres = (const double*)rv.buf[R_R];
+  double* pw = (double*)rv.buf[R_P];
   double nrm = 0.0;
   for (int t = threadIdx.x; t < nrows * n2; t += blockDim.x) {
     const int r = t / n2;
@@ -175,6 +180,13 @@ __global__ void __launch_bounds__(256) k_zfwd(const RveDev* __restrict__ rvs, in
     if (in_mode == IN_CONST_DE) {
 #pragma unroll
       for (int c = 0; c < 6; ++c) p[c] = T(rv.dE[c]);
+    } else if (update_p) {
+#pragma unroll
+      for (int c = 0; c < 6; ++c) {
+        const double pn = rres[c * nvox + v] + beta * pw[c * nvox + v];
+        pw[c * nvox + v] = pn;
+        p[c] = T(pn);
+      }
     } else {
 #pragma unroll
       for (int c = 0; c < 6; ++c) p[c] = T(in[c * nvox + v]);
@@ -204,7 +216,7 @@ __global__ void __launch_bounds__(256) k_zfwd(const RveDev* __restrict__ rvs, in
     for (int pr = 0; pr < 3; ++pr) L.line[(3 * r + pr) * ld + z] = cx<T>{tau[2 * pr], tau[2 * pr + 1]};
   }
   __syncthreads();
-  cx<T>* res = line_fft<-1, T>(L.line, L.scratch, ld, 3 * nrows, *rv.ax[2], L.dc);
+  cx<T>* res = line_fft<-1, T, BIG>(L.line, L.scratch, ld, 3 * nrows, *rv.ax[2], L.dc);
   // untangle two real transforms: A_k = (Z_k + conj Z_-k)/2, B_k = (Z_k - conj Z_-k)/(2i)
   cx<T>* spec = (cx<T>*)rv.spec;
   for (int t = threadIdx.x; t < nrows * 3 * H; t += blockDim.x) {
@@ -229,7 +241,7 @@ __global__ void __launch_bounds__(256) k_zfwd(const RveDev* __restrict__ rvs, in
 }
 
 // --------------------------------------------------------------- y pass
-template <class T, int DIR>
+template <class T, int DIR, int BIG>
 __global__ void __launch_bounds__(256) k_ypass(const RveDev* __restrict__ rvs, int nrve, int lines_per_tile,
                                                int check_done) {
   extern __shared__ __align__(16) char smem[];
@@ -254,7 +266,7 @@ __global__ void __launch_bounds__(256) k_ypass(const RveDev* __restrict__ rvs, i
     L.line[hh * ld + y] = base[(long long)y * H + hh];
   }
   __syncthreads();
-  cx<T>* res = line_fft<DIR, T>(L.line, L.scratch, ld, nh, *rv.ax[1], L.dc);
+  cx<T>* res = line_fft<DIR, T, BIG>(L.line, L.scratch, ld, nh, *rv.ax[1], L.dc);
   for (int t = threadIdx.x; t < n1 * nh; t += blockDim.x) {
     const int y = t / nh;
     const int hh = t - y * nh;
@@ -263,7 +275,7 @@ __global__ void __launch_bounds__(256) k_ypass(const RveDev* __restrict__ rvs, i
 }
 
 // --------------------------------------------------- x pass with G^(k)
-template <class T>
+template <class T, int BIG>
 __global__ void __launch_bounds__(256) k_xpass(const RveDev* __restrict__ rvs, int nrve, int lines_per_tile,
                                                double scale_in, int check_done) {
   extern __shared__ __align__(16) char smem[];
@@ -292,7 +304,7 @@ __global__ void __launch_bounds__(256) k_xpass(const RveDev* __restrict__ rvs, i
     L.line[(cx_ * nh + hh) * ld + x] = spec[cx_ * nspec + x * rs + off + hh];
   }
   __syncthreads();
-  cx<T>* res = line_fft<-1, T>(L.line, L.scratch, ld, nl, *rv.ax[0], L.dc);
+  cx<T>* res = line_fft<-1, T, BIG>(L.line, L.scratch, ld, nl, *rv.ax[0], L.dc);
   cx<T>* oth = (res == L.line) ? L.scratch : L.line;
   // projection on every frequency (k0, k1, k2) of the tile; xi_i = k_i / L_i, L_i = n_i
   const T scale = T(scale_in / double(rv.nvox));   // inverse DFT normalisation 1/|N|
@@ -317,7 +329,7 @@ __global__ void __launch_bounds__(256) k_xpass(const RveDev* __restrict__ rvs, i
     for (int c = 0; c < 6; ++c) res[(c * nh + hh) * ld + x] = v[c];
   }
   __syncthreads();
-  cx<T>* res2 = line_fft<1, T>(res, oth, ld, nl, *rv.ax[0], L.dc);
+  cx<T>* res2 = line_fft<1, T, BIG>(res, oth, ld, nl, *rv.ax[0], L.dc);
   for (int t = threadIdx.x; t < 6 * n0 * nh; t += blockDim.x) {
     const int cx_ = t / (n0 * nh);
     const int r = t - cx_ * n0 * nh;
@@ -328,7 +340,7 @@ __global__ void __launch_bounds__(256) k_xpass(const RveDev* __restrict__ rvs, i
 }
 
 // ------------------------------------------------------------- z inverse
-template <class T>
+template <class T, int BIG>
 __global__ void __launch_bounds__(256) k_zinv(const RveDev* __restrict__ rvs, int nrve, int rows_per_tile,
                                               int out_mode, int out_role, int check_done) {
   extern __shared__ __align__(16) char smem[];
@@ -365,7 +377,7 @@ __global__ void __launch_bounds__(256) k_zinv(const RveDev* __restrict__ rvs, in
     L.line[rp * ld + z] = Z;
   }
   __syncthreads();
-  cx<T>* res = line_fft<1, T>(L.line, L.scratch, ld, 3 * nrows, *rv.ax[2], L.dc);
+  cx<T>* res = line_fft<1, T, BIG>(L.line, L.scratch, ld, 3 * nrows, *rv.ax[2], L.dc);
   double dot = 0.0;
   if (out_mode == OUT_CG) {
     typedef typename ApType<T>::type AT;
@@ -436,6 +448,7 @@ __global__ void __launch_bounds__(256) k_zinv(const RveDev* __restrict__ rvs, in
       } else {
         cg->rr = tot;
         cg->bnorm2 = tot;
+        cg->beta = 0.0;
         const double t1 = cg->eta2 * tot, t2 = cg->floor2 * cg->snorm2;
         cg->target2 = t1 > t2 ? t1 : t2;
         cg->iters = 0;
@@ -504,24 +517,6 @@ __global__ void __launch_bounds__(256) k_cg_xr(const RveDev* __restrict__ rvs, i
       cg->status = st;
       cg->done = done;
     }
-  }
-}
-
-__global__ void __launch_bounds__(256) k_cg_p(const RveDev* __restrict__ rvs, int nrve, int vox_per_tile) {
-  int tile;
-  const int ri = find_rve(rvs, nrve, P_VEC, tile);
-  if (ri < 0) return;
-  const RveDev& rv = rvs[ri];
-  if (rv.skip || rv.cg->done) return;
-  const long long nvox = rv.nvox;
-  const double beta = rv.cg->beta;
-  const double* r = (const double*)rv.buf[R_R];
-  double* p = (double*)rv.buf[R_P];
-  const long long v0 = (long long)tile * vox_per_tile;
-  const int nv = (int)min((long long)vox_per_tile, nvox - v0);
-  for (int c = 0; c < 6; ++c) {
-    const long long o = c * nvox + v0;
-    for (int t = threadIdx.x; t < nv; t += blockDim.x) p[o + t] = r[o + t] + beta * p[o + t];
   }
 }
 
@@ -689,35 +684,68 @@ size_t lds_x(int mixed, int lines, int n0) {
   return mixed ? tile_lds<float>(6 * lines, n0) : tile_lds<double>(6 * lines, n0);
 }
 
+template <class T, int BIG>
+static void zfwd_go(dim3 G, dim3 B, size_t lds, hipStream_t s, const RveDev* rv, int nrve, int rows, int in_mode,
+                    int in_role, int tan_mode, int want_norm, int check_done, int update_p) {
+  hipLaunchKernelGGL((k_zfwd<T, BIG>), G, B, lds, s, rv, nrve, rows, in_mode, in_role, tan_mode, want_norm,
+                     check_done, update_p);
+}
+template <class T, int DIR, int BIG>
+static void ypass_go(dim3 G, dim3 B, size_t lds, hipStream_t s, const RveDev* rv, int nrve, int lines,
+                     int check_done) {
+  hipLaunchKernelGGL((k_ypass<T, DIR, BIG>), G, B, lds, s, rv, nrve, lines, check_done);
+}
+template <class T, int BIG>
+static void xpass_go(dim3 G, dim3 B, size_t lds, hipStream_t s, const RveDev* rv, int nrve, int lines,
+                     double scale, int check_done) {
+  hipLaunchKernelGGL((k_xpass<T, BIG>), G, B, lds, s, rv, nrve, lines, scale, check_done);
+}
+template <class T, int BIG>
+static void zinv_go(dim3 G, dim3 B, size_t lds, hipStream_t s, const RveDev* rv, int nrve, int rows, int out_mode,
+                    int out_role, int check_done) {
+  hipLaunchKernelGGL((k_zinv<T, BIG>), G, B, lds, s, rv, nrve, rows, out_mode, out_role, check_done);
+}
+
+#define DISPATCH_TB(fn, ...)                          \
+  do {                                                \
+    if (mixed) {                                      \
+      if (cfg.big_radix) fn<float, 1>(__VA_ARGS__);   \
+      else fn<float, 0>(__VA_ARGS__);                 \
+    } else {                                          \
+      if (cfg.big_radix) fn<double, 1>(__VA_ARGS__);  \
+      else fn<double, 0>(__VA_ARGS__);                \
+    }                                                 \
+  } while (0)
+
 hipError_t launch_zfwd(int mixed, const RveDev* rv, int nrve, int tiles, const LaunchCfg& cfg, size_t lds,
-                       int in_mode, int in_role, int tan_mode, int want_norm, int check_done, hipStream_t s) {
+                       int in_mode, int in_role, int tan_mode, int want_norm, int check_done, int update_p,
+                       hipStream_t s) {
   if (tiles <= 0) return hipSuccess;
-  if (mixed)
-    hipLaunchKernelGGL(k_zfwd<float>, dim3(tiles), dim3(cfg.threads), lds, s, rv, nrve, cfg.rows_per_tile,
-                       in_mode, in_role, tan_mode, want_norm, check_done);
-  else
-    hipLaunchKernelGGL(k_zfwd<double>, dim3(tiles), dim3(cfg.threads), lds, s, rv, nrve, cfg.rows_per_tile,
-                       in_mode, in_role, tan_mode, want_norm, check_done);
+  DISPATCH_TB(zfwd_go, dim3(tiles), dim3(cfg.threads_z), lds, s, rv, nrve, cfg.rows_per_tile, in_mode, in_role,
+              tan_mode, want_norm, check_done, update_p);
   return hipGetLastError();
 }
 
 hipError_t launch_ypass(int mixed, int dir, const RveDev* rv, int nrve, int tiles, const LaunchCfg& cfg,
                         size_t lds, int check_done, hipStream_t s) {
   if (tiles <= 0) return hipSuccess;
+  const dim3 G(tiles), B(cfg.threads_y);
   if (mixed) {
-    if (dir < 0)
-      hipLaunchKernelGGL((k_ypass<float, -1>), dim3(tiles), dim3(cfg.threads), lds, s, rv, nrve,
-                         cfg.lines_y, check_done);
-    else
-      hipLaunchKernelGGL((k_ypass<float, 1>), dim3(tiles), dim3(cfg.threads), lds, s, rv, nrve,
-                         cfg.lines_y, check_done);
+    if (cfg.big_radix) {
+      if (dir < 0) ypass_go<float, -1, 1>(G, B, lds, s, rv, nrve, cfg.lines_y, check_done);
+      else ypass_go<float, 1, 1>(G, B, lds, s, rv, nrve, cfg.lines_y, check_done);
+    } else {
+      if (dir < 0) ypass_go<float, -1, 0>(G, B, lds, s, rv, nrve, cfg.lines_y, check_done);
+      else ypass_go<float, 1, 0>(G, B, lds, s, rv, nrve, cfg.lines_y, check_done);
+    }
   } else {
-    if (dir < 0)
-      hipLaunchKernelGGL((k_ypass<double, -1>), dim3(tiles), dim3(cfg.threads), lds, s, rv, nrve,
-                         cfg.lines_y, check_done);
-    else
-      hipLaunchKernelGGL((k_ypass<double, 1>), dim3(tiles), dim3(cfg.threads), lds, s, rv, nrve,
-                         cfg.lines_y, check_done);
+    if (cfg.big_radix) {
+      if (dir < 0) ypass_go<double, -1, 1>(G, B, lds, s, rv, nrve, cfg.lines_y, check_done);
+      else ypass_go<double, 1, 1>(G, B, lds, s, rv, nrve, cfg.lines_y, check_done);
+    } else {
+      if (dir < 0) ypass_go<double, -1, 0>(G, B, lds, s, rv, nrve, cfg.lines_y, check_done);
+      else ypass_go<double, 1, 0>(G, B, lds, s, rv, nrve, cfg.lines_y, check_done);
+    }
   }
   return hipGetLastError();
 }
@@ -725,45 +753,30 @@ hipError_t launch_ypass(int mixed, int dir, const RveDev* rv, int nrve, int tile
 hipError_t launch_xpass(int mixed, const RveDev* rv, int nrve, int tiles, const LaunchCfg& cfg, size_t lds,
                         double scale, int check_done, hipStream_t s) {
   if (tiles <= 0) return hipSuccess;
-  if (mixed)
-    hipLaunchKernelGGL(k_xpass<float>, dim3(tiles), dim3(cfg.threads), lds, s, rv, nrve, cfg.lines_x, scale,
-                       check_done);
-  else
-    hipLaunchKernelGGL(k_xpass<double>, dim3(tiles), dim3(cfg.threads), lds, s, rv, nrve, cfg.lines_x, scale,
-                       check_done);
+  DISPATCH_TB(xpass_go, dim3(tiles), dim3(cfg.threads_x), lds, s, rv, nrve, cfg.lines_x, scale, check_done);
   return hipGetLastError();
 }
 
 hipError_t launch_zinv(int mixed, const RveDev* rv, int nrve, int tiles, const LaunchCfg& cfg, size_t lds,
                        int out_mode, int out_role, int check_done, hipStream_t s) {
   if (tiles <= 0) return hipSuccess;
-  if (mixed)
-    hipLaunchKernelGGL(k_zinv<float>, dim3(tiles), dim3(cfg.threads), lds, s, rv, nrve, cfg.rows_per_tile,
-                       out_mode, out_role, check_done);
-  else
-    hipLaunchKernelGGL(k_zinv<double>, dim3(tiles), dim3(cfg.threads), lds, s, rv, nrve, cfg.rows_per_tile,
-                       out_mode, out_role, check_done);
+  DISPATCH_TB(zinv_go, dim3(tiles), dim3(cfg.threads_z), lds, s, rv, nrve, cfg.rows_per_tile, out_mode, out_role,
+              check_done);
   return hipGetLastError();
 }
 
 hipError_t launch_cg_xr(int mixed, const RveDev* rv, int nrve, int tiles, const LaunchCfg& cfg, hipStream_t s) {
   if (tiles <= 0) return hipSuccess;
   if (mixed)
-    hipLaunchKernelGGL(k_cg_xr<float>, dim3(tiles), dim3(cfg.threads), 0, s, rv, nrve, cfg.vec_per_tile);
+    hipLaunchKernelGGL(k_cg_xr<float>, dim3(tiles), dim3(cfg.threads_v), 0, s, rv, nrve, cfg.vec_per_tile);
   else
-    hipLaunchKernelGGL(k_cg_xr<double>, dim3(tiles), dim3(cfg.threads), 0, s, rv, nrve, cfg.vec_per_tile);
-  return hipGetLastError();
-}
-
-hipError_t launch_cg_p(const RveDev* rv, int nrve, int tiles, const LaunchCfg& cfg, hipStream_t s) {
-  if (tiles <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_cg_p, dim3(tiles), dim3(cfg.threads), 0, s, rv, nrve, cfg.vec_per_tile);
+    hipLaunchKernelGGL(k_cg_xr<double>, dim3(tiles), dim3(cfg.threads_v), 0, s, rv, nrve, cfg.vec_per_tile);
   return hipGetLastError();
 }
 
 hipError_t launch_newton_update(const RveDev* rv, int nrve, int tiles, const LaunchCfg& cfg, hipStream_t s) {
   if (tiles <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_newton_update, dim3(tiles), dim3(cfg.threads), 0, s, rv, nrve, cfg.vec_per_tile);
+  hipLaunchKernelGGL(k_newton_update, dim3(tiles), dim3(cfg.threads_v), 0, s, rv, nrve, cfg.vec_per_tile);
   return hipGetLastError();
 }
 
@@ -771,10 +784,10 @@ hipError_t launch_constitutive(int mixed, const RveDev* rv, int nrve, int tiles,
                                int eps_role, int commit, hipStream_t s) {
   if (tiles <= 0) return hipSuccess;
   if (mixed)
-    hipLaunchKernelGGL(k_constitutive<float>, dim3(tiles), dim3(cfg.threads), 0, s, rv, nrve, cfg.vec_per_tile,
+    hipLaunchKernelGGL(k_constitutive<float>, dim3(tiles), dim3(cfg.threads_v), 0, s, rv, nrve, cfg.vec_per_tile,
                        eps_role, commit);
   else
-    hipLaunchKernelGGL(k_constitutive<double>, dim3(tiles), dim3(cfg.threads), 0, s, rv, nrve,
+    hipLaunchKernelGGL(k_constitutive<double>, dim3(tiles), dim3(cfg.threads_v), 0, s, rv, nrve,
                        cfg.vec_per_tile, eps_role, commit);
   return hipGetLastError();
 }

@@ -22,7 +22,8 @@ size_t lds_z(int mixed, int rows, int n2);
 size_t lds_y(int mixed, int lines, int n1);
 size_t lds_x(int mixed, int lines, int n0);
 hipError_t launch_zfwd(int mixed, const RveDev* rv, int nrve, int tiles, const LaunchCfg& cfg, size_t lds,
-                       int in_mode, int in_role, int tan_mode, int want_norm, int check_done, hipStream_t s);
+                       int in_mode, int in_role, int tan_mode, int want_norm, int check_done, int update_p,
+                       hipStream_t s);
 hipError_t launch_ypass(int mixed, int dir, const RveDev* rv, int nrve, int tiles, const LaunchCfg& cfg,
                         size_t lds, int check_done, hipStream_t s);
 hipError_t launch_xpass(int mixed, const RveDev* rv, int nrve, int tiles, const LaunchCfg& cfg, size_t lds,
@@ -30,7 +31,6 @@ hipError_t launch_xpass(int mixed, const RveDev* rv, int nrve, int tiles, const 
 hipError_t launch_zinv(int mixed, const RveDev* rv, int nrve, int tiles, const LaunchCfg& cfg, size_t lds,
                        int out_mode, int out_role, int check_done, hipStream_t s);
 hipError_t launch_cg_xr(int mixed, const RveDev* rv, int nrve, int tiles, const LaunchCfg& cfg, hipStream_t s);
-hipError_t launch_cg_p(const RveDev* rv, int nrve, int tiles, const LaunchCfg& cfg, hipStream_t s);
 hipError_t launch_newton_update(const RveDev* rv, int nrve, int tiles, const LaunchCfg& cfg, hipStream_t s);
 hipError_t launch_constitutive(int mixed, const RveDev* rv, int nrve, int tiles, const LaunchCfg& cfg,
                                int eps_role, int commit, hipStream_t s);
@@ -259,6 +259,7 @@ struct fftg_plan_s {
   int stage_next;
   CgState* h_cg;      // pinned
   int max_tiles;
+  int big_radix;      // an axis uses the radix-11/13/17 codelets
 };
 
 struct fftg_history_s {
@@ -282,23 +283,49 @@ void fftg_options_default(fftg_options* o) {
 }
 
 // Tile sizes fit the FP64 passes in 64 KB of LDS (mixed plans also run the
-// FP64 residual with the same configuration).
-static LaunchCfg choose_cfg(int n0, int n1, int n2, long long nvox) {
+// FP64 residual with the same configuration).  Starting from the widest tile
+// LDS allows, tiles shrink until a launch has at least kMinTiles workgroups
+// (the chip has 256 CUs), so small RVEs still spread over the device.
+static const int kMinTiles = 2048;
+
+static int threads_for(long long points) {
+  return points <= 192 ? 64 : (points <= 640 ? 128 : 256);
+}
+
+struct GridSum {
+  int n0 = 1, n1 = 1, n2 = 1;      // maxima over members
+  long long rows = 0;               // sum of n0*n1
+  long long yl = 0;                 // sum of 6*n0 (y-line groups per h)
+  long long xl = 0;                 // sum of n1
+  long long hmax = 1;
+  long long vox = 0;
+  int big = 0;
+};
+
+static LaunchCfg choose_cfg(const GridSum& gs) {
   LaunchCfg c;
-  c.threads = 256;
   const size_t budget = 64 * 1024;
+  const long long H = gs.hmax;
   int R = 8;
-  while (R > 1 && lds_z(0, R, n2) > budget) --R;
+  while (R > 1 && lds_z(0, R, gs.n2) > budget) --R;
+  while (R > 1 && (gs.rows + R - 1) / R < kMinTiles) --R;
   c.rows_per_tile = R;
+  c.threads_z = threads_for((long long)3 * R * gs.n2 / 2);
   int L = 16;
-  while (L > 1 && lds_y(0, L, n1) > budget) --L;
+  while (L > 1 && lds_y(0, L, gs.n1) > budget) --L;
+  while (L > 1 && gs.yl * ((H + L - 1) / L) < kMinTiles) --L;
   c.lines_y = L;
+  c.threads_y = threads_for((long long)L * gs.n1 / 2);
   int Lx = 8;
-  while (Lx > 1 && lds_x(0, Lx, n0) > budget) --Lx;
+  while (Lx > 1 && lds_x(0, Lx, gs.n0) > budget) --Lx;
+  while (Lx > 1 && gs.xl * ((H + Lx - 1) / Lx) < kMinTiles) --Lx;
   c.lines_x = Lx;
-  long long v = nvox / 2048;
-  v = std::max(256LL, std::min(4096LL, v));
-  c.vec_per_tile = (int)((v + 255) / 256 * 256);
+  c.threads_x = threads_for((long long)6 * Lx * gs.n0 / 2);
+  long long v = gs.vox / kMinTiles;
+  v = std::max(64LL, std::min(4096LL, v));
+  c.vec_per_tile = (int)((v + 63) / 64 * 64);
+  c.threads_v = std::min(256, c.vec_per_tile);
+  c.big_radix = gs.big;
   return c;
 }
 
@@ -417,6 +444,10 @@ fftg_status fftg_plan_create(fftg_plan* out, int n0, int n1, int n2, const uint8
     }
     idx[ns[i]] = (int)pl->axes.size() - 1;
   }
+  pl->big_radix = 0;
+  for (auto& a : pl->axes)
+    for (int s = 0; s < a.dev.nst; ++s)
+      if (a.dev.radix[s] > 9) pl->big_radix = 1;
   hipError_t e = hipSuccess;
 #define PLAN_TRY(expr)                                                            \
   do {                                                                            \
@@ -612,15 +643,20 @@ static void fill_desc(RveDev& rv, fftg_plan pl, fftg_history h, const LaunchCfg&
 }
 
 static void group_config(Group& g) {
-  int n0 = 1, n1 = 1, n2 = 1;
-  long long nv = 0;
+  GridSum gs;
   for (auto* pl : g.plans) {
-    n0 = std::max(n0, pl->n[0]);
-    n1 = std::max(n1, pl->n[1]);
-    n2 = std::max(n2, pl->n[2]);
-    nv = std::max(nv, pl->nvox);
+    gs.n0 = std::max(gs.n0, pl->n[0]);
+    gs.n1 = std::max(gs.n1, pl->n[1]);
+    gs.n2 = std::max(gs.n2, pl->n[2]);
+    gs.rows += (long long)pl->n[0] * pl->n[1];
+    gs.yl += 6LL * pl->n[0];
+    gs.xl += pl->n[1];
+    gs.hmax = std::max<long long>(gs.hmax, pl->H);
+    gs.vox += pl->nvox;
+    gs.big = gs.big || pl->big_radix;
   }
-  g.cfg = choose_cfg(n0, n1, n2, nv);
+  g.cfg = choose_cfg(gs);
+  const int n0 = gs.n0, n1 = gs.n1, n2 = gs.n2;
   g.lds_zf = lds_z(0, g.cfg.rows_per_tile, n2);
   g.lds_y = lds_y(0, g.cfg.lines_y, n1);
   g.lds_x = lds_x(0, g.cfg.lines_x, n0);
@@ -673,10 +709,10 @@ static void set_skip(Group& g, size_t i, bool skip) {
 // -------------------------------------------------------- apply sequences
 // G:(C:in) into the out mode; in_role / const dE input.
 static fftg_status enqueue_apply(Group& g, int mixed, int in_mode, int in_role, int tan_mode, int want_norm,
-                                 int out_mode, int out_role, double scale, int check_done) {
+                                 int out_mode, int out_role, double scale, int check_done, int update_p = 0) {
   const int nr = (int)g.h.size();
   PROF_LAUNCH(FFTG_KERNEL_ZFWD, launch_zfwd(mixed, g.d, nr, g.total[P_ZF], g.cfg, g.lds_zf, in_mode, in_role,
-                                            tan_mode, want_norm, check_done, g.stream));
+                                            tan_mode, want_norm, check_done, update_p, g.stream));
   PROF_LAUNCH(FFTG_KERNEL_Y_FWD,
               launch_ypass(mixed, -1, g.d, nr, g.total[P_Y], g.cfg, g.lds_y, check_done, g.stream));
   PROF_LAUNCH(FFTG_KERNEL_X_PROJ,
@@ -691,10 +727,10 @@ static fftg_status enqueue_apply(Group& g, int mixed, int in_mode, int in_role, 
 static fftg_status enqueue_cg_iters(Group& g, int iters) {
   const int nr = (int)g.h.size();
   for (int i = 0; i < iters; ++i) {
-    fftg_status st = enqueue_apply(g, g.mixed, IN_ROLE, R_P, TAN_CURRENT, 0, OUT_CG, R_AP, 1.0, 1);
+    // p <- r + beta p is fused into the first pass of the product
+    fftg_status st = enqueue_apply(g, g.mixed, IN_ROLE, R_P, TAN_CURRENT, 0, OUT_CG, R_AP, 1.0, 1, 1);
     if (st != FFTG_OK) return st;
     PROF_LAUNCH(FFTG_KERNEL_CG_XR, launch_cg_xr(g.mixed, g.d, nr, g.total[P_VEC], g.cfg, g.stream));
-    PROF_LAUNCH(FFTG_KERNEL_CG_P, launch_cg_p(g.d, nr, g.total[P_VEC], g.cfg, g.stream));
   }
   return FFTG_OK;
 }

@@ -84,7 +84,8 @@ typedef struct {
   int max_cg;             /* CG iterations per Newton iteration */
   int predictor;          /* fftg_predictor */
   double rhs_floor;       /* CG also stops at ||r|| <= rhs_floor ||s|| (default 1e-14) */
-  double mixed_cg_floor;  /* MIXED only: effective eta_CG >= this (default 1e-5) */
+  double mixed_cg_floor;  /* MIXED only: effective eta_CG >= this, and the floor of the
+                             FP32-evaluated predictor right-hand side (default 1e-5) */
   int cg_chunk;           /* CG iterations enqueued between host checks (default 16) */
 } fftg_options;
 

@@ -133,12 +133,71 @@ __device__ __forceinline__ const cx<double>* axis_tw<double>(const AxisDev& P) {
 template <>
 __device__ __forceinline__ const cx<float>* axis_tw<float>(const AxisDev& P) { return P.tw32; }
 
+template <class T>
+__device__ __forceinline__ const cx<T>* rader_bhat(const AxisDev& P, int dir);
+template <>
+__device__ __forceinline__ const cx<double>* rader_bhat<double>(const AxisDev& P, int dir) {
+  return dir < 0 ? P.bf64 : P.bi64;
+}
+template <>
+__device__ __forceinline__ const cx<float>* rader_bhat<float>(const AxisDev& P, int dir) {
+  return dir < 0 ? P.bf32 : P.bi32;
+}
+
+// LDS copy of one axis' tables, loaded once per workgroup so that the
+// barrier-separated stages never wait on global memory.
+template <class T>
+struct AxisLds {
+  int M, nst, rader;
+  int radix[kMaxStages];
+  cx<T>* tw;     // M roots exp(-2 pi i m / M)
+  int* pin;      // Rader permutations (M each)
+  int* pout;
+  cx<T>* bf;     // Rader DFT_M(b)/M, forward and inverse
+  cx<T>* bi;
+};
+
+// LDS bytes of the tables of an axis of length <= N.
+template <class T>
+__host__ __device__ constexpr size_t axis_lds_bytes(int N) {
+  return (((size_t)N * (3 * sizeof(cx<T>) + 2 * sizeof(int))) + 15) / 16 * 16;
+}
+
+// Carves the tables out of base and loads them (whole workgroup; the
+// caller's next __syncthreads publishes them).
+template <class T>
+__device__ void load_axis_lds(const AxisDev& P, char* base, AxisLds<T>& A) {
+  A.M = P.M;
+  A.nst = P.nst;
+  A.rader = P.rader;
+#pragma unroll
+  for (int s = 0; s < kMaxStages; ++s) A.radix[s] = P.radix[s];
+  const int N = P.N;
+  A.tw = reinterpret_cast<cx<T>*>(base);
+  A.bf = A.tw + N;
+  A.bi = A.bf + N;
+  A.pin = reinterpret_cast<int*>(A.bi + N);
+  A.pout = A.pin + N;
+  const cx<T>* tw = axis_tw<T>(P);
+  for (int t = threadIdx.x; t < P.M; t += blockDim.x) A.tw[t] = tw[t];
+  if (P.rader) {
+    const cx<T>* bf = rader_bhat<T>(P, -1);
+    const cx<T>* bi = rader_bhat<T>(P, 1);
+    for (int t = threadIdx.x; t < P.M; t += blockDim.x) {
+      A.bf[t] = bf[t];
+      A.bi[t] = bi[t];
+      A.pin[t] = P.perm_in[t];
+      A.pout[t] = P.perm_out[t];
+    }
+  }
+}
+
 // Runs the Stockham chain of P on a (result ends in a; buffers are swapped).
 // BIG = 0 compiles only the radix 2, 3, 4, 5, 7, 9 codelets (lower register
 // use); BIG = 1 adds 11, 13, 17.
 template <int DIR, class T, int BIG>
-__device__ void run_chain(cx<T>*& a, cx<T>*& b, int ld, int nl, const AxisDev& P) {
-  const cx<T>* tw = axis_tw<T>(P);
+__device__ void run_chain(cx<T>*& a, cx<T>*& b, int ld, int nl, const AxisLds<T>& P) {
+  const cx<T>* tw = P.tw;
   int Ns = 1;
   for (int s = 0; s < P.nst; ++s) {
     const int R = P.radix[s];
@@ -162,23 +221,12 @@ __device__ void run_chain(cx<T>*& a, cx<T>*& b, int ld, int nl, const AxisDev& P
   }
 }
 
-template <class T>
-__device__ __forceinline__ const cx<T>* rader_bhat(const AxisDev& P, int dir);
-template <>
-__device__ __forceinline__ const cx<double>* rader_bhat<double>(const AxisDev& P, int dir) {
-  return dir < 0 ? P.bf64 : P.bi64;
-}
-template <>
-__device__ __forceinline__ const cx<float>* rader_bhat<float>(const AxisDev& P, int dir) {
-  return dir < 0 ? P.bf32 : P.bi32;
-}
-
 // In-LDS FFT of nl lines of length P.N, DIR = -1 forward, +1 inverse
 // (unnormalised).  line and scratch each hold nl lines of stride ld >= N;
 // dc holds nl scratch slots (Rader only).  Returns the buffer holding the
 // result (line or scratch).  Must be called by the whole workgroup.
 template <int DIR, class T, int BIG>
-__device__ cx<T>* line_fft(cx<T>* line, cx<T>* scratch, int ld, int nl, const AxisDev& P, cx<T>* dc) {
+__device__ cx<T>* line_fft(cx<T>* line, cx<T>* scratch, int ld, int nl, const AxisLds<T>& P, cx<T>* dc) {
   if (!P.rader) {
     cx<T>* a = line;
     cx<T>* b = scratch;
@@ -190,13 +238,13 @@ __device__ cx<T>* line_fft(cx<T>* line, cx<T>* scratch, int ld, int nl, const Ax
   for (int t = threadIdx.x; t < total; t += blockDim.x) {
     const int l = t / M;
     const int q = t - l * M;
-    scratch[l * ld + q] = line[l * ld + P.perm_in[q]];
+    scratch[l * ld + q] = line[l * ld + P.pin[q]];
   }
   __syncthreads();
   cx<T>* a = scratch;
   cx<T>* b = line + 1;
   run_chain<-1, T, BIG>(a, b, ld, nl, P);
-  const cx<T>* bh = rader_bhat<T>(P, DIR);
+  const cx<T>* bh = DIR < 0 ? P.bf : P.bi;
   for (int t = threadIdx.x; t < total; t += blockDim.x) {
     const int l = t / M;
     const int q = t - l * M;
@@ -210,7 +258,7 @@ __device__ cx<T>* line_fft(cx<T>* line, cx<T>* scratch, int ld, int nl, const Ax
   for (int t = threadIdx.x; t < total; t += blockDim.x) {
     const int l = t / M;
     const int m = t - l * M;
-    line[l * ld + P.perm_out[m]] = cadd(line[l * ld], a[l * ld + m]);
+    line[l * ld + P.pout[m]] = cadd(line[l * ld], a[l * ld + m]);
   }
   __syncthreads();
   for (int l = threadIdx.x; l < nl; l += blockDim.x) line[l * ld] = cadd(line[l * ld], dc[l]);

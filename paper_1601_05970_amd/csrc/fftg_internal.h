@@ -104,6 +104,7 @@ struct LaunchCfg {
   int vec_per_tile;    // elementwise kernels (voxels per tile)
   int threads_z, threads_y, threads_x, threads_v;
   int big_radix;       // 1 when some axis needs the radix-11/13/17 codelets
+  int n0max, n1max, n2max;  // largest extents of the launch (LDS table sizing)
 };
 
 }  // namespace fftg

@@ -71,11 +71,11 @@ __device__ bool reduce_tiles(const double* vals, int nv, double* partial, int nt
   __syncthreads();
   const bool last = s_last;
   if (!last) return false;
-  __threadfence();
+  __threadfence();  // acquire: the other tiles' partials are visible below
   for (int i = 0; i < nv; ++i) {
     double acc = 0.0;
-    for (int t = threadIdx.x; t < ntiles; t += blockDim.x)
-      acc += __hip_atomic_load(partial + i * ntiles + t, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const double* pp = partial + i * ntiles;
+    for (int t = threadIdx.x; t < ntiles; t += blockDim.x) acc += pp[t];
     const double s = block_sum(acc, sh);
     if (threadIdx.x == 0) out[i] = s;
   }
@@ -129,15 +129,18 @@ __device__ __forceinline__ void ghat_apply(cx<T> t[6], T q0, T q1, T q2, T scale
 
 __device__ __forceinline__ int sfreq(int m, int n) { return (2 * m < n) ? m : m - n; }
 
-// LDS carve-up for a tile of nl lines of stride ld
+// LDS carve-up for a tile: axis tables, then nl lines of stride ld, the
+// ping-pong scratch, Rader slots and the reduction scratch.
 template <class T>
 struct TileLds {
+  AxisLds<T> ax;
   cx<T>* line;
   cx<T>* scratch;
   cx<T>* dc;
   double* red;
-  __device__ TileLds(char* base, int nl, int ld) {
-    line = reinterpret_cast<cx<T>*>(base);
+  __device__ TileLds(char* base, int nl, int ld, const AxisDev& P, int ldmax) {
+    load_axis_lds<T>(P, base, ax);
+    line = reinterpret_cast<cx<T>*>(base + axis_lds_bytes<T>(ldmax));
     scratch = line + (size_t)nl * ld;
     dc = scratch + (size_t)nl * ld;
     red = reinterpret_cast<double*>(dc + nl + (nl & 1));
@@ -147,7 +150,7 @@ struct TileLds {
 // ------------------------------------------------------------- z forward
 // tau = C(x):p(x) (or p, or Ce:p, or C(x):dE) for a tile of rows, R2C along z.
 template <class T, int BIG>
-__global__ void __launch_bounds__(256) k_zfwd(const RveDev* __restrict__ rvs, int nrve, int rows_per_tile,
+__global__ void __launch_bounds__(256) k_zfwd(const RveDev* __restrict__ rvs, int nrve, int rows_per_tile, int ldmax,
                                               int in_mode, int in_role, int tan_mode, int want_norm,
                                               int check_done, int update_p) {
   extern __shared__ __align__(16) char smem[];
@@ -162,7 +165,7 @@ __global__ void __launch_bounds__(256) k_zfwd(const RveDev* __restrict__ rvs, in
   const int row0 = tile * rows_per_tile;
   const int nrows = min(rows_per_tile, nrows_tot - row0);
   const int ld = n2;
-  TileLds<T> L(smem, 3 * rows_per_tile, ld);
+  TileLds<T> L(smem, 3 * rows_per_tile, ld, *rv.ax[2], ldmax);
 
   const double* in = (const double*)rv.buf[in_role];
   const T* tg = (const T*)rv.tang;
@@ -216,7 +219,7 @@ __global__ void __launch_bounds__(256) k_zfwd(const RveDev* __restrict__ rvs, in
     for (int pr = 0; pr < 3; ++pr) L.line[(3 * r + pr) * ld + z] = cx<T>{tau[2 * pr], tau[2 * pr + 1]};
   }
   __syncthreads();
-  cx<T>* res = line_fft<-1, T, BIG>(L.line, L.scratch, ld, 3 * nrows, *rv.ax[2], L.dc);
+  cx<T>* res = line_fft<-1, T, BIG>(L.line, L.scratch, ld, 3 * nrows, L.ax, L.dc);
   // untangle two real transforms: A_k = (Z_k + conj Z_-k)/2, B_k = (Z_k - conj Z_-k)/(2i)
   cx<T>* spec = (cx<T>*)rv.spec;
   for (int t = threadIdx.x; t < nrows * 3 * H; t += blockDim.x) {
@@ -243,7 +246,7 @@ __global__ void __launch_bounds__(256) k_zfwd(const RveDev* __restrict__ rvs, in
 // --------------------------------------------------------------- y pass
 template <class T, int DIR, int BIG>
 __global__ void __launch_bounds__(256) k_ypass(const RveDev* __restrict__ rvs, int nrve, int lines_per_tile,
-                                               int check_done) {
+                                               int ldmax, int check_done) {
   extern __shared__ __align__(16) char smem[];
   int tile;
   const int ri = find_rve(rvs, nrve, P_Y, tile);
@@ -258,7 +261,7 @@ __global__ void __launch_bounds__(256) k_ypass(const RveDev* __restrict__ rvs, i
   const int h0 = (rem - i0 * nhb) * lines_per_tile;
   const int nh = min(lines_per_tile, H - h0);
   const int ld = n1;
-  TileLds<T> L(smem, lines_per_tile, ld);
+  TileLds<T> L(smem, lines_per_tile, ld, *rv.ax[1], ldmax);
   cx<T>* base = (cx<T>*)rv.spec + c * rv.nspec + (long long)i0 * n1 * H + h0;
   for (int t = threadIdx.x; t < n1 * nh; t += blockDim.x) {
     const int y = t / nh;
@@ -266,7 +269,7 @@ __global__ void __launch_bounds__(256) k_ypass(const RveDev* __restrict__ rvs, i
     L.line[hh * ld + y] = base[(long long)y * H + hh];
   }
   __syncthreads();
-  cx<T>* res = line_fft<DIR, T, BIG>(L.line, L.scratch, ld, nh, *rv.ax[1], L.dc);
+  cx<T>* res = line_fft<DIR, T, BIG>(L.line, L.scratch, ld, nh, L.ax, L.dc);
   for (int t = threadIdx.x; t < n1 * nh; t += blockDim.x) {
     const int y = t / nh;
     const int hh = t - y * nh;
@@ -277,7 +280,7 @@ __global__ void __launch_bounds__(256) k_ypass(const RveDev* __restrict__ rvs, i
 // --------------------------------------------------- x pass with G^(k)
 template <class T, int BIG>
 __global__ void __launch_bounds__(256) k_xpass(const RveDev* __restrict__ rvs, int nrve, int lines_per_tile,
-                                               double scale_in, int check_done) {
+                                               int ldmax, double scale_in, int check_done) {
   extern __shared__ __align__(16) char smem[];
   int tile;
   const int ri = find_rve(rvs, nrve, P_X, tile);
@@ -292,7 +295,7 @@ __global__ void __launch_bounds__(256) k_xpass(const RveDev* __restrict__ rvs, i
   const int nh = min(lines_per_tile, H - h0);
   const int ld = n0;
   const int nl = 6 * nh;
-  TileLds<T> L(smem, 6 * lines_per_tile, ld);
+  TileLds<T> L(smem, 6 * lines_per_tile, ld, *rv.ax[0], ldmax);
   cx<T>* spec = (cx<T>*)rv.spec;
   const long long rs = (long long)n1 * H;
   const long long off = (long long)i1 * H + h0;
@@ -304,7 +307,7 @@ __global__ void __launch_bounds__(256) k_xpass(const RveDev* __restrict__ rvs, i
     L.line[(cx_ * nh + hh) * ld + x] = spec[cx_ * nspec + x * rs + off + hh];
   }
   __syncthreads();
-  cx<T>* res = line_fft<-1, T, BIG>(L.line, L.scratch, ld, nl, *rv.ax[0], L.dc);
+  cx<T>* res = line_fft<-1, T, BIG>(L.line, L.scratch, ld, nl, L.ax, L.dc);
   cx<T>* oth = (res == L.line) ? L.scratch : L.line;
   // projection on every frequency (k0, k1, k2) of the tile; xi_i = k_i / L_i, L_i = n_i
   const T scale = T(scale_in / double(rv.nvox));   // inverse DFT normalisation 1/|N|
@@ -329,7 +332,7 @@ __global__ void __launch_bounds__(256) k_xpass(const RveDev* __restrict__ rvs, i
     for (int c = 0; c < 6; ++c) res[(c * nh + hh) * ld + x] = v[c];
   }
   __syncthreads();
-  cx<T>* res2 = line_fft<1, T, BIG>(res, oth, ld, nl, *rv.ax[0], L.dc);
+  cx<T>* res2 = line_fft<1, T, BIG>(res, oth, ld, nl, L.ax, L.dc);
   for (int t = threadIdx.x; t < 6 * n0 * nh; t += blockDim.x) {
     const int cx_ = t / (n0 * nh);
     const int r = t - cx_ * n0 * nh;
@@ -341,7 +344,7 @@ __global__ void __launch_bounds__(256) k_xpass(const RveDev* __restrict__ rvs, i
 
 // ------------------------------------------------------------- z inverse
 template <class T, int BIG>
-__global__ void __launch_bounds__(256) k_zinv(const RveDev* __restrict__ rvs, int nrve, int rows_per_tile,
+__global__ void __launch_bounds__(256) k_zinv(const RveDev* __restrict__ rvs, int nrve, int rows_per_tile, int ldmax,
                                               int out_mode, int out_role, int check_done) {
   extern __shared__ __align__(16) char smem[];
   int tile;
@@ -355,7 +358,7 @@ __global__ void __launch_bounds__(256) k_zinv(const RveDev* __restrict__ rvs, in
   const int row0 = tile * rows_per_tile;
   const int nrows = min(rows_per_tile, nrows_tot - row0);
   const int ld = n2;
-  TileLds<T> L(smem, 3 * rows_per_tile, ld);
+  TileLds<T> L(smem, 3 * rows_per_tile, ld, *rv.ax[2], ldmax);
   const cx<T>* spec = (const cx<T>*)rv.spec;
   // Z_k = A_k + i B_k, Z_{n-k} = conj(A_k) + i conj(B_k)
   for (int t = threadIdx.x; t < nrows * 3 * n2; t += blockDim.x) {
@@ -377,7 +380,7 @@ __global__ void __launch_bounds__(256) k_zinv(const RveDev* __restrict__ rvs, in
     L.line[rp * ld + z] = Z;
   }
   __syncthreads();
-  cx<T>* res = line_fft<1, T, BIG>(L.line, L.scratch, ld, 3 * nrows, *rv.ax[2], L.dc);
+  cx<T>* res = line_fft<1, T, BIG>(L.line, L.scratch, ld, 3 * nrows, L.ax, L.dc);
   double dot = 0.0;
   if (out_mode == OUT_CG) {
     typedef typename ApType<T>::type AT;
@@ -675,35 +678,38 @@ static size_t tile_lds(int nl, int ld) {
 }
 
 size_t lds_z(int mixed, int rows, int n2) {
-  return mixed ? tile_lds<float>(3 * rows, n2) : tile_lds<double>(3 * rows, n2);
+  return mixed ? tile_lds<float>(3 * rows, n2) + axis_lds_bytes<float>(n2)
+               : tile_lds<double>(3 * rows, n2) + axis_lds_bytes<double>(n2);
 }
 size_t lds_y(int mixed, int lines, int n1) {
-  return mixed ? tile_lds<float>(lines, n1) : tile_lds<double>(lines, n1);
+  return mixed ? tile_lds<float>(lines, n1) + axis_lds_bytes<float>(n1)
+               : tile_lds<double>(lines, n1) + axis_lds_bytes<double>(n1);
 }
 size_t lds_x(int mixed, int lines, int n0) {
-  return mixed ? tile_lds<float>(6 * lines, n0) : tile_lds<double>(6 * lines, n0);
+  return mixed ? tile_lds<float>(6 * lines, n0) + axis_lds_bytes<float>(n0)
+               : tile_lds<double>(6 * lines, n0) + axis_lds_bytes<double>(n0);
 }
 
 template <class T, int BIG>
-static void zfwd_go(dim3 G, dim3 B, size_t lds, hipStream_t s, const RveDev* rv, int nrve, int rows, int in_mode,
-                    int in_role, int tan_mode, int want_norm, int check_done, int update_p) {
-  hipLaunchKernelGGL((k_zfwd<T, BIG>), G, B, lds, s, rv, nrve, rows, in_mode, in_role, tan_mode, want_norm,
+static void zfwd_go(dim3 G, dim3 B, size_t lds, hipStream_t s, const RveDev* rv, int nrve, int rows, int ldmax,
+                    int in_mode, int in_role, int tan_mode, int want_norm, int check_done, int update_p) {
+  hipLaunchKernelGGL((k_zfwd<T, BIG>), G, B, lds, s, rv, nrve, rows, ldmax, in_mode, in_role, tan_mode, want_norm,
                      check_done, update_p);
 }
 template <class T, int DIR, int BIG>
-static void ypass_go(dim3 G, dim3 B, size_t lds, hipStream_t s, const RveDev* rv, int nrve, int lines,
+static void ypass_go(dim3 G, dim3 B, size_t lds, hipStream_t s, const RveDev* rv, int nrve, int lines, int ldmax,
                      int check_done) {
-  hipLaunchKernelGGL((k_ypass<T, DIR, BIG>), G, B, lds, s, rv, nrve, lines, check_done);
+  hipLaunchKernelGGL((k_ypass<T, DIR, BIG>), G, B, lds, s, rv, nrve, lines, ldmax, check_done);
 }
 template <class T, int BIG>
-static void xpass_go(dim3 G, dim3 B, size_t lds, hipStream_t s, const RveDev* rv, int nrve, int lines,
+static void xpass_go(dim3 G, dim3 B, size_t lds, hipStream_t s, const RveDev* rv, int nrve, int lines, int ldmax,
                      double scale, int check_done) {
-  hipLaunchKernelGGL((k_xpass<T, BIG>), G, B, lds, s, rv, nrve, lines, scale, check_done);
+  hipLaunchKernelGGL((k_xpass<T, BIG>), G, B, lds, s, rv, nrve, lines, ldmax, scale, check_done);
 }
 template <class T, int BIG>
-static void zinv_go(dim3 G, dim3 B, size_t lds, hipStream_t s, const RveDev* rv, int nrve, int rows, int out_mode,
-                    int out_role, int check_done) {
-  hipLaunchKernelGGL((k_zinv<T, BIG>), G, B, lds, s, rv, nrve, rows, out_mode, out_role, check_done);
+static void zinv_go(dim3 G, dim3 B, size_t lds, hipStream_t s, const RveDev* rv, int nrve, int rows, int ldmax,
+                    int out_mode, int out_role, int check_done) {
+  hipLaunchKernelGGL((k_zinv<T, BIG>), G, B, lds, s, rv, nrve, rows, ldmax, out_mode, out_role, check_done);
 }
 
 #define DISPATCH_TB(fn, ...)                          \
@@ -721,8 +727,8 @@ hipError_t launch_zfwd(int mixed, const RveDev* rv, int nrve, int tiles, const L
                        int in_mode, int in_role, int tan_mode, int want_norm, int check_done, int update_p,
                        hipStream_t s) {
   if (tiles <= 0) return hipSuccess;
-  DISPATCH_TB(zfwd_go, dim3(tiles), dim3(cfg.threads_z), lds, s, rv, nrve, cfg.rows_per_tile, in_mode, in_role,
-              tan_mode, want_norm, check_done, update_p);
+  DISPATCH_TB(zfwd_go, dim3(tiles), dim3(cfg.threads_z), lds, s, rv, nrve, cfg.rows_per_tile, cfg.n2max, in_mode,
+              in_role, tan_mode, want_norm, check_done, update_p);
   return hipGetLastError();
 }
 
@@ -732,19 +738,19 @@ hipError_t launch_ypass(int mixed, int dir, const RveDev* rv, int nrve, int tile
   const dim3 G(tiles), B(cfg.threads_y);
   if (mixed) {
     if (cfg.big_radix) {
-      if (dir < 0) ypass_go<float, -1, 1>(G, B, lds, s, rv, nrve, cfg.lines_y, check_done);
-      else ypass_go<float, 1, 1>(G, B, lds, s, rv, nrve, cfg.lines_y, check_done);
+      if (dir < 0) ypass_go<float, -1, 1>(G, B, lds, s, rv, nrve, cfg.lines_y, cfg.n1max, check_done);
+      else ypass_go<float, 1, 1>(G, B, lds, s, rv, nrve, cfg.lines_y, cfg.n1max, check_done);
     } else {
-      if (dir < 0) ypass_go<float, -1, 0>(G, B, lds, s, rv, nrve, cfg.lines_y, check_done);
-      else ypass_go<float, 1, 0>(G, B, lds, s, rv, nrve, cfg.lines_y, check_done);
+      if (dir < 0) ypass_go<float, -1, 0>(G, B, lds, s, rv, nrve, cfg.lines_y, cfg.n1max, check_done);
+      else ypass_go<float, 1, 0>(G, B, lds, s, rv, nrve, cfg.lines_y, cfg.n1max, check_done);
     }
   } else {
     if (cfg.big_radix) {
-      if (dir < 0) ypass_go<double, -1, 1>(G, B, lds, s, rv, nrve, cfg.lines_y, check_done);
-      else ypass_go<double, 1, 1>(G, B, lds, s, rv, nrve, cfg.lines_y, check_done);
+      if (dir < 0) ypass_go<double, -1, 1>(G, B, lds, s, rv, nrve, cfg.lines_y, cfg.n1max, check_done);
+      else ypass_go<double, 1, 1>(G, B, lds, s, rv, nrve, cfg.lines_y, cfg.n1max, check_done);
     } else {
-      if (dir < 0) ypass_go<double, -1, 0>(G, B, lds, s, rv, nrve, cfg.lines_y, check_done);
-      else ypass_go<double, 1, 0>(G, B, lds, s, rv, nrve, cfg.lines_y, check_done);
+      if (dir < 0) ypass_go<double, -1, 0>(G, B, lds, s, rv, nrve, cfg.lines_y, cfg.n1max, check_done);
+      else ypass_go<double, 1, 0>(G, B, lds, s, rv, nrve, cfg.lines_y, cfg.n1max, check_done);
     }
   }
   return hipGetLastError();
@@ -753,15 +759,16 @@ hipError_t launch_ypass(int mixed, int dir, const RveDev* rv, int nrve, int tile
 hipError_t launch_xpass(int mixed, const RveDev* rv, int nrve, int tiles, const LaunchCfg& cfg, size_t lds,
                         double scale, int check_done, hipStream_t s) {
   if (tiles <= 0) return hipSuccess;
-  DISPATCH_TB(xpass_go, dim3(tiles), dim3(cfg.threads_x), lds, s, rv, nrve, cfg.lines_x, scale, check_done);
+  DISPATCH_TB(xpass_go, dim3(tiles), dim3(cfg.threads_x), lds, s, rv, nrve, cfg.lines_x, cfg.n0max, scale,
+              check_done);
   return hipGetLastError();
 }
 
 hipError_t launch_zinv(int mixed, const RveDev* rv, int nrve, int tiles, const LaunchCfg& cfg, size_t lds,
                        int out_mode, int out_role, int check_done, hipStream_t s) {
   if (tiles <= 0) return hipSuccess;
-  DISPATCH_TB(zinv_go, dim3(tiles), dim3(cfg.threads_z), lds, s, rv, nrve, cfg.rows_per_tile, out_mode, out_role,
-              check_done);
+  DISPATCH_TB(zinv_go, dim3(tiles), dim3(cfg.threads_z), lds, s, rv, nrve, cfg.rows_per_tile, cfg.n2max, out_mode,
+              out_role, check_done);
   return hipGetLastError();
 }
 

@@ -326,6 +326,9 @@ static LaunchCfg choose_cfg(const GridSum& gs) {
   c.vec_per_tile = (int)((v + 63) / 64 * 64);
   c.threads_v = std::min(256, c.vec_per_tile);
   c.big_radix = gs.big;
+  c.n0max = gs.n0;
+  c.n1max = gs.n1;
+  c.n2max = gs.n2;
   return c;
 }
 
@@ -824,7 +827,11 @@ static fftg_status group_increment(Group& g, const double* dE_tensor, const int*
     if (!any || it >= max_newton) break;
     const bool pred_step = predictor && it == 0;
     const int force = lockstep ? lockstep[it] : -1;
-    HIP_TRY(launch_cg_setup(g.d, nr, eta2, floor2, o.max_cg, force, g.stream));
+    // A right-hand side evaluated with the FP32 product (the mixed-mode
+    // predictor) is only known to FP32 rounding of s = C_last:dE, so its
+    // floor is mixed_cg_floor ||s|| instead of rhs_floor ||s||.
+    const double fl2 = (pred_step && g.mixed) ? o.mixed_cg_floor * o.mixed_cg_floor : floor2;
+    HIP_TRY(launch_cg_setup(g.d, nr, eta2, fl2, o.max_cg, force, g.stream));
     if (pred_step) {
       // G C_last dE: constant input, CURRENT tangent, FP64 or mixed apply
       st = enqueue_apply(g, g.mixed, IN_CONST_DE, R_P, TAN_CURRENT, 1, OUT_RESIDUAL, R_R, -1.0, 0);

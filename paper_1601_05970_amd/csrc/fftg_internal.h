@@ -18,6 +18,7 @@ namespace fftg {
 constexpr int kMaxStages = 8;
 constexpr int kMaxPhases = 16;
 constexpr int kMaxAxisLen = 1024;
+constexpr int kRedGroups = 32;   // first-level counters of a tile reduction
 
 template <class T>
 struct cx {
@@ -57,7 +58,8 @@ struct CgState {
   double Sigma[6];
   int iters, done, force, max_iter, status;
   int pad_;
-  unsigned int counter[8];
+  unsigned int counter[8];             // per reduction slot: groups finished
+  unsigned int sub[8][kRedGroups];     // per reduction slot and group: tiles finished
 };
 
 enum CgStatus { CG_RUNNING = 0, CG_CONVERGED = 1, CG_MAXITER = 2, CG_BREAKDOWN = 3, CG_FORCED = 4 };
@@ -86,6 +88,7 @@ struct RveDev {
   double dE[6];              // load increment, Mandel
   int tiles[P_NPASS];        // tiles of each pass for this RVE
   int skip;                  // 1: RVE masked out of batched launches
+  int xcd_remap;             // (first descriptor of a launch) spread tiles XCD-contiguously
 };
 
 // Apply modes (kernel flags)

@@ -26,8 +26,17 @@ namespace fftg {
 constexpr double kSqrt2 = 1.41421356237309504880;
 
 // ------------------------------------------------------------------ helpers
+// Workgroups are dispatched round-robin over the 8 XCDs (each with its own
+// L2).  The bijection below hands XCD x a contiguous range of tiles, so
+// neighbouring tiles that share cache lines are served by one L2.
+__device__ __forceinline__ int xcd_tile(int b, int n) {
+  const int q = n >> 3, r = n & 7;
+  const int x = b & 7, i = b >> 3;
+  return x * q + min(x, r) + i;
+}
+
 __device__ __forceinline__ int find_rve(const RveDev* __restrict__ rv, int nrve, int pass, int& tile) {
-  int b = blockIdx.x;
+  int b = rv[0].xcd_remap ? xcd_tile(blockIdx.x, gridDim.x) : (int)blockIdx.x;
   for (int r = 0; r < nrve; ++r) {
     const int n = rv[r].tiles[pass];
     if (b < n) {
@@ -58,28 +67,47 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
 
 // Publishes this tile's partial sums (nv values, in thread 0) and returns
 // true in every thread of the tile that finished last; that tile then sees
-// the totals in out[] (thread 0 only).  Sum order is fixed: tile 0, 1, ...
+// the totals in out[] (thread 0 only).  Completion is counted in two levels
+// (kRedGroups group counters, then one slot counter) to spread the atomic
+// traffic.  Sum order is fixed (tile 0, 1, ... in an unrolled strided
+// pattern), so the result does not depend on which tile finishes last.
 __device__ bool reduce_tiles(const double* vals, int nv, double* partial, int ntiles, int tile,
-                             unsigned int* counter, double* sh, double* out) {
+                             unsigned int* counter, unsigned int* sub, double* sh, double* out) {
   __shared__ int s_last;
   if (threadIdx.x == 0) {
     for (int i = 0; i < nv; ++i) partial[i * ntiles + tile] = vals[i];
     __threadfence();
-    const unsigned int t = atomicAdd(counter, 1u);
-    s_last = (t == (unsigned int)(ntiles - 1));
+    const int g = tile % kRedGroups;
+    const int gsize = ntiles / kRedGroups + (g < ntiles % kRedGroups ? 1 : 0);
+    const int ngroups = ntiles < kRedGroups ? ntiles : kRedGroups;
+    int last = 0;
+    if (atomicAdd(&sub[g], 1u) == (unsigned int)(gsize - 1)) {
+      __threadfence();
+      last = atomicAdd(counter, 1u) == (unsigned int)(ngroups - 1);
+    }
+    s_last = last;
   }
   __syncthreads();
   const bool last = s_last;
   if (!last) return false;
   __threadfence();  // acquire: the other tiles' partials are visible below
   for (int i = 0; i < nv; ++i) {
-    double acc = 0.0;
     const double* pp = partial + i * ntiles;
-    for (int t = threadIdx.x; t < ntiles; t += blockDim.x) acc += pp[t];
-    const double s = block_sum(acc, sh);
+    const int st = blockDim.x;
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    int t = threadIdx.x;
+    for (; t + 3 * st < ntiles; t += 4 * st) {
+      a0 += pp[t];
+      a1 += pp[t + st];
+      a2 += pp[t + 2 * st];
+      a3 += pp[t + 3 * st];
+    }
+    for (; t < ntiles; t += st) a0 += pp[t];
+    const double s = block_sum((a0 + a1) + (a2 + a3), sh);
     if (threadIdx.x == 0) out[i] = s;
   }
   if (threadIdx.x == 0) *counter = 0u;
+  for (int g = threadIdx.x; g < kRedGroups; g += blockDim.x) sub[g] = 0u;
   return true;
 }
 
@@ -237,7 +265,7 @@ __global__ void __launch_bounds__(256) k_zfwd(const RveDev* __restrict__ rvs, in
   if (want_norm) {
     const double s = block_sum(nrm, L.red);
     double tot;
-    if (reduce_tiles(&s, 1, rv.partial, rv.tiles[P_ZF], tile, &rv.cg->counter[0], L.red, &tot)) {
+    if (reduce_tiles(&s, 1, rv.partial, rv.tiles[P_ZF], tile, &rv.cg->counter[0], rv.cg->sub[0], L.red, &tot)) {
       if (threadIdx.x == 0) rv.cg->snorm2 = tot;
     }
   }
@@ -437,7 +465,7 @@ __global__ void __launch_bounds__(256) k_zinv(const RveDev* __restrict__ rvs, in
   }
   const double s = block_sum(dot, L.red);
   double tot;
-  if (reduce_tiles(&s, 1, rv.partial, rv.tiles[P_ZI], tile, &rv.cg->counter[1], L.red, &tot)) {
+  if (reduce_tiles(&s, 1, rv.partial, rv.tiles[P_ZI], tile, &rv.cg->counter[1], rv.cg->sub[1], L.red, &tot)) {
     if (threadIdx.x == 0) {
       CgState* cg = rv.cg;
       if (out_mode == OUT_CG) {
@@ -479,25 +507,34 @@ __global__ void __launch_bounds__(256) k_cg_xr(const RveDev* __restrict__ rvs, i
   if (rv.skip || rv.cg->done) return;
   const long long nvox = rv.nvox;
   const double alpha = rv.cg->alpha;
-  double* x = (double*)rv.buf[R_X];
-  double* r = (double*)rv.buf[R_R];
-  const double* p = (const double*)rv.buf[R_P];
-  const AT* ap = (const AT*)rv.buf[R_AP];
+  double* __restrict__ x = (double*)rv.buf[R_X];
+  double* __restrict__ r = (double*)rv.buf[R_R];
+  const double* __restrict__ p = (const double*)rv.buf[R_P];
+  const AT* __restrict__ ap = (const AT*)rv.buf[R_AP];
   const long long v0 = (long long)tile * vox_per_tile;
   const int nv = (int)min((long long)vox_per_tile, nvox - v0);
   double acc = 0.0;
-  for (int c = 0; c < 6; ++c) {
-    const long long o = c * nvox + v0;
-    for (int t = threadIdx.x; t < nv; t += blockDim.x) {
-      x[o + t] += alpha * p[o + t];
-      const double rn = r[o + t] - alpha * double(ap[o + t]);
-      r[o + t] = rn;
+  for (int t = threadIdx.x; t < nv; t += blockDim.x) {
+    const long long v = v0 + t;
+    double xv[6], rv6[6], pv[6], av[6];
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+      xv[c] = x[c * nvox + v];
+      rv6[c] = r[c * nvox + v];
+      pv[c] = p[c * nvox + v];
+      av[c] = double(ap[c * nvox + v]);
+    }
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+      const double rn = rv6[c] - alpha * av[c];
+      x[c * nvox + v] = xv[c] + alpha * pv[c];
+      r[c * nvox + v] = rn;
       acc += rn * rn;
     }
   }
   const double s = block_sum(acc, red);
   double tot;
-  if (reduce_tiles(&s, 1, rv.partial, rv.tiles[P_VEC], tile, &rv.cg->counter[2], red, &tot)) {
+  if (reduce_tiles(&s, 1, rv.partial, rv.tiles[P_VEC], tile, &rv.cg->counter[2], rv.cg->sub[2], red, &tot)) {
     if (threadIdx.x == 0) {
       CgState* cg = rv.cg;
       cg->iters += 1;
@@ -532,22 +569,28 @@ __global__ void __launch_bounds__(256) k_newton_update(const RveDev* __restrict_
   const RveDev& rv = rvs[ri];
   if (rv.skip) return;
   const long long nvox = rv.nvox;
-  double* e = (double*)rv.buf[R_EPS_FL];
-  const double* x = (const double*)rv.buf[R_X];
+  double* __restrict__ e = (double*)rv.buf[R_EPS_FL];
+  const double* __restrict__ x = (const double*)rv.buf[R_X];
   const long long v0 = (long long)tile * vox_per_tile;
   const int nv = (int)min((long long)vox_per_tile, nvox - v0);
   double acc = 0.0;
-  for (int c = 0; c < 6; ++c) {
-    const long long o = c * nvox + v0;
-    for (int t = threadIdx.x; t < nv; t += blockDim.x) {
-      const double d = x[o + t];
-      e[o + t] += d;
-      acc += d * d;
+  for (int t = threadIdx.x; t < nv; t += blockDim.x) {
+    const long long v = v0 + t;
+    double dv[6], ev[6];
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+      dv[c] = x[c * nvox + v];
+      ev[c] = e[c * nvox + v];
+    }
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+      e[c * nvox + v] = ev[c] + dv[c];
+      acc += dv[c] * dv[c];
     }
   }
   const double s = block_sum(acc, red);
   double tot;
-  if (reduce_tiles(&s, 1, rv.partial, rv.tiles[P_VEC], tile, &rv.cg->counter[3], red, &tot)) {
+  if (reduce_tiles(&s, 1, rv.partial, rv.tiles[P_VEC], tile, &rv.cg->counter[3], rv.cg->sub[3], red, &tot)) {
     if (threadIdx.x == 0) rv.cg->dnorm2 = tot;
   }
 }
@@ -640,7 +683,7 @@ __global__ void __launch_bounds__(256) k_constitutive(const RveDev* __restrict__
     double s[6];
     for (int c = 0; c < 6; ++c) s[c] = block_sum(ssum[c], red);
     double tot[6];
-    if (reduce_tiles(s, 6, rv.partial, rv.tiles[P_VEC], tile, &rv.cg->counter[4], red, tot)) {
+    if (reduce_tiles(s, 6, rv.partial, rv.tiles[P_VEC], tile, &rv.cg->counter[4], rv.cg->sub[4], red, tot)) {
       if (threadIdx.x == 0)
         for (int c = 0; c < 6; ++c) rv.cg->Sigma[c] = tot[c] / double(nvox);
     }

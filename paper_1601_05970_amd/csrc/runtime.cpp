@@ -7,6 +7,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <string>
@@ -282,11 +283,18 @@ void fftg_options_default(fftg_options* o) {
   o->cg_chunk = 16;
 }
 
-// Tile sizes fit the FP64 passes in 64 KB of LDS (mixed plans also run the
-// FP64 residual with the same configuration).  Starting from the widest tile
-// LDS allows, tiles shrink until a launch has at least kMinTiles workgroups
-// (the chip has 256 CUs), so small RVEs still spread over the device.
-static const int kMinTiles = 2048;
+// Tile sizes fit the FP64 passes in an LDS budget (default 64 KB; mixed
+// plans also run the FP64 residual with the same configuration).  Starting
+// from the widest tile LDS allows, tiles shrink until a launch has at least
+// min_tiles workgroups (the chip has 256 CUs), so small RVEs still spread
+// over the device.  FFTG_LDS_KB and FFTG_MIN_TILES override the two knobs.
+static long env_long(const char* name, long dflt) {
+  const char* s = getenv(name);
+  if (!s || !*s) return dflt;
+  char* end = nullptr;
+  const long v = strtol(s, &end, 10);
+  return (end && *end == 0 && v > 0) ? v : dflt;
+}
 
 static int threads_for(long long points) {
   return points <= 192 ? 64 : (points <= 640 ? 128 : 256);
@@ -304,7 +312,8 @@ struct GridSum {
 
 static LaunchCfg choose_cfg(const GridSum& gs) {
   LaunchCfg c;
-  const size_t budget = 64 * 1024;
+  const size_t budget = (size_t)env_long("FFTG_LDS_KB", 64) * 1024;
+  const long long kMinTiles = env_long("FFTG_MIN_TILES", 2048);
   const long long H = gs.hmax;
   int R = 8;
   while (R > 1 && lds_z(0, R, gs.n2) > budget) --R;
@@ -599,7 +608,8 @@ struct Group {
   int mixed;
   hipStream_t stream;
   LaunchCfg cfg;
-  size_t lds_zf, lds_y, lds_x;
+  size_t lds_zf, lds_y, lds_x;          // FP64 launches
+  size_t lds_zf32, lds_y32, lds_x32;    // FP32 launches
   int total[P_NPASS];
   std::vector<RveDev> h;         // host copies
   RveDev* d;                     // device array
@@ -612,6 +622,7 @@ struct Group {
   std::vector<fftg_history> hists;
   bool own;                      // device arrays owned by the group
   double active_vox;             // voxels of the members not skipped
+  int xcd_remap;
 };
 
 static void fill_desc(RveDev& rv, fftg_plan pl, fftg_history h, const LaunchCfg& cfg) {
@@ -663,6 +674,10 @@ static void group_config(Group& g) {
   g.lds_zf = lds_z(0, g.cfg.rows_per_tile, n2);
   g.lds_y = lds_y(0, g.cfg.lines_y, n1);
   g.lds_x = lds_x(0, g.cfg.lines_x, n0);
+  g.lds_zf32 = lds_z(1, g.cfg.rows_per_tile, n2);
+  g.lds_y32 = lds_y(1, g.cfg.lines_y, n1);
+  g.lds_x32 = lds_x(1, g.cfg.lines_x, n0);
+  g.xcd_remap = (int)env_long("FFTG_XCD_REMAP", 1) == 1;
 }
 
 static void group_totals(Group& g) {
@@ -690,6 +705,7 @@ static fftg_status group_upload(Group& g) {
   g.next = (g.next + 1) & 3;
   HIP_TRY(hipEventSynchronize(g.ev[slot]));
   RveDev* st = g.h_pinned + slot * n;
+  for (size_t i = 0; i < n; ++i) g.h[i].xcd_remap = g.xcd_remap;
   memcpy(st, g.h.data(), n * sizeof(RveDev));
   HIP_TRY(hipMemcpyAsync(g.d, st, n * sizeof(RveDev), hipMemcpyHostToDevice, g.stream));
   HIP_TRY(hipEventRecord(g.ev[slot], g.stream));
@@ -714,15 +730,14 @@ static void set_skip(Group& g, size_t i, bool skip) {
 static fftg_status enqueue_apply(Group& g, int mixed, int in_mode, int in_role, int tan_mode, int want_norm,
                                  int out_mode, int out_role, double scale, int check_done, int update_p = 0) {
   const int nr = (int)g.h.size();
-  PROF_LAUNCH(FFTG_KERNEL_ZFWD, launch_zfwd(mixed, g.d, nr, g.total[P_ZF], g.cfg, g.lds_zf, in_mode, in_role,
-                                            tan_mode, want_norm, check_done, update_p, g.stream));
-  PROF_LAUNCH(FFTG_KERNEL_Y_FWD,
-              launch_ypass(mixed, -1, g.d, nr, g.total[P_Y], g.cfg, g.lds_y, check_done, g.stream));
-  PROF_LAUNCH(FFTG_KERNEL_X_PROJ,
-              launch_xpass(mixed, g.d, nr, g.total[P_X], g.cfg, g.lds_x, scale, check_done, g.stream));
-  PROF_LAUNCH(FFTG_KERNEL_Y_INV,
-              launch_ypass(mixed, 1, g.d, nr, g.total[P_Y], g.cfg, g.lds_y, check_done, g.stream));
-  PROF_LAUNCH(FFTG_KERNEL_ZINV, launch_zinv(mixed, g.d, nr, g.total[P_ZI], g.cfg, g.lds_zf, out_mode, out_role,
+  const size_t lz = mixed ? g.lds_zf32 : g.lds_zf, ly = mixed ? g.lds_y32 : g.lds_y;
+  const size_t lx = mixed ? g.lds_x32 : g.lds_x;
+  PROF_LAUNCH(FFTG_KERNEL_ZFWD, launch_zfwd(mixed, g.d, nr, g.total[P_ZF], g.cfg, lz, in_mode, in_role, tan_mode,
+                                            want_norm, check_done, update_p, g.stream));
+  PROF_LAUNCH(FFTG_KERNEL_Y_FWD, launch_ypass(mixed, -1, g.d, nr, g.total[P_Y], g.cfg, ly, check_done, g.stream));
+  PROF_LAUNCH(FFTG_KERNEL_X_PROJ, launch_xpass(mixed, g.d, nr, g.total[P_X], g.cfg, lx, scale, check_done, g.stream));
+  PROF_LAUNCH(FFTG_KERNEL_Y_INV, launch_ypass(mixed, 1, g.d, nr, g.total[P_Y], g.cfg, ly, check_done, g.stream));
+  PROF_LAUNCH(FFTG_KERNEL_ZINV, launch_zinv(mixed, g.d, nr, g.total[P_ZI], g.cfg, lz, out_mode, out_role,
                                             check_done, g.stream));
   return FFTG_OK;
 }

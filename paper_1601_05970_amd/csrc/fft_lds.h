@@ -35,6 +35,22 @@ __device__ __forceinline__ cx<T> mul_si(cx<T> a) {
   return S > 0 ? cx<T>{-a.im, a.re} : cx<T>{a.im, -a.re};
 }
 
+// Integer division by a workgroup-uniform divisor through the FP32
+// reciprocal, exact for 0 <= t < 2^22: the float quotient is off by at most
+// one and a single remainder test corrects it.
+struct FastDiv {
+  float inv;
+  int d;
+  __device__ __forceinline__ explicit FastDiv(int d_) : inv(1.0f / (float)d_), d(d_) {}
+  __device__ __forceinline__ int div(int t) const {
+    int q = (int)((float)t * inv);
+    const int r = t - q * d;
+    q += (r >= d) ? 1 : 0;
+    q -= (r < 0) ? 1 : 0;
+    return q;
+  }
+};
+
 // Direct DFT of R points in registers: X_k = sum_n v_n exp(DIR 2 pi i n k / R).
 template <int R, int DIR, class T>
 struct Dft {
@@ -103,10 +119,11 @@ __device__ __forceinline__ void stockham_stage(const cx<T>* __restrict__ src, cx
   const int nb = M / R;
   const int total = nb * nl;
   const int tstep = M / (Ns * R);
+  const FastDiv fnb(nb), fns(Ns);
   for (int t = threadIdx.x; t < total; t += blockDim.x) {
-    const int line = t / nb;
+    const int line = fnb.div(t);
     const int j = t - line * nb;
-    const int k = j % Ns;
+    const int k = j - fns.div(j) * Ns;
     const cx<T>* s = src + line * ld + j;
     cx<T> v[R];
 #pragma unroll
@@ -235,8 +252,9 @@ __device__ cx<T>* line_fft(cx<T>* line, cx<T>* scratch, int ld, int nl, const Ax
   }
   const int M = P.M;
   const int total = nl * M;
+  const FastDiv fm(M);
   for (int t = threadIdx.x; t < total; t += blockDim.x) {
-    const int l = t / M;
+    const int l = fm.div(t);
     const int q = t - l * M;
     scratch[l * ld + q] = line[l * ld + P.pin[q]];
   }
@@ -246,7 +264,7 @@ __device__ cx<T>* line_fft(cx<T>* line, cx<T>* scratch, int ld, int nl, const Ax
   run_chain<-1, T, BIG>(a, b, ld, nl, P);
   const cx<T>* bh = DIR < 0 ? P.bf : P.bi;
   for (int t = threadIdx.x; t < total; t += blockDim.x) {
-    const int l = t / M;
+    const int l = fm.div(t);
     const int q = t - l * M;
     const cx<T> v = a[l * ld + q];
     if (q == 0) dc[l] = v;
@@ -256,7 +274,7 @@ __device__ cx<T>* line_fft(cx<T>* line, cx<T>* scratch, int ld, int nl, const Ax
   run_chain<1, T, BIG>(a, b, ld, nl, P);
   // a == scratch here (2 * nst swaps); scatter back, x_0 still in line[0]
   for (int t = threadIdx.x; t < total; t += blockDim.x) {
-    const int l = t / M;
+    const int l = fm.div(t);
     const int m = t - l * M;
     line[l * ld + P.pout[m]] = cadd(line[l * ld], a[l * ld + m]);
   }

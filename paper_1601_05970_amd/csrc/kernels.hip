@@ -203,8 +203,9 @@ __global__ void __launch_bounds__(256) k_zfwd(const RveDev* __restrict__ rvs, in
   const double* rres = (const double*)rv.buf[R_R];
   double* pw = (double*)rv.buf[R_P];
   double nrm = 0.0;
+  const FastDiv fn2(n2), fH(H), f3(3);
   for (int t = threadIdx.x; t < nrows * n2; t += blockDim.x) {
-    const int r = t / n2;
+    const int r = fn2.div(t);
     const int z = t - r * n2;
     const long long v = (long long)(row0 + r) * n2 + z;
     T p[6], tau[6];
@@ -251,9 +252,9 @@ __global__ void __launch_bounds__(256) k_zfwd(const RveDev* __restrict__ rvs, in
   // untangle two real transforms: A_k = (Z_k + conj Z_-k)/2, B_k = (Z_k - conj Z_-k)/(2i)
   cx<T>* spec = (cx<T>*)rv.spec;
   for (int t = threadIdx.x; t < nrows * 3 * H; t += blockDim.x) {
-    const int rp = t / H;
+    const int rp = fH.div(t);
     const int k = t - rp * H;
-    const int r = rp / 3, pr = rp - 3 * r;
+    const int r = f3.div(rp), pr = rp - 3 * r;
     const cx<T> zk = res[rp * ld + k];
     const cx<T> zm = res[rp * ld + (k == 0 ? 0 : n2 - k)];
     const cx<T> A = {T(0.5) * (zk.re + zm.re), T(0.5) * (zk.im - zm.im)};
@@ -291,15 +292,16 @@ __global__ void __launch_bounds__(256) k_ypass(const RveDev* __restrict__ rvs, i
   const int ld = n1;
   TileLds<T> L(smem, lines_per_tile, ld, *rv.ax[1], ldmax);
   cx<T>* base = (cx<T>*)rv.spec + c * rv.nspec + (long long)i0 * n1 * H + h0;
+  const FastDiv fnh(nh);
   for (int t = threadIdx.x; t < n1 * nh; t += blockDim.x) {
-    const int y = t / nh;
+    const int y = fnh.div(t);
     const int hh = t - y * nh;
     L.line[hh * ld + y] = base[(long long)y * H + hh];
   }
   __syncthreads();
   cx<T>* res = line_fft<DIR, T, BIG>(L.line, L.scratch, ld, nh, L.ax, L.dc);
   for (int t = threadIdx.x; t < n1 * nh; t += blockDim.x) {
-    const int y = t / nh;
+    const int y = fnh.div(t);
     const int hh = t - y * nh;
     base[(long long)y * H + hh] = res[hh * ld + y];
   }
@@ -327,10 +329,11 @@ __global__ void __launch_bounds__(256) k_xpass(const RveDev* __restrict__ rvs, i
   cx<T>* spec = (cx<T>*)rv.spec;
   const long long rs = (long long)n1 * H;
   const long long off = (long long)i1 * H + h0;
+  const FastDiv fxn(n0 * nh), fnh(nh);
   for (int t = threadIdx.x; t < 6 * n0 * nh; t += blockDim.x) {
-    const int cx_ = t / (n0 * nh);
+    const int cx_ = fxn.div(t);
     const int r = t - cx_ * n0 * nh;
-    const int x = r / nh;
+    const int x = fnh.div(r);
     const int hh = r - x * nh;
     L.line[(cx_ * nh + hh) * ld + x] = spec[cx_ * nspec + x * rs + off + hh];
   }
@@ -341,7 +344,7 @@ __global__ void __launch_bounds__(256) k_xpass(const RveDev* __restrict__ rvs, i
   const T scale = T(scale_in / double(rv.nvox));   // inverse DFT normalisation 1/|N|
   const double k1 = double(sfreq(i1, n1)) / double(n1);
   for (int t = threadIdx.x; t < n0 * nh; t += blockDim.x) {
-    const int x = t / nh;
+    const int x = fnh.div(t);
     const int hh = t - x * nh;
     const double k0 = double(sfreq(x, n0)) / double(n0);
     const double k2 = double(h0 + hh) / double(n2);
@@ -362,9 +365,9 @@ __global__ void __launch_bounds__(256) k_xpass(const RveDev* __restrict__ rvs, i
   __syncthreads();
   cx<T>* res2 = line_fft<1, T, BIG>(res, oth, ld, nl, L.ax, L.dc);
   for (int t = threadIdx.x; t < 6 * n0 * nh; t += blockDim.x) {
-    const int cx_ = t / (n0 * nh);
+    const int cx_ = fxn.div(t);
     const int r = t - cx_ * n0 * nh;
-    const int x = r / nh;
+    const int x = fnh.div(r);
     const int hh = r - x * nh;
     spec[cx_ * nspec + x * rs + off + hh] = res2[(cx_ * nh + hh) * ld + x];
   }
@@ -389,10 +392,11 @@ __global__ void __launch_bounds__(256) k_zinv(const RveDev* __restrict__ rvs, in
   TileLds<T> L(smem, 3 * rows_per_tile, ld, *rv.ax[2], ldmax);
   const cx<T>* spec = (const cx<T>*)rv.spec;
   // Z_k = A_k + i B_k, Z_{n-k} = conj(A_k) + i conj(B_k)
+  const FastDiv fn2(n2), f3(3);
   for (int t = threadIdx.x; t < nrows * 3 * n2; t += blockDim.x) {
-    const int rp = t / n2;
+    const int rp = fn2.div(t);
     const int z = t - rp * n2;
-    const int r = rp / 3, pr = rp - 3 * r;
+    const int r = f3.div(rp), pr = rp - 3 * r;
     const long long rowo = (long long)(row0 + r) * H;
     cx<T> Z;
     if (z < H) {
@@ -415,7 +419,7 @@ __global__ void __launch_bounds__(256) k_zinv(const RveDev* __restrict__ rvs, in
     AT* out = (AT*)rv.buf[R_AP];
     const double* p = (const double*)rv.buf[R_P];
     for (int t = threadIdx.x; t < nrows * n2; t += blockDim.x) {
-      const int r = t / n2;
+      const int r = fn2.div(t);
       const int z = t - r * n2;
       const long long v = (long long)(row0 + r) * n2 + z;
 #pragma unroll
@@ -432,7 +436,7 @@ __global__ void __launch_bounds__(256) k_zinv(const RveDev* __restrict__ rvs, in
     double* pp = (double*)rv.buf[R_P];
     double* xx = (double*)rv.buf[R_X];
     for (int t = threadIdx.x; t < nrows * n2; t += blockDim.x) {
-      const int r = t / n2;
+      const int r = fn2.div(t);
       const int z = t - r * n2;
       const long long v = (long long)(row0 + r) * n2 + z;
 #pragma unroll
@@ -451,7 +455,7 @@ __global__ void __launch_bounds__(256) k_zinv(const RveDev* __restrict__ rvs, in
   } else {
     T* out = (T*)rv.buf[out_role];
     for (int t = threadIdx.x; t < nrows * n2; t += blockDim.x) {
-      const int r = t / n2;
+      const int r = fn2.div(t);
       const int z = t - r * n2;
       const long long v = (long long)(row0 + r) * n2 + z;
 #pragma unroll

@@ -52,60 +52,81 @@ struct FastDiv {
 };
 
 // Direct DFT of R points in registers: X_k = sum_n v_n exp(DIR 2 pi i n k / R).
+// run_store hands each output to st(k, X_k) as soon as it is formed, so the
+// codelet never holds inputs and outputs at the same time.
 template <int R, int DIR, class T>
 struct Dft {
-  // odd R: pair n and R-n, X_k = A_k + DIR i B_k, X_{R-k} = A_k - DIR i B_k
-  __device__ __forceinline__ static void run(cx<T>* v) {
+  // odd R: with s_j = v_j + v_{R-j}, d_j = v_j - v_{R-j} (formed in place),
+  // X_k = A_k + DIR i B_k and X_{R-k} = A_k - DIR i B_k, where
+  // A_k = v_0 + sum_j s_j cos(2 pi jk/R), B_k = sum_j d_j sin(2 pi jk/R).
+  template <class S>
+  __device__ __forceinline__ static void run_store(cx<T>* v, S&& st) {
     constexpr int m = (R - 1) / 2;
-    cx<T> s[m + 1], d[m + 1];
 #pragma unroll
     for (int j = 1; j <= m; ++j) {
-      s[j] = cadd(v[j], v[R - j]);
-      d[j] = csub(v[j], v[R - j]);
+      const cx<T> a = v[j], b = v[R - j];
+      v[j] = cadd(a, b);
+      v[R - j] = csub(a, b);
     }
     cx<T> x0 = v[0];
 #pragma unroll
-    for (int j = 1; j <= m; ++j) x0 = cadd(x0, s[j]);
+    for (int j = 1; j <= m; ++j) x0 = cadd(x0, v[j]);
+    st(0, x0);
+    if constexpr (R <= 9) {
 #pragma unroll
-    for (int k = 1; k <= m; ++k) {
-      cx<T> A = v[0];
-      cx<T> B = {T(0), T(0)};
-#pragma unroll
-      for (int j = 1; j <= m; ++j) {
-        const T c = T(RadixConst<R>::c[(j * k) % R]);
-        const T sn = T(RadixConst<R>::s[(j * k) % R]);
-        A.re += s[j].re * c;
-        A.im += s[j].im * c;
-        B.re += d[j].re * sn;
-        B.im += d[j].im * sn;
-      }
-      const cx<T> iB = mul_si<DIR>(B);
-      v[k] = cadd(A, iB);
-      v[R - k] = csub(A, iB);
+      for (int k = 1; k <= m; ++k) one_pair(v, k, k, st);
+    } else {
+      // large radices: the k loop stays rolled (constants by uniform index)
+      // so that the unrolled body, and the register footprint, stay small
+#pragma unroll 1
+      for (int k = 1; k <= m; ++k) one_pair(v, k, k, st);
     }
-    v[0] = x0;
+  }
+
+  template <class S>
+  __device__ __forceinline__ static void one_pair(const cx<T>* v, int k, int, S&& st) {
+    constexpr int m = (R - 1) / 2;
+    cx<T> A = v[0];
+    cx<T> B = {T(0), T(0)};
+    int jk = 0;
+#pragma unroll
+    for (int j = 1; j <= m; ++j) {
+      jk += k;
+      if (jk >= R) jk -= R;   // (j k) mod R
+      const T c = T(RadixConst<R>::c[jk]);
+      const T sn = T(RadixConst<R>::s[jk]);
+      A.re += v[j].re * c;
+      A.im += v[j].im * c;
+      B.re += v[R - j].re * sn;
+      B.im += v[R - j].im * sn;
+    }
+    const cx<T> iB = mul_si<DIR>(B);
+    st(k, cadd(A, iB));
+    st(R - k, csub(A, iB));
   }
 };
 
 template <int DIR, class T>
 struct Dft<2, DIR, T> {
-  __device__ __forceinline__ static void run(cx<T>* v) {
+  template <class S>
+  __device__ __forceinline__ static void run_store(cx<T>* v, S&& st) {
     const cx<T> a = v[0], b = v[1];
-    v[0] = cadd(a, b);
-    v[1] = csub(a, b);
+    st(0, cadd(a, b));
+    st(1, csub(a, b));
   }
 };
 
 template <int DIR, class T>
 struct Dft<4, DIR, T> {
-  __device__ __forceinline__ static void run(cx<T>* v) {
+  template <class S>
+  __device__ __forceinline__ static void run_store(cx<T>* v, S&& st) {
     const cx<T> s02 = cadd(v[0], v[2]), d02 = csub(v[0], v[2]);
     const cx<T> s13 = cadd(v[1], v[3]), d13 = csub(v[1], v[3]);
     const cx<T> t = mul_si<DIR>(d13);
-    v[0] = cadd(s02, s13);
-    v[2] = csub(s02, s13);
-    v[1] = cadd(d02, t);
-    v[3] = csub(d02, t);
+    st(0, cadd(s02, s13));
+    st(2, csub(s02, s13));
+    st(1, cadd(d02, t));
+    st(3, csub(d02, t));
   }
 };
 
@@ -136,10 +157,8 @@ __device__ __forceinline__ void stockham_stage(const cx<T>* __restrict__ src, cx
         v[q] = cmul(v[q], w);
       }
     }
-    Dft<R, DIR, T>::run(v);
     cx<T>* d = dst + line * ld + (j - k) * R + k;
-#pragma unroll
-    for (int q = 0; q < R; ++q) d[q * Ns] = v[q];
+    Dft<R, DIR, T>::run_store(v, [&](int q, cx<T> x) { d[q * Ns] = x; });
   }
 }
 
@@ -165,8 +184,8 @@ __device__ __forceinline__ const cx<float>* rader_bhat<float>(const AxisDev& P, 
 // barrier-separated stages never wait on global memory.
 template <class T>
 struct AxisLds {
+  const AxisDev* dev;  // sizes and radices (uniform loads)
   int M, nst, rader;
-  int radix[kMaxStages];
   cx<T>* tw;     // M roots exp(-2 pi i m / M)
   int* pin;      // Rader permutations (M each)
   int* pout;
@@ -184,11 +203,10 @@ __host__ __device__ constexpr size_t axis_lds_bytes(int N) {
 // caller's next __syncthreads publishes them).
 template <class T>
 __device__ void load_axis_lds(const AxisDev& P, char* base, AxisLds<T>& A) {
+  A.dev = &P;
   A.M = P.M;
   A.nst = P.nst;
   A.rader = P.rader;
-#pragma unroll
-  for (int s = 0; s < kMaxStages; ++s) A.radix[s] = P.radix[s];
   const int N = P.N;
   A.tw = reinterpret_cast<cx<T>*>(base);
   A.bf = A.tw + N;
@@ -217,7 +235,7 @@ __device__ void run_chain(cx<T>*& a, cx<T>*& b, int ld, int nl, const AxisLds<T>
   const cx<T>* tw = P.tw;
   int Ns = 1;
   for (int s = 0; s < P.nst; ++s) {
-    const int R = P.radix[s];
+    const int R = P.dev->radix[s];
     switch (R) {
       case 2: stockham_stage<2, DIR, T>(a, b, ld, nl, P.M, Ns, tw); break;
       case 3: stockham_stage<3, DIR, T>(a, b, ld, nl, P.M, Ns, tw); break;

@@ -89,6 +89,12 @@ def main():
     ap.add_argument("--workload", default="random_31")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--profile-kernel", type=int, default=2, help="fftg_kernel_id timed for the roofline")
+    ap.add_argument("--also", default="batch64_fp64,batch64_mixed",
+                    help="extra workloads timed after the main one (1 warmup + 1 step each); '' for none")
+    ap.add_argument("--max-increments", type=int, default=0,
+                    help="profiling runs only: stop each solve after this many increments")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="only run a device copy of MIB MiB 10 times (HBM counter calibration) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}): the solve of one RVE is not sharded "
@@ -98,8 +104,43 @@ def main():
     import torch
     from paper_1601_05970_amd import fftg
 
-    ws = workload(args.workload)
-    desc = WORKLOADS[args.workload]
+    if args.calibrate_copy:
+        n = args.calibrate_copy * (1 << 20) // 8
+        src = torch.ones(n, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(10):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_per_launch_read": n * 8, "copy_bytes_per_launch_write": n * 8, "launches": 10}))
+        return
+
+    result = measure(fftg, torch, args.workload, args.steps, args.warmup, args.profile_kernel, args.max_increments)
+    out = result
+    out["n_gpus"] = 1
+    if not args.no_cpu_baseline:
+        ws = workload(args.workload)
+        out["cpu_baseline"] = cpu_baseline(ws[0] if len(ws) == 1 else max(ws, key=lambda x: x.nvox))
+    also = [a for a in args.also.split(",") if a and a != args.workload]
+    if also:
+        out["also"] = []
+        for name in also:
+            r = measure(fftg, torch, name, 1, 1, args.profile_kernel)
+            out["also"].append({"workload": r["config"]["workload"], "value": r["value"], "unit": r["unit"],
+                                "dtype": r["dtype"], "ms_per_step": r["ms_per_step"],
+                                "rves": r["config"]["rves"], "voxels": r["config"]["voxels"],
+                                "roofline_frac": r["roofline"]["frac"],
+                                "x_pass_GBs": r["roofline"]["achieved"]})
+    print(json.dumps(out))
+
+
+def measure(fftg, torch, name, steps, warmup, profile_kernel, max_inc=0):
+    """Times `steps` full solves of workload `name`; returns the bench dict."""
+    ws = workload(name)
+    if max_inc:
+        for x in ws:
+            x.E_final = x.E_final * (min(max_inc, x.n_inc) / x.n_inc)
+            x.n_inc = min(max_inc, x.n_inc)
+    desc = WORKLOADS[name]
     w = ws[0]
     opts = fftg.fftg_options_default()
     opts.tol_newton, opts.tol_cg = w.tol_newton, w.tol_cg
@@ -126,13 +167,13 @@ def main():
             h.close()
         return work
 
-    for _ in range(args.warmup):
+    for _ in range(warmup):
         step()
     torch.cuda.synchronize()
-    fftg.fftg_profiler_start(args.profile_kernel)
+    fftg.fftg_profiler_start(profile_kernel)
     t0 = time.perf_counter()
     total_work = 0.0
-    for _ in range(args.steps):
+    for _ in range(steps):
         total_work += step()
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
@@ -144,24 +185,23 @@ def main():
     avg_ms = kms / max(klaunch, 1)
     bytes_per_launch = bpv * kvox / max(klaunch, 1)
     achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else 0.0
-    out = {
+    for p in plans:
+        p.close()
+    return {
         "metric": "voxel-CG-iters/s", "value": value, "unit": "voxel-CG-iters/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * dt / args.steps,
+        "steps": steps, "warmup": warmup, "ms_per_step": 1e3 * dt / steps,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32+f64" if opts.precision == fftg.FFTG_MIXED else "f64", "data": "synthetic",
         "config": {"workload": desc, "rves": len(ws), "voxels": int(nvox.sum()),
                    "grid": list(w.shape) if len(ws) == 1 else "mixed", "increments": w.n_inc,
                    "tol_newton": w.tol_newton, "tol_cg": w.tol_cg,
-                   "voxel_cg_iters_per_step": total_work / args.steps},
+                   "voxel_cg_iters_per_step": total_work / steps},
         "roofline": {"kernel": "k_xpass (DFT x, G^(k) projection, inverse DFT x)", "bound": "hbm",
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                      "avg_launch_us": 1e3 * avg_ms, "launches": klaunch,
                      "bytes_per_launch": bytes_per_launch},
     }
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(w if len(ws) == 1 else max(ws, key=lambda x: x.nvox))
-    print(json.dumps(out))
 
 
 if __name__ == "__main__":

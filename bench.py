@@ -65,6 +65,34 @@ def x_pass_bytes_per_voxel(shape, real_bytes):
     return 2 * 6 * 2 * real_bytes * (n0 * n1 * H) / float(n0 * n1 * n2)
 
 
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("kernels.hip", "fft_lds.h", "fftg_internal.h", "radix_consts.h"):
+        with open(os.path.join(ROOT, "paper_1601_05970_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload_name):
+    """HBM bytes per k_xpass launch from the committed FETCH_SIZE/WRITE_SIZE
+    summary, or None when it covers another workload or older kernels."""
+    path = os.path.join(ROOT, "profiles", "random31_fp64_hbm_traffic.md")
+    if workload_name != "random_31" or not os.path.exists(path):
+        return None
+    kv = {}
+    for line in open(path):
+        if ":" in line and not line.startswith(("#", "|", "`")):
+            k, v = line.split(":", 1)
+            kv[k.strip()] = v.strip()
+    if kv.get("kernel_source_sha256_16") != kernel_source_hash():
+        return None
+    try:
+        return float(kv["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
 def cpu_baseline(w, budget_s=15.0):
     """The FP64 oracle on the host cores, increments 1.. until ~budget_s."""
     from oracle import solver as S
@@ -198,7 +226,7 @@ def measure(fftg, torch, name, steps, warmup, profile_kernel, max_inc=0):
                    "voxel_cg_iters_per_step": total_work / steps},
         "roofline": {"kernel": "k_xpass (DFT x, G^(k) projection, inverse DFT x)", "bound": "hbm",
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(name),
                      "avg_launch_us": 1e3 * avg_ms, "launches": klaunch,
                      "bytes_per_launch": bytes_per_launch},
     }

@@ -35,18 +35,24 @@ __device__ __forceinline__ int xcd_tile(int b, int n) {
   return x * q + min(x, r) + i;
 }
 
+// The descriptor array of a launch is followed by a prefix table of tile
+// offsets, starts[pass][r] for r = 0..nrve (members skipped from a launch
+// own no tiles); a block finds its RVE by binary search over that table.
 __device__ __forceinline__ int find_rve(const RveDev* __restrict__ rv, int nrve, int pass, int& tile) {
-  int b = rv[0].xcd_remap ? xcd_tile(blockIdx.x, gridDim.x) : (int)blockIdx.x;
-  for (int r = 0; r < nrve; ++r) {
-    const int n = rv[r].tiles[pass];
-    if (b < n) {
-      tile = b;
-      return r;
-    }
-    b -= n;
+  const int b = rv[0].xcd_remap ? xcd_tile(blockIdx.x, gridDim.x) : (int)blockIdx.x;
+  const int* __restrict__ st = reinterpret_cast<const int*>(rv + nrve) + pass * (nrve + 1);
+  if (b >= st[nrve]) {
+    tile = -1;
+    return -1;
   }
-  tile = -1;
-  return -1;
+  int lo = 0, hi = nrve;  // invariant: st[lo] <= b < st[hi]
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (st[mid] <= b) lo = mid;
+    else hi = mid;
+  }
+  tile = b - st[lo];
+  return lo;
 }
 
 // Sum over the workgroup; result valid in thread 0.

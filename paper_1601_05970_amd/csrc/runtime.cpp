@@ -236,6 +236,12 @@ static fftg_status build_axis(int N, AxisHost& ax) {
 }
 
 // ------------------------------------------------------------------- plan
+// Device bytes of a launch descriptor block: count descriptors followed by
+// the per-pass tile prefix table (P_NPASS x (count + 1) ints).
+static size_t desc_bytes(size_t count) {
+  return count * sizeof(RveDev) + (size_t)P_NPASS * (count + 1) * sizeof(int);
+}
+
 struct fftg_plan_s {
   int n[3];
   int H;
@@ -486,8 +492,8 @@ fftg_status fftg_plan_create(fftg_plan* out, int n0, int n1, int n2, const uint8
   PLAN_TRY(dalloc(pl, &pl->partial, (size_t)6 * pl->max_tiles * 8 + 64));
   PLAN_TRY(dalloc(pl, &pl->cg, sizeof(CgState)));
   PLAN_TRY(hipMemset(pl->cg, 0, sizeof(CgState)));
-  PLAN_TRY(dalloc(pl, &pl->d_rv, sizeof(RveDev)));
-  PLAN_TRY(hipHostMalloc((void**)&pl->h_stage, 4 * sizeof(RveDev), hipHostMallocDefault));
+  PLAN_TRY(dalloc(pl, (char**)&pl->d_rv, desc_bytes(1)));
+  PLAN_TRY(hipHostMalloc((void**)&pl->h_stage, 4 * desc_bytes(1), hipHostMallocDefault));
   PLAN_TRY(hipHostMalloc((void**)&pl->h_cg, sizeof(CgState), hipHostMallocDefault));
   for (int i = 0; i < 4; ++i) PLAN_TRY(hipEventCreateWithFlags(&pl->stage_ev[i], hipEventDisableTiming));
   pl->stage_next = 0;
@@ -704,10 +710,19 @@ static fftg_status group_upload(Group& g) {
   const int slot = g.next;
   g.next = (g.next + 1) & 3;
   HIP_TRY(hipEventSynchronize(g.ev[slot]));
-  RveDev* st = g.h_pinned + slot * n;
+  char* st = reinterpret_cast<char*>(g.h_pinned) + slot * desc_bytes(n);
   for (size_t i = 0; i < n; ++i) g.h[i].xcd_remap = g.xcd_remap;
   memcpy(st, g.h.data(), n * sizeof(RveDev));
-  HIP_TRY(hipMemcpyAsync(g.d, st, n * sizeof(RveDev), hipMemcpyHostToDevice, g.stream));
+  int* tab = reinterpret_cast<int*>(st + n * sizeof(RveDev));
+  for (int p = 0; p < P_NPASS; ++p) {
+    int acc = 0;
+    for (size_t i = 0; i < n; ++i) {
+      tab[p * (n + 1) + i] = acc;
+      acc += g.h[i].tiles[p];
+    }
+    tab[p * (n + 1) + n] = acc;
+  }
+  HIP_TRY(hipMemcpyAsync(g.d, st, desc_bytes(n), hipMemcpyHostToDevice, g.stream));
   HIP_TRY(hipEventRecord(g.ev[slot], g.stream));
   group_totals(g);
   return FFTG_OK;
@@ -1175,11 +1190,11 @@ fftg_status fftg_batch_create(fftg_batch* out, int count, const fftg_plan* plans
   g.h_cg = nullptr;
   g.d_cg = nullptr;
   memset(g.ev, 0, sizeof(g.ev));
-  hipError_t e = hipMalloc((void**)&g.d, count * sizeof(RveDev));
+  hipError_t e = hipMalloc((void**)&g.d, desc_bytes(count));
   if (e == hipSuccess) e = hipMalloc((void**)&g.d_cg, count * sizeof(CgState));
   if (e == hipSuccess) e = hipMemset(g.d_cg, 0, count * sizeof(CgState));
   for (int i = 0; i < count && e == hipSuccess; ++i) g.h[i].cg = g.d_cg + i;
-  if (e == hipSuccess) e = hipHostMalloc((void**)&g.h_pinned, 4 * count * sizeof(RveDev), hipHostMallocDefault);
+  if (e == hipSuccess) e = hipHostMalloc((void**)&g.h_pinned, 4 * desc_bytes(count), hipHostMallocDefault);
   if (e == hipSuccess) e = hipHostMalloc((void**)&g.h_cg, count * sizeof(CgState), hipHostMallocDefault);
   for (int i = 0; i < 4 && e == hipSuccess; ++i) e = hipEventCreateWithFlags(&g.ev[i], hipEventDisableTiming);
   if (e != hipSuccess) {

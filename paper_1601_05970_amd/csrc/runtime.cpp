@@ -267,6 +267,8 @@ struct fftg_plan_s {
   CgState* h_cg;      // pinned
   int max_tiles;
   int big_radix;      // an axis uses the radix-11/13/17 codelets
+  int tuned;          // cfg holds the autotuned launch configuration
+  LaunchCfg cfg;
 };
 
 struct fftg_history_s {
@@ -336,10 +338,11 @@ static LaunchCfg choose_cfg(const GridSum& gs) {
   while (Lx > 1 && gs.xl * ((H + Lx - 1) / Lx) < kMinTiles) --Lx;
   c.lines_x = Lx;
   c.threads_x = threads_for((long long)6 * Lx * gs.n0 / 2);
-  long long v = gs.vox / kMinTiles;
-  v = std::max(64LL, std::min(4096LL, v));
-  c.vec_per_tile = (int)((v + 63) / 64 * 64);
-  c.threads_v = std::min(256, c.vec_per_tile);
+  // elementwise kernels carry a reduction; a few hundred tiles suffice
+  long long v = (gs.vox + 511) / 512;
+  v = std::max(256LL, std::min(8192LL, (v + 255) / 256 * 256));
+  c.vec_per_tile = (int)v;
+  c.threads_v = 256;
   c.big_radix = gs.big;
   c.n0max = gs.n0;
   c.n1max = gs.n1;
@@ -662,7 +665,7 @@ static void fill_desc(RveDev& rv, fftg_plan pl, fftg_history h, const LaunchCfg&
   compute_tiles(cfg, rv.n0, rv.n1, rv.n2, rv.nvox, rv.tiles);
 }
 
-static void group_config(Group& g) {
+static GridSum group_gridsum(const Group& g) {
   GridSum gs;
   for (auto* pl : g.plans) {
     gs.n0 = std::max(gs.n0, pl->n[0]);
@@ -675,14 +678,26 @@ static void group_config(Group& g) {
     gs.vox += pl->nvox;
     gs.big = gs.big || pl->big_radix;
   }
-  g.cfg = choose_cfg(gs);
-  const int n0 = gs.n0, n1 = gs.n1, n2 = gs.n2;
-  g.lds_zf = lds_z(0, g.cfg.rows_per_tile, n2);
-  g.lds_y = lds_y(0, g.cfg.lines_y, n1);
-  g.lds_x = lds_x(0, g.cfg.lines_x, n0);
-  g.lds_zf32 = lds_z(1, g.cfg.rows_per_tile, n2);
-  g.lds_y32 = lds_y(1, g.cfg.lines_y, n1);
-  g.lds_x32 = lds_x(1, g.cfg.lines_x, n0);
+  return gs;
+}
+
+// Applies a launch configuration: LDS sizes and every member's tile counts.
+static void group_set_cfg(Group& g, const LaunchCfg& c) {
+  g.cfg = c;
+  const int n0 = c.n0max, n1 = c.n1max, n2 = c.n2max;
+  g.lds_zf = lds_z(0, c.rows_per_tile, n2);
+  g.lds_y = lds_y(0, c.lines_y, n1);
+  g.lds_x = lds_x(0, c.lines_x, n0);
+  g.lds_zf32 = lds_z(1, c.rows_per_tile, n2);
+  g.lds_y32 = lds_y(1, c.lines_y, n1);
+  g.lds_x32 = lds_x(1, c.lines_x, n0);
+  for (auto& rv : g.h)
+    if (!rv.skip) compute_tiles(c, rv.n0, rv.n1, rv.n2, rv.nvox, rv.tiles);
+}
+
+static void group_config(Group& g) {
+  g.cfg = choose_cfg(group_gridsum(g));
+  group_set_cfg(g, g.cfg);
   g.xcd_remap = (int)env_long("FFTG_XCD_REMAP", 1) == 1;
 }
 
@@ -944,6 +959,149 @@ static fftg_status group_increment(Group& g, const double* dE_tensor, const int*
   return ret;
 }
 
+// ------------------------------------------------------------- autotuner
+// Times candidate tile widths and workgroup sizes of each pass kernel on the
+// group's own buffers (scratch roles P -> spectrum -> AP, no CG state is
+// touched) and keeps the fastest per pass.  Results are cached per grid
+// signature for the process.  FFTG_AUTOTUNE=0 keeps the heuristic.
+static std::map<std::string, LaunchCfg> g_tune_cache;
+
+static std::string tune_key(const Group& g, const GridSum& gs) {
+  std::string k = std::to_string(g.mixed) + ":" + std::to_string(env_long("FFTG_LDS_KB", 64));
+  for (auto* pl : g.plans)
+    k += ":" + std::to_string(pl->n[0]) + "x" + std::to_string(pl->n[1]) + "x" + std::to_string(pl->n[2]);
+  (void)gs;
+  return k;
+}
+
+template <class F>
+static double time_ms(hipStream_t s, int reps, F&& launch) {
+  hipEvent_t a, b;
+  if (hipEventCreate(&a) != hipSuccess) return 1e30;
+  if (hipEventCreate(&b) != hipSuccess) {
+    hipEventDestroy(a);
+    return 1e30;
+  }
+  double ms = 1e30;
+  if (launch() == hipSuccess) {
+    hipEventRecord(a, s);
+    bool ok = true;
+    for (int i = 0; i < reps && ok; ++i) ok = launch() == hipSuccess;
+    hipEventRecord(b, s);
+    float t = 0.f;
+    if (ok && hipEventSynchronize(b) == hipSuccess && hipEventElapsedTime(&t, a, b) == hipSuccess) ms = t / reps;
+  }
+  hipEventDestroy(a);
+  hipEventDestroy(b);
+  return ms;
+}
+
+static fftg_status group_autotune(Group& g) {
+  const GridSum gs = group_gridsum(g);
+  LaunchCfg best = choose_cfg(gs);
+  if (env_long("FFTG_AUTOTUNE", 1) != 1) {
+    group_set_cfg(g, best);
+    return FFTG_OK;
+  }
+  const std::string key = tune_key(g, gs);
+  auto it = g_tune_cache.find(key);
+  if (it != g_tune_cache.end()) {
+    group_set_cfg(g, it->second);
+    return FFTG_OK;
+  }
+  const size_t budget = (size_t)env_long("FFTG_LDS_KB", 64) * 1024;
+  const int nr = (int)g.h.size();
+  const int mixed = g.mixed;
+  const int thr[3] = {64, 128, 256};
+  const int reps = gs.vox > 4000000 ? 2 : 4;
+  fftg_status st;
+  // z passes: rows per tile and threads (zfwd + zinv timed together)
+  {
+    double tbest = 1e30;
+    LaunchCfg cb = best;
+    for (int R : {1, 2, 3, 4, 6, 8}) {
+      if (lds_z(0, R, gs.n2) > budget) break;
+      for (int t : thr) {
+        LaunchCfg c = best;
+        c.rows_per_tile = R;
+        c.threads_z = t;
+        group_set_cfg(g, c);
+        if ((st = group_upload(g)) != FFTG_OK) return st;
+        const size_t lz = mixed ? g.lds_zf32 : g.lds_zf;
+        const double ms = time_ms(g.stream, reps, [&]() {
+          hipError_t e = launch_zfwd(mixed, g.d, nr, g.total[P_ZF], g.cfg, lz, IN_ROLE, R_P, TAN_ELASTIC, 0, 0, 0,
+                                     g.stream);
+          if (e != hipSuccess) return e;
+          return launch_zinv(mixed, g.d, nr, g.total[P_ZI], g.cfg, lz, OUT_PLAIN, R_AP, 0, g.stream);
+        });
+        if (ms < tbest) {
+          tbest = ms;
+          cb = c;
+        }
+      }
+    }
+    best.rows_per_tile = cb.rows_per_tile;
+    best.threads_z = cb.threads_z;
+  }
+  // y pass
+  {
+    double tbest = 1e30;
+    LaunchCfg cb = best;
+    for (int L : {1, 2, 4, 8, 12, 16}) {
+      if (lds_y(0, L, gs.n1) > budget) break;
+      for (int t : thr) {
+        LaunchCfg c = best;
+        c.lines_y = L;
+        c.threads_y = t;
+        group_set_cfg(g, c);
+        if ((st = group_upload(g)) != FFTG_OK) return st;
+        const size_t ly = mixed ? g.lds_y32 : g.lds_y;
+        const double ms = time_ms(g.stream, reps, [&]() {
+          return launch_ypass(mixed, -1, g.d, nr, g.total[P_Y], g.cfg, ly, 0, g.stream);
+        });
+        if (ms < tbest) {
+          tbest = ms;
+          cb = c;
+        }
+      }
+    }
+    best.lines_y = cb.lines_y;
+    best.threads_y = cb.threads_y;
+  }
+  // x pass
+  {
+    double tbest = 1e30;
+    LaunchCfg cb = best;
+    for (int L : {1, 2, 3, 4, 6, 8}) {
+      if (lds_x(0, L, gs.n0) > budget) break;
+      for (int t : thr) {
+        LaunchCfg c = best;
+        c.lines_x = L;
+        c.threads_x = t;
+        group_set_cfg(g, c);
+        if ((st = group_upload(g)) != FFTG_OK) return st;
+        const size_t lx = mixed ? g.lds_x32 : g.lds_x;
+        const double ms = time_ms(g.stream, reps, [&]() {
+          return launch_xpass(mixed, g.d, nr, g.total[P_X], g.cfg, lx, 1.0, 0, g.stream);
+        });
+        if (ms < tbest) {
+          tbest = ms;
+          cb = c;
+        }
+      }
+    }
+    best.lines_x = cb.lines_x;
+    best.threads_x = cb.threads_x;
+  }
+  HIP_TRY(hipStreamSynchronize(g.stream));
+  if (env_long("FFTG_VERBOSE", 0) == 1)
+    fprintf(stderr, "fftg autotune %s: rows %d/%d thr, y %d/%d, x %d/%d, vec %d\n", key.c_str(), best.rows_per_tile,
+            best.threads_z, best.lines_y, best.threads_y, best.lines_x, best.threads_x, best.vec_per_tile);
+  g_tune_cache[key] = best;
+  group_set_cfg(g, best);
+  return FFTG_OK;
+}
+
 // Single-member group view on a plan (uses the plan's own descriptor slot).
 static fftg_status single_group(fftg_plan pl, fftg_history h, Group& g) {
   g.mixed = pl->mixed;
@@ -951,6 +1109,7 @@ static fftg_status single_group(fftg_plan pl, fftg_history h, Group& g) {
   g.plans = {pl};
   g.hists = {h};
   group_config(g);
+  if (pl->tuned) group_set_cfg(g, pl->cfg);
   g.h.resize(1);
   fill_desc(g.h[0], pl, h, g.cfg);
   g.d = pl->d_rv;
@@ -964,6 +1123,16 @@ static fftg_status single_group(fftg_plan pl, fftg_history h, Group& g) {
 }
 
 static void single_group_done(fftg_plan pl, Group& g) { pl->stage_next = g.next; }
+
+// Autotunes a plan's launch configuration on its first solve or product.
+static fftg_status ensure_tuned(fftg_plan pl, Group& g) {
+  if (pl->tuned) return FFTG_OK;
+  const fftg_status st = group_autotune(g);
+  if (st != FFTG_OK) return st;
+  pl->cfg = g.cfg;
+  pl->tuned = 1;
+  return FFTG_OK;
+}
 
 static fftg_status eval_elastic_tangent(fftg_plan pl, fftg_history h) {
   // constitutive at zero strain from the virgin history gives Ce everywhere
@@ -989,7 +1158,8 @@ fftg_status fftg_solve_increment(fftg_plan pl, fftg_history h, const double dE[6
       if (lockstep[i] < 0) return fail(FFTG_E_INVALID, "negative lockstep count");
   Group g;
   single_group(pl, h, g);
-  fftg_status st = group_increment(g, dE, lockstep, n_lockstep, stats);
+  fftg_status st = ensure_tuned(pl, g);
+  if (st == FFTG_OK) st = group_increment(g, dE, lockstep, n_lockstep, stats);
   single_group_done(pl, g);
   return st;
 }
@@ -1002,9 +1172,14 @@ fftg_status fftg_apply_GK(fftg_plan pl, fftg_history h, const double* d_in, void
   if (h && h->plan != pl) return fail(FFTG_E_INVALID, "history belongs to another plan");
   Group g;
   single_group(pl, h, g);
+  fftg_status st = ensure_tuned(pl, g);
+  if (st != FFTG_OK) {
+    single_group_done(pl, g);
+    return st;
+  }
   g.h[0].buf[R_USER_IN] = (void*)d_in;
   g.h[0].buf[R_USER_OUT] = d_out;
-  fftg_status st = group_upload(g);
+  st = group_upload(g);
   if (st == FFTG_OK)
     st = enqueue_apply(g, pl->mixed, IN_ROLE, R_USER_IN, (int)mode, 0, OUT_PLAIN, R_USER_OUT, 1.0, 0);
   single_group_done(pl, g);
@@ -1200,6 +1375,11 @@ fftg_status fftg_batch_create(fftg_batch* out, int count, const fftg_plan* plans
   if (e != hipSuccess) {
     fftg_batch_destroy(b);
     return fail(FFTG_E_NOMEM, std::string("batch allocation: ") + hipGetErrorString(e));
+  }
+  const fftg_status st = group_autotune(g);
+  if (st != FFTG_OK) {
+    fftg_batch_destroy(b);
+    return st;
   }
   *out = b;
   return FFTG_OK;

@@ -189,7 +189,7 @@ fftg_status fftg_batch_solve_increment(fftg_batch batch, const double* dE, fftg_
  * synchronises the recorded events and returns the summed kernel time in
  * milliseconds, the number of launches and the voxels those launches
  * covered (sum over the RVEs each launch processed); any output may be
- * NULL.  Not thread-safe with concurrent solves on other threads. */
+ * NULL.  Safe to call while other threads solve on distinct plans. */
 typedef enum {
   FFTG_KERNEL_ZFWD = 0,        /* p update, tangent contraction, real-to-complex DFT along z */
   FFTG_KERNEL_Y_FWD = 1,       /* DFT along y */

@@ -10,6 +10,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -564,8 +565,11 @@ struct Profiler {
   long long launches = 0;
 };
 static Profiler g_prof;
+static std::mutex g_prof_mutex;
 
 static int prof_begin(int kid, hipStream_t s) {
+  if (g_prof.kid != kid) return -1;  // racy read is benign: profiling is off or on for one kind
+  std::lock_guard<std::mutex> lk(g_prof_mutex);
   if (g_prof.kid != kid) return -1;
   if (g_prof.used + 2 > g_prof.pool.size()) {
     for (int i = 0; i < 64; ++i) {
@@ -582,6 +586,7 @@ static int prof_begin(int kid, hipStream_t s) {
 
 static void prof_end(int idx, hipStream_t s, double voxels) {
   if (idx < 0) return;
+  std::lock_guard<std::mutex> lk(g_prof_mutex);
   hipEventRecord(g_prof.pool[idx + 1], s);
   g_prof.launches += 1;
   g_prof.voxels += voxels;
@@ -589,6 +594,7 @@ static void prof_end(int idx, hipStream_t s, double voxels) {
 
 fftg_status fftg_profiler_start(int kernel_id) {
   if (kernel_id < 0 || kernel_id >= FFTG_KERNEL_COUNT) return fail(FFTG_E_INVALID, "bad kernel id");
+  std::lock_guard<std::mutex> lk(g_prof_mutex);
   g_prof.kid = kernel_id;
   g_prof.used = 0;
   g_prof.voxels = 0.0;
@@ -597,6 +603,7 @@ fftg_status fftg_profiler_start(int kernel_id) {
 }
 
 fftg_status fftg_profiler_stop(double* total_ms, long long* launches, double* voxels) {
+  std::lock_guard<std::mutex> lk(g_prof_mutex);
   double tot = 0.0;
   for (size_t i = 0; i + 1 < g_prof.used; i += 2) {
     HIP_TRY(hipEventSynchronize(g_prof.pool[i + 1]));
@@ -965,13 +972,16 @@ static fftg_status group_increment(Group& g, const double* dE_tensor, const int*
 // touched) and keeps the fastest per pass.  Results are cached per grid
 // signature for the process.  FFTG_AUTOTUNE=0 keeps the heuristic.
 static std::map<std::string, LaunchCfg> g_tune_cache;
+static std::mutex g_tune_mutex;
 
+// Cache key: precision, LDS budget, largest extents and the total voxel
+// count rounded to a power of two (batches of similar size share a tuning).
 static std::string tune_key(const Group& g, const GridSum& gs) {
-  std::string k = std::to_string(g.mixed) + ":" + std::to_string(env_long("FFTG_LDS_KB", 64));
-  for (auto* pl : g.plans)
-    k += ":" + std::to_string(pl->n[0]) + "x" + std::to_string(pl->n[1]) + "x" + std::to_string(pl->n[2]);
-  (void)gs;
-  return k;
+  int lg = 0;
+  while ((1LL << (lg + 1)) <= gs.vox) ++lg;
+  return std::to_string(g.mixed) + ":" + std::to_string(env_long("FFTG_LDS_KB", 64)) + ":" +
+         std::to_string(gs.n0) + "x" + std::to_string(gs.n1) + "x" + std::to_string(gs.n2) + ":n" +
+         std::to_string(g.plans.size() > 1 ? 1 : 0) + ":v" + std::to_string(lg);
 }
 
 template <class F>
@@ -1004,10 +1014,13 @@ static fftg_status group_autotune(Group& g) {
     return FFTG_OK;
   }
   const std::string key = tune_key(g, gs);
-  auto it = g_tune_cache.find(key);
-  if (it != g_tune_cache.end()) {
-    group_set_cfg(g, it->second);
-    return FFTG_OK;
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mutex);
+    auto it = g_tune_cache.find(key);
+    if (it != g_tune_cache.end()) {
+      group_set_cfg(g, it->second);
+      return FFTG_OK;
+    }
   }
   const size_t budget = (size_t)env_long("FFTG_LDS_KB", 64) * 1024;
   const int nr = (int)g.h.size();
@@ -1097,7 +1110,10 @@ static fftg_status group_autotune(Group& g) {
   if (env_long("FFTG_VERBOSE", 0) == 1)
     fprintf(stderr, "fftg autotune %s: rows %d/%d thr, y %d/%d, x %d/%d, vec %d\n", key.c_str(), best.rows_per_tile,
             best.threads_z, best.lines_y, best.threads_y, best.lines_x, best.threads_x, best.vec_per_tile);
-  g_tune_cache[key] = best;
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mutex);
+    g_tune_cache[key] = best;
+  }
   group_set_cfg(g, best);
   return FFTG_OK;
 }

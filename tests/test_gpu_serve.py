@@ -1,0 +1,49 @@
+"""Served requests give the same results as the same requests solved alone
+(within the stated tolerance: 1e-10 FP64, 1e-6 mixed), with arrivals that
+overlap work already on the device."""
+import numpy as np
+import pytest
+
+import synth
+from tests.gpu_util import tensor6
+
+pytestmark = pytest.mark.gpu
+
+
+def _requests():
+    shapes = [(9, 9, 9), (15, 15, 15), (11, 13, 7), (15, 15, 15), (9, 11, 13), (13, 13, 13)]
+    precs = ["fp64", "mixed", "fp64", "fp64", "mixed", "mixed"]
+    arrivals = [0.0, 0.0, 0.002, 0.004, 0.006, 0.05]
+    out = []
+    for i, (sh, pr, t) in enumerate(zip(shapes, precs, arrivals)):
+        w = synth.small_random(sh, 0.35, 10 + i, E_eq=0.01, n_inc=3 + (i % 2))
+        w.precision = pr
+        out.append(synth.Request(i, t, w))
+    return out
+
+
+def _alone(w):
+    from paper_1601_05970_amd import fftg
+    o = fftg.fftg_options_default()
+    o.tol_newton, o.tol_cg = w.tol_newton, w.tol_cg
+    o.precision = fftg.FFTG_MIXED if w.precision == "mixed" else fftg.FFTG_FP64
+    pl = fftg.Plan(w.phase, w.materials, o)
+    h = fftg.History(pl)
+    return [h.solve_increment(tensor6(w.dE(n)))["Sigma"] for n in range(1, w.n_inc + 1)]
+
+
+def test_served_results_equal_alone():
+    print("serve alone vs mix", flush=True)
+    from paper_1601_05970_amd.serve import FftgExecutor, Server, summarize
+    reqs = _requests()
+    srv = Server(FftgExecutor(size_split=12), 8 * 10 ** 9)
+    recs = srv.run(reqs)
+    assert all(r.status == "ok" for r in recs), [(r.rid, r.status, r.error) for r in recs]
+    for q, r in zip(reqs, recs):
+        ref = np.array(_alone(q.workload))
+        got = np.array(r.sigma)
+        tol = 1e-10 if q.workload.precision == "fp64" else 1e-6
+        assert got.shape == ref.shape
+        assert np.max(np.abs(got - ref)) <= tol * np.max(np.abs(ref)), (q.rid, q.workload.precision)
+    s = summarize(recs)
+    assert s["ok"] == len(reqs)

@@ -15,9 +15,10 @@
  * ---------------------------------
  * Grid: extents n0, n1, n2 >= 1, all odd (even grids are not conforming,
  *   Sec. 2.3).  Axis 0 = x is slowest, axis 2 = z fastest (C order).
- *   Supported extents: products of 3, 5, 7, 11, 13, 17 and primes p whose
+ *   Supported extents: products of 3, 5, 7, 11, 13, 17, primes p whose
  *   p - 1 is a product of 2, 3, 4, 5, 7, 9, 11, 13, 17 (e.g. 11, 15, 31, 63,
- *   127, 255); others give FFTG_E_UNSUPPORTED.  Cell size L_i = n_i.
+ *   127, 255), and any odd extent up to 64 (direct DFT); others give
+ *   FFTG_E_UNSUPPORTED.  Cell size L_i = n_i.
  * Tensor fields on the device: 6 contiguous planes of n0*n1*n2 values each,
  *   Mandel order [11, 22, 33, sqrt2*e23, sqrt2*e13, sqrt2*e12] (Appendix B,
  *   extended to 3-D).  Host 6-vectors in this API (dE, E, Sigma) are plain

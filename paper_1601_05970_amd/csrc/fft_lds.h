@@ -215,7 +215,7 @@ __device__ void load_axis_lds(const AxisDev& P, char* base, AxisLds<T>& A) {
   A.pout = A.pin + N;
   const cx<T>* tw = axis_tw<T>(P);
   for (int t = threadIdx.x; t < P.M; t += blockDim.x) A.tw[t] = tw[t];
-  if (P.rader) {
+  if (P.rader == AX_RADER) {
     const cx<T>* bf = rader_bhat<T>(P, -1);
     const cx<T>* bi = rader_bhat<T>(P, 1);
     for (int t = threadIdx.x; t < P.M; t += blockDim.x) {
@@ -262,11 +262,52 @@ __device__ void run_chain(cx<T>*& a, cx<T>*& b, int ld, int nl, const AxisLds<T>
 // result (line or scratch).  Must be called by the whole workgroup.
 template <int DIR, class T, int BIG>
 __device__ cx<T>* line_fft(cx<T>* line, cx<T>* scratch, int ld, int nl, const AxisLds<T>& P, cx<T>* dc) {
-  if (!P.rader) {
+  if (P.rader == AX_CHAIN) {
     cx<T>* a = line;
     cx<T>* b = scratch;
     run_chain<DIR, T, BIG>(a, b, ld, nl, P);
     return a;
+  }
+  if (P.rader == AX_DIRECT) {
+    // X_k = sum_j x_j w^(jk), w = exp(-+ 2 pi i / N): one output per thread,
+    // the root index jk mod N advanced by k per term.
+    const int N = P.M;
+    const FastDiv fn(N);
+    for (int t = threadIdx.x; t < nl * N; t += blockDim.x) {
+      const int l = fn.div(t);
+      const int k = t - l * N;
+      const cx<T>* x = line + l * ld;
+      T re0 = T(0), im0 = T(0), re1 = T(0), im1 = T(0);
+      int idx = 0;
+      int j = 0;
+      for (; j + 1 < N; j += 2) {
+        cx<T> w0 = P.tw[idx];
+        idx += k;
+        idx -= (idx >= N) ? N : 0;
+        cx<T> w1 = P.tw[idx];
+        idx += k;
+        idx -= (idx >= N) ? N : 0;
+        if (DIR > 0) {
+          w0.im = -w0.im;
+          w1.im = -w1.im;
+        }
+        const cx<T> a = x[j], b = x[j + 1];
+        re0 += a.re * w0.re - a.im * w0.im;
+        im0 += a.re * w0.im + a.im * w0.re;
+        re1 += b.re * w1.re - b.im * w1.im;
+        im1 += b.re * w1.im + b.im * w1.re;
+      }
+      if (j < N) {
+        cx<T> w0 = P.tw[idx];
+        if (DIR > 0) w0.im = -w0.im;
+        const cx<T> a = x[j];
+        re0 += a.re * w0.re - a.im * w0.im;
+        im0 += a.re * w0.im + a.im * w0.re;
+      }
+      scratch[l * ld + k] = cx<T>{re0 + re1, im0 + im1};
+    }
+    __syncthreads();
+    return scratch;
   }
   const int M = P.M;
   const int total = nl * M;

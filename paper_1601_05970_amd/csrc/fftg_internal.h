@@ -28,10 +28,14 @@ struct cx {
 // One transform length: either a Stockham chain of direct radices, or Rader's
 // algorithm for a prime p with its length-(p-1) cyclic convolution done by a
 // Stockham chain.
+// How an axis is transformed: a Stockham chain over N, Rader's algorithm
+// over prime N (chains over N-1), or the O(N^2) direct DFT from a root table.
+enum AxisKind { AX_CHAIN = 0, AX_RADER = 1, AX_DIRECT = 2 };
+
 struct AxisDev {
   int N;
-  int rader;            // 0: direct chain over N; 1: Rader over prime N
-  int M;                // chain length (N, or N-1 for Rader)
+  int rader;            // AX_CHAIN, AX_RADER or AX_DIRECT
+  int M;                // chain length (N, or N-1 for Rader; N for the direct DFT)
   int nst;              // stages of the chain
   int radix[kMaxStages];
   // tables (device pointers); roots are exp(-2 pi i m / M), m < M

@@ -14,7 +14,8 @@ from tests.gpu_util import m2t, rel_err, t2m, to_dev, to_host
 pytestmark = pytest.mark.gpu
 
 SHAPES = [(3, 3, 3), (1, 5, 7), (7, 5, 1), (3, 5, 7), (5, 7, 9), (11, 11, 11), (13, 17, 11),
-          (15, 15, 15), (21, 25, 27), (31, 31, 31), (63, 31, 15), (19, 23, 29), (61, 9, 5)]
+          (15, 15, 15), (21, 25, 27), (31, 31, 31), (63, 31, 15), (19, 23, 29), (61, 9, 5),
+          (47, 5, 59), (3, 53, 43)]
 
 
 def _plan(shape, phase=None, mats=None, precision=0):
@@ -39,6 +40,20 @@ def test_projection_matches_oracle(shape):
     got = to_host(d_out)
     ref = t2m(apply_G(tau))
     assert rel_err(got, ref) < 1e-12
+
+
+@pytest.mark.parametrize("shape", [(19, 23, 29), (31, 31, 31), (61, 9, 53)])
+def test_projection_rader_path_matches_oracle(shape, monkeypatch):
+    """Prime extents with smooth p-1 taken through Rader's algorithm instead
+    of the direct DFT (FFTG_DIRECT_MAX=0 is read at plan creation)."""
+    from paper_1601_05970_amd import fftg
+    print("apply IDENTITY rader", shape, flush=True)
+    monkeypatch.setenv("FFTG_DIRECT_MAX", "0")
+    pl = _plan(shape)
+    tau = synth.random_sym_tensor_field(shape, 3)
+    d_out = pl.field()
+    pl.apply_GK(to_dev(t2m(tau)), d_out, fftg.FFTG_TANGENT_IDENTITY)
+    assert rel_err(to_host(d_out), t2m(apply_G(tau))) < 1e-12
 
 
 @pytest.mark.parametrize("shape", [(5, 7, 9), (15, 15, 15), (31, 31, 31)])

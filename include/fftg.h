@@ -198,7 +198,7 @@ typedef enum {
   FFTG_KERNEL_Y_INV = 3,       /* inverse DFT along y */
   FFTG_KERNEL_ZINV = 4,        /* complex-to-real inverse DFT along z + CG dot */
   FFTG_KERNEL_CG_XR = 5,       /* x += alpha p, r -= alpha Ap, r.r */
-  FFTG_KERNEL_CG_P = 6,        /* unused: p = r + beta p runs inside ZFWD */
+  FFTG_KERNEL_FINALIZE = 6,    /* per-RVE totals of tile partial sums, CG scalar steps */
   FFTG_KERNEL_CONSTITUTIVE = 7,/* J2 return map + consistent tangent */
   FFTG_KERNEL_NEWTON = 8,      /* eps* += d eps, ||d eps|| */
   FFTG_KERNEL_COUNT = 9

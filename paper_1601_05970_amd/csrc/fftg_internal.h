@@ -18,7 +18,6 @@ namespace fftg {
 constexpr int kMaxStages = 8;
 constexpr int kMaxPhases = 16;
 constexpr int kMaxAxisLen = 1024;
-constexpr int kRedGroups = 32;   // first-level counters of a tile reduction
 
 template <class T>
 struct cx {
@@ -62,9 +61,10 @@ struct CgState {
   double Sigma[6];
   int iters, done, force, max_iter, status;
   int pad_;
-  unsigned int counter[8];             // per reduction slot: groups finished
-  unsigned int sub[8][kRedGroups];     // per reduction slot and group: tiles finished
 };
+
+// Scalar steps of k_finalize (which partial sums it totals, and what for).
+enum FinStep { FIN_SNORM = 0, FIN_RESID, FIN_PAP, FIN_RR, FIN_DNORM, FIN_SIGMA };
 
 enum CgStatus { CG_RUNNING = 0, CG_CONVERGED = 1, CG_MAXITER = 2, CG_BREAKDOWN = 3, CG_FORCED = 4 };
 

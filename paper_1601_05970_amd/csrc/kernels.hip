@@ -71,50 +71,30 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
   return r;
 }
 
-// Publishes this tile's partial sums (nv values, in thread 0) and returns
-// true in every thread of the tile that finished last; that tile then sees
-// the totals in out[] (thread 0 only).  Completion is counted in two levels
-// (kRedGroups group counters, then one slot counter) to spread the atomic
-// traffic.  Sum order is fixed (tile 0, 1, ... in an unrolled strided
-// pattern), so the result does not depend on which tile finishes last.
-__device__ bool reduce_tiles(const double* vals, int nv, double* partial, int ntiles, int tile,
-                             unsigned int* counter, unsigned int* sub, double* sh, double* out) {
-  __shared__ int s_last;
-  if (threadIdx.x == 0) {
+// Stores a tile's partial sums (nv values held by thread 0) at
+// partial[i * ntiles + tile].  The per-RVE totals are formed by k_finalize,
+// launched after the producer on the same stream: the kernel boundary makes
+// the partials visible, so no fence or atomic is needed inside the producer
+// (a device-scope fence costs an L2 write-back and invalidate per tile).
+__device__ __forceinline__ void put_partials(const double* vals, int nv, double* partial, int ntiles, int tile) {
+  if (threadIdx.x == 0)
     for (int i = 0; i < nv; ++i) partial[i * ntiles + tile] = vals[i];
-    __threadfence();
-    const int g = tile % kRedGroups;
-    const int gsize = ntiles / kRedGroups + (g < ntiles % kRedGroups ? 1 : 0);
-    const int ngroups = ntiles < kRedGroups ? ntiles : kRedGroups;
-    int last = 0;
-    if (atomicAdd(&sub[g], 1u) == (unsigned int)(gsize - 1)) {
-      __threadfence();
-      last = atomicAdd(counter, 1u) == (unsigned int)(ngroups - 1);
-    }
-    s_last = last;
+}
+
+// Sum of p[0..n) over the workgroup in a fixed order (four strided
+// accumulators per thread, then the block tree); valid in thread 0.
+__device__ double sum_partials(const double* __restrict__ p, int n, double* sh) {
+  const int st = blockDim.x;
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+  int t = threadIdx.x;
+  for (; t + 3 * st < n; t += 4 * st) {
+    a0 += p[t];
+    a1 += p[t + st];
+    a2 += p[t + 2 * st];
+    a3 += p[t + 3 * st];
   }
-  __syncthreads();
-  const bool last = s_last;
-  if (!last) return false;
-  __threadfence();  // acquire: the other tiles' partials are visible below
-  for (int i = 0; i < nv; ++i) {
-    const double* pp = partial + i * ntiles;
-    const int st = blockDim.x;
-    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-    int t = threadIdx.x;
-    for (; t + 3 * st < ntiles; t += 4 * st) {
-      a0 += pp[t];
-      a1 += pp[t + st];
-      a2 += pp[t + 2 * st];
-      a3 += pp[t + 3 * st];
-    }
-    for (; t < ntiles; t += st) a0 += pp[t];
-    const double s = block_sum((a0 + a1) + (a2 + a3), sh);
-    if (threadIdx.x == 0) out[i] = s;
-  }
-  if (threadIdx.x == 0) *counter = 0u;
-  for (int g = threadIdx.x; g < kRedGroups; g += blockDim.x) sub[g] = 0u;
-  return true;
+  for (; t < n; t += st) a0 += p[t];
+  return block_sum((a0 + a1) + (a2 + a3), sh);
 }
 
 template <class T>
@@ -271,10 +251,7 @@ __global__ void __launch_bounds__(256) k_zfwd(const RveDev* __restrict__ rvs, in
   }
   if (want_norm) {
     const double s = block_sum(nrm, L.red);
-    double tot;
-    if (reduce_tiles(&s, 1, rv.partial, rv.tiles[P_ZF], tile, &rv.cg->counter[0], rv.cg->sub[0], L.red, &tot)) {
-      if (threadIdx.x == 0) rv.cg->snorm2 = tot;
-    }
+    put_partials(&s, 1, rv.partial, rv.tiles[P_ZF], tile);
   }
 }
 
@@ -474,39 +451,11 @@ __global__ void __launch_bounds__(256) k_zinv(const RveDev* __restrict__ rvs, in
     return;
   }
   const double s = block_sum(dot, L.red);
-  double tot;
-  if (reduce_tiles(&s, 1, rv.partial, rv.tiles[P_ZI], tile, &rv.cg->counter[1], rv.cg->sub[1], L.red, &tot)) {
-    if (threadIdx.x == 0) {
-      CgState* cg = rv.cg;
-      if (out_mode == OUT_CG) {
-        cg->pAp = tot;
-        if (!(tot > 0.0)) {
-          cg->done = 1;
-          cg->status = CG_BREAKDOWN;
-        } else {
-          cg->alpha = cg->rr / tot;
-        }
-      } else {
-        cg->rr = tot;
-        cg->bnorm2 = tot;
-        cg->beta = 0.0;
-        const double t1 = cg->eta2 * tot, t2 = cg->floor2 * cg->snorm2;
-        cg->target2 = t1 > t2 ? t1 : t2;
-        cg->iters = 0;
-        if (cg->force >= 0) {
-          cg->done = (cg->force == 0);
-          cg->status = cg->done ? CG_FORCED : CG_RUNNING;
-        } else {
-          cg->done = (tot <= cg->target2);
-          cg->status = cg->done ? CG_CONVERGED : CG_RUNNING;
-        }
-      }
-    }
-  }
+  put_partials(&s, 1, rv.partial, rv.tiles[P_ZI], tile);
 }
 
 // ------------------------------------------------------ CG vector updates
-// x += alpha p; r -= alpha Ap; rr' = r.r; convergence test; beta.
+// x += alpha p; r -= alpha Ap; per-tile partials of r.r.
 template <class AT>
 __global__ void __launch_bounds__(256) k_cg_xr(const RveDev* __restrict__ rvs, int nrve, int vox_per_tile) {
   __shared__ double red[16];
@@ -543,31 +492,7 @@ __global__ void __launch_bounds__(256) k_cg_xr(const RveDev* __restrict__ rvs, i
     }
   }
   const double s = block_sum(acc, red);
-  double tot;
-  if (reduce_tiles(&s, 1, rv.partial, rv.tiles[P_VEC], tile, &rv.cg->counter[2], rv.cg->sub[2], red, &tot)) {
-    if (threadIdx.x == 0) {
-      CgState* cg = rv.cg;
-      cg->iters += 1;
-      cg->rr_new = tot;
-      int done = 0, st = CG_RUNNING;
-      if (cg->force >= 0) {
-        if (cg->iters >= cg->force) {
-          done = 1;
-          st = CG_FORCED;
-        }
-      } else if (tot <= cg->target2) {
-        done = 1;
-        st = CG_CONVERGED;
-      } else if (cg->iters >= cg->max_iter) {
-        done = 1;
-        st = CG_MAXITER;
-      }
-      cg->beta = tot / cg->rr;
-      cg->rr = tot;
-      cg->status = st;
-      cg->done = done;
-    }
-  }
+  put_partials(&s, 1, rv.partial, rv.tiles[P_VEC], tile);
 }
 
 // eps* += x (Algorithm 1, iterative update) and ||x||^2.
@@ -599,10 +524,7 @@ __global__ void __launch_bounds__(256) k_newton_update(const RveDev* __restrict_
     }
   }
   const double s = block_sum(acc, red);
-  double tot;
-  if (reduce_tiles(&s, 1, rv.partial, rv.tiles[P_VEC], tile, &rv.cg->counter[3], rv.cg->sub[3], red, &tot)) {
-    if (threadIdx.x == 0) rv.cg->dnorm2 = tot;
-  }
+  put_partials(&s, 1, rv.partial, rv.tiles[P_VEC], tile);
 }
 
 // ------------------------------------------------ J2 return map (Sec. 4.2)
@@ -692,11 +614,93 @@ __global__ void __launch_bounds__(256) k_constitutive(const RveDev* __restrict__
   if (commit) {
     double s[6];
     for (int c = 0; c < 6; ++c) s[c] = block_sum(ssum[c], red);
-    double tot[6];
-    if (reduce_tiles(s, 6, rv.partial, rv.tiles[P_VEC], tile, &rv.cg->counter[4], rv.cg->sub[4], red, tot)) {
-      if (threadIdx.x == 0)
-        for (int c = 0; c < 6; ++c) rv.cg->Sigma[c] = tot[c] / double(nvox);
+    put_partials(s, 6, rv.partial, rv.tiles[P_VEC], tile);
+  }
+}
+
+// ------------------------------------------------------------- finalize
+// One workgroup per RVE: sums the tile partials of the preceding producer
+// kernel in a fixed order and applies the scalar step that uses the total.
+//   FIN_SNORM  ||C:dE||^2 of the right-hand side floor
+//   FIN_RESID  b.b of the CG right-hand side: target, start or skip of CG
+//   FIN_PAP    p.Ap: alpha = r.r / p.Ap (breakdown when p.Ap <= 0)
+//   FIN_RR     r.r after the update: iteration count, stopping test, beta
+//   FIN_DNORM  ||d eps||^2 of the Newton update
+//   FIN_SIGMA  volume average of sigma (six sums)
+__global__ void __launch_bounds__(256) k_finalize(const RveDev* __restrict__ rvs, int nrve, int step) {
+  __shared__ double red[16];
+  const int ri = blockIdx.x;
+  if (ri >= nrve) return;
+  const RveDev& rv = rvs[ri];
+  if (rv.skip) return;
+  CgState* cg = rv.cg;
+  if ((step == FIN_PAP || step == FIN_RR) && cg->done) return;
+  const int pass = step == FIN_SNORM ? P_ZF : ((step == FIN_RESID || step == FIN_PAP) ? P_ZI : P_VEC);
+  const int nt = rv.tiles[pass];
+  const int nv = step == FIN_SIGMA ? 6 : 1;
+  double tot[6];
+  for (int i = 0; i < nv; ++i) tot[i] = sum_partials(rv.partial + (size_t)i * nt, nt, red);
+  if (threadIdx.x != 0) return;
+  const double t = tot[0];
+  switch (step) {
+    case FIN_SNORM:
+      cg->snorm2 = t;
+      break;
+    case FIN_RESID: {
+      cg->rr = t;
+      cg->bnorm2 = t;
+      cg->beta = 0.0;
+      const double t1 = cg->eta2 * t, t2 = cg->floor2 * cg->snorm2;
+      cg->target2 = t1 > t2 ? t1 : t2;
+      cg->iters = 0;
+      if (cg->force >= 0) {
+        cg->done = (cg->force == 0);
+        cg->status = cg->done ? CG_FORCED : CG_RUNNING;
+      } else {
+        cg->done = (t <= cg->target2);
+        cg->status = cg->done ? CG_CONVERGED : CG_RUNNING;
+      }
+      break;
     }
+    case FIN_PAP:
+      cg->pAp = t;
+      if (!(t > 0.0)) {
+        cg->done = 1;
+        cg->status = CG_BREAKDOWN;
+      } else {
+        cg->alpha = cg->rr / t;
+      }
+      break;
+    case FIN_RR: {
+      cg->iters += 1;
+      cg->rr_new = t;
+      int done = 0, st = CG_RUNNING;
+      if (cg->force >= 0) {
+        if (cg->iters >= cg->force) {
+          done = 1;
+          st = CG_FORCED;
+        }
+      } else if (t <= cg->target2) {
+        done = 1;
+        st = CG_CONVERGED;
+      } else if (cg->iters >= cg->max_iter) {
+        done = 1;
+        st = CG_MAXITER;
+      }
+      cg->beta = t / cg->rr;
+      cg->rr = t;
+      cg->status = st;
+      cg->done = done;
+      break;
+    }
+    case FIN_DNORM:
+      cg->dnorm2 = t;
+      break;
+    case FIN_SIGMA:
+      for (int c = 0; c < 6; ++c) cg->Sigma[c] = tot[c] / double(rv.nvox);
+      break;
+    default:
+      break;
   }
 }
 
@@ -849,6 +853,12 @@ hipError_t launch_constitutive(int mixed, const RveDev* rv, int nrve, int tiles,
   else
     hipLaunchKernelGGL(k_constitutive<double>, dim3(tiles), dim3(cfg.threads_v), 0, s, rv, nrve,
                        cfg.vec_per_tile, eps_role, commit);
+  return hipGetLastError();
+}
+
+hipError_t launch_finalize(const RveDev* rv, int nrve, int step, hipStream_t s) {
+  if (nrve <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_finalize, dim3(nrve), dim3(256), 0, s, rv, nrve, step);
   return hipGetLastError();
 }
 

@@ -34,6 +34,7 @@ hipError_t launch_zinv(int mixed, const RveDev* rv, int nrve, int tiles, const L
                        int out_mode, int out_role, int check_done, hipStream_t s);
 hipError_t launch_cg_xr(int mixed, const RveDev* rv, int nrve, int tiles, const LaunchCfg& cfg, hipStream_t s);
 hipError_t launch_newton_update(const RveDev* rv, int nrve, int tiles, const LaunchCfg& cfg, hipStream_t s);
+hipError_t launch_finalize(const RveDev* rv, int nrve, int step, hipStream_t s);
 hipError_t launch_constitutive(int mixed, const RveDev* rv, int nrve, int tiles, const LaunchCfg& cfg,
                                int eps_role, int commit, hipStream_t s);
 hipError_t launch_cg_setup(const RveDev* rv, int nrve, double eta2, double floor2, int max_iter, int force,
@@ -150,9 +151,10 @@ static hipError_t upload(const std::vector<T>& v, T** out, std::vector<void*>& a
 // direct DFT; primes up to FFTG_DIRECT_MAX (default kDirectPrimeMax) use it
 // in place of Rader's algorithm, whose two chained transforms cost about ten
 // workgroup barriers against the direct form's one (measured at 31 points:
-// 41 us per product against 67 us; at 61 points Rader is faster).
+// 41 us per product against 67 us, at 53 points 118 against 121 us; at 61
+// points Rader is faster, 135 against 183 us).
 constexpr int kDirectMax = 64;
-constexpr int kDirectPrimeMax = 41;
+constexpr int kDirectPrimeMax = 53;
 
 static fftg_status build_axis(int N, AxisHost& ax) {
   AxisDev& d = ax.dev;
@@ -794,11 +796,15 @@ static fftg_status enqueue_apply(Group& g, int mixed, int in_mode, int in_role, 
   const size_t lx = mixed ? g.lds_x32 : g.lds_x;
   PROF_LAUNCH(FFTG_KERNEL_ZFWD, launch_zfwd(mixed, g.d, nr, g.total[P_ZF], g.cfg, lz, in_mode, in_role, tan_mode,
                                             want_norm, check_done, update_p, g.stream));
+  if (want_norm) PROF_LAUNCH(FFTG_KERNEL_FINALIZE, launch_finalize(g.d, nr, FIN_SNORM, g.stream));
   PROF_LAUNCH(FFTG_KERNEL_Y_FWD, launch_ypass(mixed, -1, g.d, nr, g.total[P_Y], g.cfg, ly, check_done, g.stream));
   PROF_LAUNCH(FFTG_KERNEL_X_PROJ, launch_xpass(mixed, g.d, nr, g.total[P_X], g.cfg, lx, scale, check_done, g.stream));
   PROF_LAUNCH(FFTG_KERNEL_Y_INV, launch_ypass(mixed, 1, g.d, nr, g.total[P_Y], g.cfg, ly, check_done, g.stream));
   PROF_LAUNCH(FFTG_KERNEL_ZINV, launch_zinv(mixed, g.d, nr, g.total[P_ZI], g.cfg, lz, out_mode, out_role,
                                             check_done, g.stream));
+  if (out_mode == OUT_CG || out_mode == OUT_RESIDUAL)
+    PROF_LAUNCH(FFTG_KERNEL_FINALIZE,
+                launch_finalize(g.d, nr, out_mode == OUT_CG ? FIN_PAP : FIN_RESID, g.stream));
   return FFTG_OK;
 }
 
@@ -809,6 +815,7 @@ static fftg_status enqueue_cg_iters(Group& g, int iters) {
     fftg_status st = enqueue_apply(g, g.mixed, IN_ROLE, R_P, TAN_CURRENT, 0, OUT_CG, R_AP, 1.0, 1, 1);
     if (st != FFTG_OK) return st;
     PROF_LAUNCH(FFTG_KERNEL_CG_XR, launch_cg_xr(g.mixed, g.d, nr, g.total[P_VEC], g.cfg, g.stream));
+    PROF_LAUNCH(FFTG_KERNEL_FINALIZE, launch_finalize(g.d, nr, FIN_RR, g.stream));
   }
   return FFTG_OK;
 }
@@ -963,6 +970,7 @@ static fftg_status group_increment(Group& g, const double* dE_tensor, const int*
       if (st != FFTG_OK) return st;
     }
     PROF_LAUNCH(FFTG_KERNEL_NEWTON, launch_newton_update(g.d, nr, g.total[P_VEC], g.cfg, g.stream));
+    PROF_LAUNCH(FFTG_KERNEL_FINALIZE, launch_finalize(g.d, nr, FIN_DNORM, g.stream));
     st = read_states(g);
     if (st != FFTG_OK) return st;
     bool changed = false;
@@ -1002,6 +1010,7 @@ static fftg_status group_increment(Group& g, const double* dE_tensor, const int*
   if (st != FFTG_OK) return st;
   PROF_LAUNCH(FFTG_KERNEL_CONSTITUTIVE,
               launch_constitutive(g.mixed, g.d, nr, g.total[P_VEC], g.cfg, R_EPS_FL, 1, g.stream));
+  PROF_LAUNCH(FFTG_KERNEL_FINALIZE, launch_finalize(g.d, nr, FIN_SIGMA, g.stream));
   st = read_states(g);
   if (st != FFTG_OK) return st;
   const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();

@@ -269,42 +269,36 @@ __device__ cx<T>* line_fft(cx<T>* line, cx<T>* scratch, int ld, int nl, const Ax
     return a;
   }
   if (P.rader == AX_DIRECT) {
-    // X_k = sum_j x_j w^(jk), w = exp(-+ 2 pi i / N): one output per thread,
-    // the root index jk mod N advanced by k per term.
+    // X_k = sum_j x_j w^(jk), w = exp(-+ 2 pi i / N), N odd.  One thread forms the
+    // pair X_k, X_(N-k) (k = 1 .. (N-1)/2; slot 0 forms X_0): both use the
+    // products of x_j with the same root w^(jk), taken conjugated for N-k.
     const int N = P.M;
-    const FastDiv fn(N);
-    for (int t = threadIdx.x; t < nl * N; t += blockDim.x) {
-      const int l = fn.div(t);
-      const int k = t - l * N;
+    const int Hn = (N + 1) / 2;
+    const FastDiv fh(Hn);
+    for (int t = threadIdx.x; t < nl * Hn; t += blockDim.x) {
+      const int l = fh.div(t);
+      const int k = t - l * Hn;
       const cx<T>* x = line + l * ld;
-      T re0 = T(0), im0 = T(0), re1 = T(0), im1 = T(0);
+      T pr = T(0), pi = T(0), mr = T(0), mi = T(0);  // X_k and X_(N-k)
       int idx = 0;
-      int j = 0;
-      for (; j + 1 < N; j += 2) {
-        cx<T> w0 = P.tw[idx];
-        idx += k;
-        idx -= (idx >= N) ? N : 0;
-        cx<T> w1 = P.tw[idx];
-        idx += k;
-        idx -= (idx >= N) ? N : 0;
-        if (DIR > 0) {
-          w0.im = -w0.im;
-          w1.im = -w1.im;
-        }
-        const cx<T> a = x[j], b = x[j + 1];
-        re0 += a.re * w0.re - a.im * w0.im;
-        im0 += a.re * w0.im + a.im * w0.re;
-        re1 += b.re * w1.re - b.im * w1.im;
-        im1 += b.re * w1.im + b.im * w1.re;
-      }
-      if (j < N) {
-        cx<T> w0 = P.tw[idx];
-        if (DIR > 0) w0.im = -w0.im;
+      for (int j = 0; j < N; ++j) {
+        const cx<T> w = P.tw[idx];
+        const T s = DIR > 0 ? -w.im : w.im;
         const cx<T> a = x[j];
-        re0 += a.re * w0.re - a.im * w0.im;
-        im0 += a.re * w0.im + a.im * w0.re;
+        pr += a.re * w.re;
+        pr -= a.im * s;
+        pi += a.re * s;
+        pi += a.im * w.re;
+        mr += a.re * w.re;
+        mr += a.im * s;
+        mi += a.im * w.re;
+        mi -= a.re * s;
+        idx += k;
+        idx -= (idx >= N) ? N : 0;
       }
-      scratch[l * ld + k] = cx<T>{re0 + re1, im0 + im1};
+      cx<T>* o = scratch + l * ld;
+      o[k] = cx<T>{pr, pi};
+      if (k > 0) o[N - k] = cx<T>{mr, mi};
     }
     __syncthreads();
     return scratch;

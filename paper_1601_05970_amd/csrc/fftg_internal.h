@@ -56,6 +56,7 @@ struct MatDev {
 // Per-RVE scalar state of the CG solve and the reductions.
 struct CgState {
   double rr, rr_new, pAp, alpha, beta;
+  double rr_prev;                      // r.r of the previous iteration (folded steps)
   double bnorm2, target2, snorm2, dnorm2;
   double eta2, floor2;
   double Sigma[6];
@@ -70,7 +71,7 @@ enum CgStatus { CG_RUNNING = 0, CG_CONVERGED = 1, CG_MAXITER = 2, CG_BREAKDOWN =
 
 // Buffer roles referenced by kernels through the descriptor.
 enum Role {
-  R_EPS_FL = 0, R_EPS_P, R_EPBAR, R_SIG, R_X, R_R, R_P, R_AP, R_USER_IN, R_USER_OUT, R_NROLES
+  R_EPS_FL = 0, R_EPS_P, R_EPBAR, R_SIG, R_X, R_R, R_P, R_AP, R_P2, R_USER_IN, R_USER_OUT, R_NROLES
 };
 
 enum Pass { P_ZF = 0, P_Y, P_X, P_ZI, P_VEC, P_NPASS };
@@ -88,10 +89,12 @@ struct RveDev {
   int mixed;                 // apply precision: 0 double, 1 float
   CgState* cg;
   double* partial;           // per-block partial sums, >= tiles of any pass
+  double* partial_rr;        // per-block partial sums of r.r in CG (disjoint from partial)
   double E[6];               // mean strain, Mandel
   double dE[6];              // load increment, Mandel
   int tiles[P_NPASS];        // tiles of each pass for this RVE
   int skip;                  // 1: RVE masked out of batched launches
+  int fold;                  // 1: CG scalar steps folded into the consumer kernels
   int xcd_remap;             // (first descriptor of a launch) spread tiles XCD-contiguously
 };
 
@@ -110,6 +113,8 @@ struct LaunchCfg {
   int lines_x;         // x pass: h-block width (x 6 components)
   int vec_per_tile;    // elementwise kernels (voxels per tile)
   int threads_z, threads_y, threads_x, threads_v;
+  int slab;            // 1: z and y transforms fused per y-z plane (k_slab_fwd / k_slab_inv)
+  int threads_s;       // slab passes
   int big_radix;       // 1 when some axis needs the radix-11/13/17 codelets
   int n0max, n1max, n2max;  // largest extents of the launch (LDS table sizing)
 };

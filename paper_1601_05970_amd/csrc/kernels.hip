@@ -97,6 +97,16 @@ __device__ double sum_partials(const double* __restrict__ p, int n, double* sh) 
   return block_sum((a0 + a1) + (a2 + a3), sh);
 }
 
+// The CG stop flag, read once per workgroup and shared through LDS: in the
+// kernels that apply a folded scalar step, tile 0 may set it while other
+// tiles of the same launch start, and all threads of a tile must agree.
+__device__ __forceinline__ int done_flag(CgState* cg) {
+  __shared__ int s_done;
+  if (threadIdx.x == 0) s_done = __hip_atomic_load(&cg->done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __syncthreads();
+  return s_done;
+}
+
 template <class T>
 struct ApType;
 template <>
@@ -161,6 +171,97 @@ struct TileLds {
   }
 };
 
+// Start of a CG iteration in the kernel that forms p <- r + beta p.  With
+// the scalar steps folded (rv.fold), every tile totals the r.r partials of
+// the last vector update (same order in each tile, so the same value),
+// applies the stopping test and forms beta; tile 0 publishes the state.
+// Other tiles of the launch read only rr_prev and iters, which it does not
+// write.  Returns false when the solve has stopped (the tile exits).  red
+// needs 10 doubles; called by the whole workgroup.
+__device__ bool cg_begin_iter(const RveDev& rv, int tile, double* red, double& beta) {
+  CgState* cg = rv.cg;
+  beta = 0.0;
+  if (!rv.fold) {
+    beta = cg->beta;
+    return true;
+  }
+  if (cg->iters == 0) return true;  // the residual pass has set p = r
+  const double rr = sum_partials(rv.partial_rr, rv.tiles[P_VEC], red);
+  if (threadIdx.x == 0) {
+    const int it = cg->iters;
+    int st = CG_RUNNING;
+    if (cg->force >= 0) {
+      if (it >= cg->force) st = CG_FORCED;
+    } else if (rr <= cg->target2) {
+      st = CG_CONVERGED;
+    } else if (it >= cg->max_iter) {
+      st = CG_MAXITER;
+    }
+    const double b = rr / cg->rr_prev;
+    red[8] = st != CG_RUNNING ? 1.0 : 0.0;
+    red[9] = b;
+    if (tile == 0) {
+      cg->rr = rr;
+      cg->rr_new = rr;
+      cg->status = st;
+      if (st != CG_RUNNING) {
+        __hip_atomic_store(&cg->done, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      } else {
+        cg->beta = b;
+      }
+    }
+  }
+  __syncthreads();
+  if (red[8] != 0.0) return false;
+  beta = red[9];
+  return true;
+}
+
+// tau = C(x):p(x) at voxel v for the input modes of the forward pass.  With
+// update_p, p = r + beta p_old is formed here and its components
+// [own_lo, own_hi) are stored to p_new (p_new may equal p_old when the
+// caller owns all six components of the voxel).
+template <class T>
+__device__ __forceinline__ void voxel_tau(const RveDev& rv, long long v, int in_mode, const double* __restrict__ in,
+                                          int update_p, double beta, const double* __restrict__ rres,
+                                          const double* p_old, double* p_new, int own_lo, int own_hi,
+                                          int tan_mode, T tau[6]) {
+  const long long nvox = rv.nvox;
+  T p[6];
+  if (in_mode == IN_CONST_DE) {
+#pragma unroll
+    for (int c = 0; c < 6; ++c) p[c] = T(rv.dE[c]);
+  } else if (update_p) {
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+      const double pn = rres[c * nvox + v] + beta * p_old[c * nvox + v];
+      if (c >= own_lo && c < own_hi) p_new[c * nvox + v] = pn;
+      p[c] = T(pn);
+    }
+  } else {
+#pragma unroll
+    for (int c = 0; c < 6; ++c) p[c] = T(in[c * nvox + v]);
+  }
+  if (tan_mode == TAN_IDENTITY) {
+#pragma unroll
+    for (int c = 0; c < 6; ++c) tau[c] = p[c];
+  } else {
+    const MatDev& mt = rv.mats[rv.phase[v]];
+    const T* tg = (const T*)rv.tang;
+    T g2, m[6];
+    if (tan_mode == TAN_ELASTIC) {
+      g2 = T(2.0 * mt.G);
+#pragma unroll
+      for (int c = 0; c < 6; ++c) m[c] = T(0);
+    } else {
+      g2 = tg[v];
+#pragma unroll
+      for (int c = 0; c < 6; ++c) m[c] = tg[(c + 1) * nvox + v];
+    }
+    tangent_apply<T>(p, T(mt.K), g2, m, tau);
+  }
+}
+
 // ------------------------------------------------------------- z forward
 // tau = C(x):p(x) (or p, or Ce:p, or C(x):dE) for a tile of rows, R2C along z.
 template <class T, int BIG>
@@ -172,9 +273,9 @@ __global__ void __launch_bounds__(256) k_zfwd(const RveDev* __restrict__ rvs, in
   const int ri = find_rve(rvs, nrve, P_ZF, tile);
   if (ri < 0) return;
   const RveDev& rv = rvs[ri];
-  if (rv.skip || (check_done && rv.cg->done)) return;
+  if (rv.skip || (check_done && done_flag(rv.cg))) return;
   const int n2 = rv.n2, H = rv.H;
-  const long long nvox = rv.nvox, nspec = rv.nspec;
+  const long long nspec = rv.nspec;
   const int nrows_tot = rv.n0 * rv.n1;
   const int row0 = tile * rows_per_tile;
   const int nrows = min(rows_per_tile, nrows_tot - row0);
@@ -182,10 +283,10 @@ __global__ void __launch_bounds__(256) k_zfwd(const RveDev* __restrict__ rvs, in
   TileLds<T> L(smem, 3 * rows_per_tile, ld, *rv.ax[2], ldmax);
 
   const double* in = (const double*)rv.buf[in_role];
-  const T* tg = (const T*)rv.tang;
-  // CG search direction update fused here: p <- r + beta p (beta = 0 on the
-  // first iteration, where the residual pass has set p = r)
-  const double beta = update_p ? rv.cg->beta : 0.0;
+  // CG search direction update fused here: p <- r + beta p (in place: this
+  // tile owns every component of its voxels)
+  double beta = 0.0;
+  if (update_p && !cg_begin_iter(rv, tile, L.red, beta)) return;
   const double* rres = (const double*)rv.buf[R_R];
   double* pw = (double*)rv.buf[R_P];
   double nrm = 0.0;
@@ -194,38 +295,8 @@ __global__ void __launch_bounds__(256) k_zfwd(const RveDev* __restrict__ rvs, in
     const int r = fn2.div(t);
     const int z = t - r * n2;
     const long long v = (long long)(row0 + r) * n2 + z;
-    T p[6], tau[6];
-    if (in_mode == IN_CONST_DE) {
-#pragma unroll
-      for (int c = 0; c < 6; ++c) p[c] = T(rv.dE[c]);
-    } else if (update_p) {
-#pragma unroll
-      for (int c = 0; c < 6; ++c) {
-        const double pn = rres[c * nvox + v] + beta * pw[c * nvox + v];
-        pw[c * nvox + v] = pn;
-        p[c] = T(pn);
-      }
-    } else {
-#pragma unroll
-      for (int c = 0; c < 6; ++c) p[c] = T(in[c * nvox + v]);
-    }
-    if (tan_mode == TAN_IDENTITY) {
-#pragma unroll
-      for (int c = 0; c < 6; ++c) tau[c] = p[c];
-    } else {
-      const MatDev& mt = rv.mats[rv.phase[v]];
-      T g2, m[6];
-      if (tan_mode == TAN_ELASTIC) {
-        g2 = T(2.0 * mt.G);
-#pragma unroll
-        for (int c = 0; c < 6; ++c) m[c] = T(0);
-      } else {
-        g2 = tg[v];
-#pragma unroll
-        for (int c = 0; c < 6; ++c) m[c] = tg[(c + 1) * nvox + v];
-      }
-      tangent_apply<T>(p, T(mt.K), g2, m, tau);
-    }
+    T tau[6];
+    voxel_tau<T>(rv, v, in_mode, in, update_p, beta, rres, pw, pw, 0, 6, tan_mode, tau);
     if (want_norm) {
 #pragma unroll
       for (int c = 0; c < 6; ++c) nrm += double(tau[c]) * double(tau[c]);
@@ -359,7 +430,7 @@ __global__ void __launch_bounds__(256) k_xpass(const RveDev* __restrict__ rvs, i
 // ------------------------------------------------------------- z inverse
 template <class T, int BIG>
 __global__ void __launch_bounds__(256) k_zinv(const RveDev* __restrict__ rvs, int nrve, int rows_per_tile, int ldmax,
-                                              int out_mode, int out_role, int check_done) {
+                                              int out_mode, int out_role, int check_done, int p_role) {
   extern __shared__ __align__(16) char smem[];
   int tile;
   const int ri = find_rve(rvs, nrve, P_ZI, tile);
@@ -400,7 +471,7 @@ __global__ void __launch_bounds__(256) k_zinv(const RveDev* __restrict__ rvs, in
   if (out_mode == OUT_CG) {
     typedef typename ApType<T>::type AT;
     AT* out = (AT*)rv.buf[R_AP];
-    const double* p = (const double*)rv.buf[R_P];
+    const double* p = (const double*)rv.buf[p_role];
     for (int t = threadIdx.x; t < nrows * n2; t += blockDim.x) {
       const int r = fn2.div(t);
       const int z = t - r * n2;
@@ -454,21 +525,223 @@ __global__ void __launch_bounds__(256) k_zinv(const RveDev* __restrict__ rvs, in
   put_partials(&s, 1, rv.partial, rv.tiles[P_ZI], tile);
 }
 
+// ------------------------------------------------------- slab passes
+// For grids whose y-z plane fits in LDS the z and y transforms of a plane
+// run in one kernel: tile (x, pr) owns Mandel components 2pr and 2pr+1 of
+// plane x, packed as the real and imaginary parts of one complex z-line per
+// y (two real transforms in one complex transform, as in the z passes).
+// LDS: tables of the z and y axes, two buffers of n1 (n2 + 1) points, Rader
+// slots and the reduction scratch.
+template <class T>
+struct SlabLds {
+  AxisLds<T> az, ay;
+  cx<T>* b0;
+  cx<T>* b1;
+  cx<T>* dc;
+  double* red;
+  __device__ SlabLds(char* base, int n1max, int n2max, const AxisDev& Pz, const AxisDev& Py) {
+    load_axis_lds<T>(Pz, base, az);
+    char* q = base + axis_lds_bytes<T>(n2max);
+    load_axis_lds<T>(Py, q, ay);
+    q += axis_lds_bytes<T>(n1max);
+    const size_t S = (size_t)n1max * (n2max + 1);
+    b0 = reinterpret_cast<cx<T>*>(q);
+    b1 = b0 + S;
+    dc = b1 + S;
+    const int nd = max(n1max, n2max + 1);
+    red = reinterpret_cast<double*>(dc + nd + (nd & 1));
+  }
+};
+
+template <class T, int BIG>
+__global__ void __launch_bounds__(512) k_slab_fwd(const RveDev* __restrict__ rvs, int nrve, int n1max, int n2max,
+                                                  int in_mode, int in_role, int tan_mode, int want_norm,
+                                                  int check_done, int update_p, int p_in, int p_out) {
+  extern __shared__ __align__(16) char smem[];
+  int tile;
+  const int ri = find_rve(rvs, nrve, P_ZF, tile);
+  if (ri < 0) return;
+  const RveDev& rv = rvs[ri];
+  if (rv.skip || (check_done && done_flag(rv.cg))) return;
+  const int n1 = rv.n1, n2 = rv.n2, H = rv.H;
+  const long long nspec = rv.nspec;
+  const int x = tile / 3, pr = tile - 3 * (tile / 3);
+  SlabLds<T> L(smem, n1max, n2max, *rv.ax[2], *rv.ax[1]);
+  double beta = 0.0;
+  if (update_p && !cg_begin_iter(rv, tile, L.red, beta)) return;
+  const double* in = (const double*)rv.buf[in_role];
+  const double* rres = (const double*)rv.buf[R_R];
+  const double* pin = (const double*)rv.buf[p_in];
+  double* pout = (double*)rv.buf[p_out];
+  const long long v0 = (long long)x * n1 * n2;
+  const int npl = n1 * n2;
+  double nrm = 0.0;
+  for (int t = threadIdx.x; t < npl; t += blockDim.x) {
+    T tau[6];
+    voxel_tau<T>(rv, v0 + t, in_mode, in, update_p, beta, rres, pin, pout, 2 * pr, 2 * pr + 2, tan_mode, tau);
+    const T a = tau[2 * pr], b = tau[2 * pr + 1];
+    if (want_norm) nrm += double(a) * double(a) + double(b) * double(b);
+    L.b0[t] = cx<T>{a, b};  // z-line y at y * n2
+  }
+  __syncthreads();
+  cx<T>* res = line_fft<-1, T, BIG>(L.b0, L.b1, n2, n1, L.az, L.dc);
+  cx<T>* oth = (res == L.b0) ? L.b1 : L.b0;
+  // untangle into y-lines: component 2pr + c2, frequency k -> line c2 * H + k
+  const FastDiv fH(H), fn1(n1);
+  for (int t = threadIdx.x; t < n1 * H; t += blockDim.x) {
+    const int y = fH.div(t);
+    const int k = t - y * H;
+    const cx<T> zk = res[y * n2 + k];
+    const cx<T> zm = res[y * n2 + (k == 0 ? 0 : n2 - k)];
+    oth[k * n1 + y] = cx<T>{T(0.5) * (zk.re + zm.re), T(0.5) * (zk.im - zm.im)};
+    oth[(H + k) * n1 + y] = cx<T>{T(0.5) * (zk.im + zm.im), T(-0.5) * (zk.re - zm.re)};
+  }
+  __syncthreads();
+  cx<T>* res2 = line_fft<-1, T, BIG>(oth, res, n1, 2 * H, L.ay, L.dc);
+  cx<T>* spec = (cx<T>*)rv.spec;
+  for (int t = threadIdx.x; t < 2 * n1 * H; t += blockDim.x) {
+    const int cy = fH.div(t);
+    const int k = t - cy * H;
+    const int c2 = fn1.div(cy), y = cy - c2 * n1;
+    spec[(2 * pr + c2) * nspec + ((long long)x * n1 + y) * H + k] = res2[(c2 * H + k) * n1 + y];
+  }
+  if (want_norm) {
+    const double s = block_sum(nrm, L.red);
+    put_partials(&s, 1, rv.partial, rv.tiles[P_ZF], tile);
+  }
+}
+
+template <class T, int BIG>
+__global__ void __launch_bounds__(512) k_slab_inv(const RveDev* __restrict__ rvs, int nrve, int n1max, int n2max,
+                                                  int out_mode, int out_role, int check_done, int p_role) {
+  extern __shared__ __align__(16) char smem[];
+  int tile;
+  const int ri = find_rve(rvs, nrve, P_ZI, tile);
+  if (ri < 0) return;
+  const RveDev& rv = rvs[ri];
+  if (rv.skip || (check_done && done_flag(rv.cg))) return;
+  const int n1 = rv.n1, n2 = rv.n2, H = rv.H;
+  const long long nvox = rv.nvox, nspec = rv.nspec;
+  const int x = tile / 3, pr = tile - 3 * (tile / 3);
+  SlabLds<T> L(smem, n1max, n2max, *rv.ax[2], *rv.ax[1]);
+  const cx<T>* spec = (const cx<T>*)rv.spec;
+  const FastDiv fH(H), fn1(n1), fn2(n2);
+  for (int t = threadIdx.x; t < 2 * n1 * H; t += blockDim.x) {
+    const int cy = fH.div(t);
+    const int k = t - cy * H;
+    const int c2 = fn1.div(cy), y = cy - c2 * n1;
+    L.b0[(c2 * H + k) * n1 + y] = spec[(2 * pr + c2) * nspec + ((long long)x * n1 + y) * H + k];
+  }
+  __syncthreads();
+  cx<T>* res = line_fft<1, T, BIG>(L.b0, L.b1, n1, 2 * H, L.ay, L.dc);
+  cx<T>* oth = (res == L.b0) ? L.b1 : L.b0;
+  // z-line y: Z_z = A_z + i B_z, Z_{n2-k} = conj(A_k) + i conj(B_k)
+  for (int t = threadIdx.x; t < n1 * n2; t += blockDim.x) {
+    const int y = fn2.div(t);
+    const int z = t - y * n2;
+    cx<T> Zv;
+    if (z < H) {
+      const cx<T> A = res[z * n1 + y], B = res[(H + z) * n1 + y];
+      Zv = cx<T>{A.re - B.im, A.im + B.re};
+    } else {
+      const int k = n2 - z;
+      const cx<T> A = res[k * n1 + y], B = res[(H + k) * n1 + y];
+      Zv = cx<T>{A.re + B.im, -A.im + B.re};
+    }
+    oth[t] = Zv;
+  }
+  __syncthreads();
+  cx<T>* res2 = line_fft<1, T, BIG>(oth, res, n2, n1, L.az, L.dc);
+  const long long v0 = (long long)x * n1 * n2;
+  const int c0 = 2 * pr, c1 = 2 * pr + 1;
+  double dot = 0.0;
+  if (out_mode == OUT_CG) {
+    typedef typename ApType<T>::type AT;
+    AT* out = (AT*)rv.buf[R_AP];
+    const double* p = (const double*)rv.buf[p_role];
+    for (int t = threadIdx.x; t < n1 * n2; t += blockDim.x) {
+      const long long v = v0 + t;
+      const cx<T> w = res2[t];
+      const AT a0 = AT(w.re), a1 = AT(w.im);
+      out[c0 * nvox + v] = a0;
+      out[c1 * nvox + v] = a1;
+      dot += p[c0 * nvox + v] * double(a0) + p[c1 * nvox + v] * double(a1);
+    }
+  } else if (out_mode == OUT_RESIDUAL) {
+    double* rr = (double*)rv.buf[R_R];
+    double* pp = (double*)rv.buf[R_P];
+    double* xx = (double*)rv.buf[R_X];
+    for (int t = threadIdx.x; t < n1 * n2; t += blockDim.x) {
+      const long long v = v0 + t;
+      const cx<T> w = res2[t];
+      const double a0 = double(w.re), a1 = double(w.im);
+      rr[c0 * nvox + v] = a0;
+      rr[c1 * nvox + v] = a1;
+      pp[c0 * nvox + v] = a0;
+      pp[c1 * nvox + v] = a1;
+      xx[c0 * nvox + v] = 0.0;
+      xx[c1 * nvox + v] = 0.0;
+      dot += a0 * a0 + a1 * a1;
+    }
+  } else {
+    T* out = (T*)rv.buf[out_role];
+    for (int t = threadIdx.x; t < n1 * n2; t += blockDim.x) {
+      const long long v = v0 + t;
+      const cx<T> w = res2[t];
+      out[c0 * nvox + v] = w.re;
+      out[c1 * nvox + v] = w.im;
+    }
+    return;
+  }
+  const double s = block_sum(dot, L.red);
+  put_partials(&s, 1, rv.partial, rv.tiles[P_ZI], tile);
+}
+
 // ------------------------------------------------------ CG vector updates
 // x += alpha p; r -= alpha Ap; per-tile partials of r.r.
 template <class AT>
-__global__ void __launch_bounds__(256) k_cg_xr(const RveDev* __restrict__ rvs, int nrve, int vox_per_tile) {
+__global__ void __launch_bounds__(256) k_cg_xr(const RveDev* __restrict__ rvs, int nrve, int vox_per_tile,
+                                               int p_role) {
   __shared__ double red[16];
   int tile;
   const int ri = find_rve(rvs, nrve, P_VEC, tile);
   if (ri < 0) return;
   const RveDev& rv = rvs[ri];
-  if (rv.skip || rv.cg->done) return;
+  if (rv.skip || done_flag(rv.cg)) return;
   const long long nvox = rv.nvox;
-  const double alpha = rv.cg->alpha;
+  CgState* cg = rv.cg;
+  double alpha;
+  if (!rv.fold) {
+    alpha = cg->alpha;
+  } else {
+    // Folded step: every tile totals the p.Ap partials of the product and
+    // forms alpha = r.r / p.Ap; tile 0 publishes the state (other tiles
+    // read only rr, which no tile of this launch writes).
+    const double pap = sum_partials(rv.partial, rv.tiles[P_ZI], red);
+    if (threadIdx.x == 0) {
+      const double rr = cg->rr;
+      const bool brk = !(pap > 0.0);
+      red[8] = brk ? 1.0 : 0.0;
+      red[9] = rr / pap;
+      if (tile == 0) {
+        cg->pAp = pap;
+        if (brk) {
+          cg->status = CG_BREAKDOWN;
+          __hip_atomic_store(&cg->done, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+          cg->alpha = rr / pap;
+          cg->rr_prev = rr;
+          cg->iters += 1;
+        }
+      }
+    }
+    __syncthreads();
+    if (red[8] != 0.0) return;
+    alpha = red[9];
+  }
   double* __restrict__ x = (double*)rv.buf[R_X];
   double* __restrict__ r = (double*)rv.buf[R_R];
-  const double* __restrict__ p = (const double*)rv.buf[R_P];
+  const double* __restrict__ p = (const double*)rv.buf[p_role];
   const AT* __restrict__ ap = (const AT*)rv.buf[R_AP];
   const long long v0 = (long long)tile * vox_per_tile;
   const int nv = (int)min((long long)vox_per_tile, nvox - v0);
@@ -492,7 +765,7 @@ __global__ void __launch_bounds__(256) k_cg_xr(const RveDev* __restrict__ rvs, i
     }
   }
   const double s = block_sum(acc, red);
-  put_partials(&s, 1, rv.partial, rv.tiles[P_VEC], tile);
+  put_partials(&s, 1, rv.partial_rr, rv.tiles[P_VEC], tile);
 }
 
 // eps* += x (Algorithm 1, iterative update) and ||x||^2.
@@ -634,12 +907,13 @@ __global__ void __launch_bounds__(256) k_finalize(const RveDev* __restrict__ rvs
   const RveDev& rv = rvs[ri];
   if (rv.skip) return;
   CgState* cg = rv.cg;
-  if ((step == FIN_PAP || step == FIN_RR) && cg->done) return;
+  if ((step == FIN_PAP || step == FIN_RR) && (rv.fold || cg->done)) return;
   const int pass = step == FIN_SNORM ? P_ZF : ((step == FIN_RESID || step == FIN_PAP) ? P_ZI : P_VEC);
   const int nt = rv.tiles[pass];
   const int nv = step == FIN_SIGMA ? 6 : 1;
+  const double* part = step == FIN_RR ? rv.partial_rr : rv.partial;
   double tot[6];
-  for (int i = 0; i < nv; ++i) tot[i] = sum_partials(rv.partial + (size_t)i * nt, nt, red);
+  for (int i = 0; i < nv; ++i) tot[i] = sum_partials(part + (size_t)i * nt, nt, red);
   if (threadIdx.x != 0) return;
   const double t = tot[0];
   switch (step) {
@@ -742,6 +1016,13 @@ size_t lds_y(int mixed, int lines, int n1) {
   return mixed ? tile_lds<float>(lines, n1) + axis_lds_bytes<float>(n1)
                : tile_lds<double>(lines, n1) + axis_lds_bytes<double>(n1);
 }
+template <class T>
+static size_t slab_lds(int n1, int n2) {
+  const int nd = n1 > n2 + 1 ? n1 : n2 + 1;
+  return axis_lds_bytes<T>(n2) + axis_lds_bytes<T>(n1) + (size_t)2 * n1 * (n2 + 1) * sizeof(cx<T>) +
+         (size_t)(nd + 2) * sizeof(cx<T>) + 16 * sizeof(double) + 64;
+}
+size_t lds_slab(int mixed, int n1, int n2) { return mixed ? slab_lds<float>(n1, n2) : slab_lds<double>(n1, n2); }
 size_t lds_x(int mixed, int lines, int n0) {
   return mixed ? tile_lds<float>(6 * lines, n0) + axis_lds_bytes<float>(n0)
                : tile_lds<double>(6 * lines, n0) + axis_lds_bytes<double>(n0);
@@ -765,8 +1046,21 @@ static void xpass_go(dim3 G, dim3 B, size_t lds, hipStream_t s, const RveDev* rv
 }
 template <class T, int BIG>
 static void zinv_go(dim3 G, dim3 B, size_t lds, hipStream_t s, const RveDev* rv, int nrve, int rows, int ldmax,
-                    int out_mode, int out_role, int check_done) {
-  hipLaunchKernelGGL((k_zinv<T, BIG>), G, B, lds, s, rv, nrve, rows, ldmax, out_mode, out_role, check_done);
+                    int out_mode, int out_role, int check_done, int p_role) {
+  hipLaunchKernelGGL((k_zinv<T, BIG>), G, B, lds, s, rv, nrve, rows, ldmax, out_mode, out_role, check_done, p_role);
+}
+template <class T, int BIG>
+static void slab_fwd_go(dim3 G, dim3 B, size_t lds, hipStream_t s, const RveDev* rv, int nrve, int n1max, int n2max,
+                        int in_mode, int in_role, int tan_mode, int want_norm, int check_done, int update_p, int p_in,
+                        int p_out) {
+  hipLaunchKernelGGL((k_slab_fwd<T, BIG>), G, B, lds, s, rv, nrve, n1max, n2max, in_mode, in_role, tan_mode,
+                     want_norm, check_done, update_p, p_in, p_out);
+}
+template <class T, int BIG>
+static void slab_inv_go(dim3 G, dim3 B, size_t lds, hipStream_t s, const RveDev* rv, int nrve, int n1max, int n2max,
+                        int out_mode, int out_role, int check_done, int p_role) {
+  hipLaunchKernelGGL((k_slab_inv<T, BIG>), G, B, lds, s, rv, nrve, n1max, n2max, out_mode, out_role, check_done,
+                     p_role);
 }
 
 #define DISPATCH_TB(fn, ...)                          \
@@ -822,19 +1116,37 @@ hipError_t launch_xpass(int mixed, const RveDev* rv, int nrve, int tiles, const 
 }
 
 hipError_t launch_zinv(int mixed, const RveDev* rv, int nrve, int tiles, const LaunchCfg& cfg, size_t lds,
-                       int out_mode, int out_role, int check_done, hipStream_t s) {
+                       int out_mode, int out_role, int check_done, int p_role, hipStream_t s) {
   if (tiles <= 0) return hipSuccess;
   DISPATCH_TB(zinv_go, dim3(tiles), dim3(cfg.threads_z), lds, s, rv, nrve, cfg.rows_per_tile, cfg.n2max, out_mode,
-              out_role, check_done);
+              out_role, check_done, p_role);
   return hipGetLastError();
 }
 
-hipError_t launch_cg_xr(int mixed, const RveDev* rv, int nrve, int tiles, const LaunchCfg& cfg, hipStream_t s) {
+hipError_t launch_slab_fwd(int mixed, const RveDev* rv, int nrve, int tiles, const LaunchCfg& cfg, size_t lds,
+                           int in_mode, int in_role, int tan_mode, int want_norm, int check_done, int update_p,
+                           int p_in, int p_out, hipStream_t s) {
+  if (tiles <= 0) return hipSuccess;
+  DISPATCH_TB(slab_fwd_go, dim3(tiles), dim3(cfg.threads_s), lds, s, rv, nrve, cfg.n1max, cfg.n2max, in_mode,
+              in_role, tan_mode, want_norm, check_done, update_p, p_in, p_out);
+  return hipGetLastError();
+}
+
+hipError_t launch_slab_inv(int mixed, const RveDev* rv, int nrve, int tiles, const LaunchCfg& cfg, size_t lds,
+                           int out_mode, int out_role, int check_done, int p_role, hipStream_t s) {
+  if (tiles <= 0) return hipSuccess;
+  DISPATCH_TB(slab_inv_go, dim3(tiles), dim3(cfg.threads_s), lds, s, rv, nrve, cfg.n1max, cfg.n2max, out_mode,
+              out_role, check_done, p_role);
+  return hipGetLastError();
+}
+
+hipError_t launch_cg_xr(int mixed, const RveDev* rv, int nrve, int tiles, const LaunchCfg& cfg, int p_role,
+                        hipStream_t s) {
   if (tiles <= 0) return hipSuccess;
   if (mixed)
-    hipLaunchKernelGGL(k_cg_xr<float>, dim3(tiles), dim3(cfg.threads_v), 0, s, rv, nrve, cfg.vec_per_tile);
+    hipLaunchKernelGGL(k_cg_xr<float>, dim3(tiles), dim3(cfg.threads_v), 0, s, rv, nrve, cfg.vec_per_tile, p_role);
   else
-    hipLaunchKernelGGL(k_cg_xr<double>, dim3(tiles), dim3(cfg.threads_v), 0, s, rv, nrve, cfg.vec_per_tile);
+    hipLaunchKernelGGL(k_cg_xr<double>, dim3(tiles), dim3(cfg.threads_v), 0, s, rv, nrve, cfg.vec_per_tile, p_role);
   return hipGetLastError();
 }
 

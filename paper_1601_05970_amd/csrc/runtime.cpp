@@ -31,8 +31,15 @@ hipError_t launch_ypass(int mixed, int dir, const RveDev* rv, int nrve, int tile
 hipError_t launch_xpass(int mixed, const RveDev* rv, int nrve, int tiles, const LaunchCfg& cfg, size_t lds,
                         double scale, int check_done, hipStream_t s);
 hipError_t launch_zinv(int mixed, const RveDev* rv, int nrve, int tiles, const LaunchCfg& cfg, size_t lds,
-                       int out_mode, int out_role, int check_done, hipStream_t s);
-hipError_t launch_cg_xr(int mixed, const RveDev* rv, int nrve, int tiles, const LaunchCfg& cfg, hipStream_t s);
+                       int out_mode, int out_role, int check_done, int p_role, hipStream_t s);
+size_t lds_slab(int mixed, int n1, int n2);
+hipError_t launch_slab_fwd(int mixed, const RveDev* rv, int nrve, int tiles, const LaunchCfg& cfg, size_t lds,
+                           int in_mode, int in_role, int tan_mode, int want_norm, int check_done, int update_p,
+                           int p_in, int p_out, hipStream_t s);
+hipError_t launch_slab_inv(int mixed, const RveDev* rv, int nrve, int tiles, const LaunchCfg& cfg, size_t lds,
+                           int out_mode, int out_role, int check_done, int p_role, hipStream_t s);
+hipError_t launch_cg_xr(int mixed, const RveDev* rv, int nrve, int tiles, const LaunchCfg& cfg, int p_role,
+                        hipStream_t s);
 hipError_t launch_newton_update(const RveDev* rv, int nrve, int tiles, const LaunchCfg& cfg, hipStream_t s);
 hipError_t launch_finalize(const RveDev* rv, int nrve, int step, hipStream_t s);
 hipError_t launch_constitutive(int mixed, const RveDev* rv, int nrve, int tiles, const LaunchCfg& cfg,
@@ -278,6 +285,7 @@ struct fftg_plan_s {
   uint8_t* d_phase;
   void* spec;
   double *sig, *x, *r, *p;
+  double* p2;        // second search-direction buffer (slab passes only; else null)
   void* ap;
   double* partial;
   CgState* cg;
@@ -326,6 +334,20 @@ static long env_long(const char* name, long dflt) {
   return (end && *end == 0 && v > 0) ? v : dflt;
 }
 
+// The slab passes hold two y-z planes of one component pair in LDS; the
+// FP64 size decides (mixed plans run their residual products in FP64).
+constexpr size_t kSlabLdsMax = 160 * 1024 - 1024;
+static bool slab_fits(int n1, int n2) { return lds_slab(0, n1, n2) <= kSlabLdsMax; }
+
+// FFTG_SLAB: 0 never uses the slab passes, 1 (default) lets the autotuner
+// choose them when faster, 2 uses them whenever the plane fits in LDS.
+static int slab_mode() {
+  const char* s = getenv("FFTG_SLAB");
+  if (!s || !*s) return 1;
+  const long v = strtol(s, nullptr, 10);
+  return (v >= 0 && v <= 2) ? (int)v : 1;
+}
+
 static int threads_for(long long points) {
   return points <= 192 ? 64 : (points <= 640 ? 128 : 256);
 }
@@ -365,6 +387,8 @@ static LaunchCfg choose_cfg(const GridSum& gs) {
   v = std::max(256LL, std::min(8192LL, (v + 255) / 256 * 256));
   c.vec_per_tile = (int)v;
   c.threads_v = 256;
+  c.slab = (slab_mode() == 2 && slab_fits(gs.n1, gs.n2)) ? 1 : 0;
+  c.threads_s = 256;
   c.big_radix = gs.big;
   c.n0max = gs.n0;
   c.n1max = gs.n1;
@@ -375,9 +399,14 @@ static LaunchCfg choose_cfg(const GridSum& gs) {
 static void compute_tiles(const LaunchCfg& c, int n0, int n1, int n2, long long nvox, int tiles[P_NPASS]) {
   const int H = (n2 + 1) / 2;
   const int rows = n0 * n1;
-  tiles[P_ZF] = (rows + c.rows_per_tile - 1) / c.rows_per_tile;
-  tiles[P_ZI] = tiles[P_ZF];
-  tiles[P_Y] = 6 * n0 * ((H + c.lines_y - 1) / c.lines_y);
+  if (c.slab) {
+    tiles[P_ZF] = tiles[P_ZI] = 3 * n0;  // (plane, component pair)
+    tiles[P_Y] = 0;
+  } else {
+    tiles[P_ZF] = (rows + c.rows_per_tile - 1) / c.rows_per_tile;
+    tiles[P_ZI] = tiles[P_ZF];
+    tiles[P_Y] = 6 * n0 * ((H + c.lines_y - 1) / c.lines_y);
+  }
   tiles[P_X] = n1 * ((H + c.lines_x - 1) / c.lines_x);
   tiles[P_VEC] = (int)((nvox + c.vec_per_tile - 1) / c.vec_per_tile);
 }
@@ -398,6 +427,7 @@ static size_t plan_bytes(int n0, int n1, int n2, int mixed) {
   size_t b = 0;
   b += 6 * nspec * 16;                   // spectrum (complex double)
   b += 4 * 6 * nvox * 8;                 // sig, x, r, p
+  if (slab_fits(n1, n2)) b += 6 * nvox * 8;  // second p buffer
   b += 6 * nvox * (mixed ? 4 : 8);       // Ap
   b += nvox;                             // phase
   b += 6 * (size_t)max_tiles_any(n0, n1, n2, nvox) * 8 + 4096;
@@ -514,6 +544,8 @@ fftg_status fftg_plan_create(fftg_plan* out, int n0, int n1, int n2, const uint8
   PLAN_TRY(dalloc(pl, &pl->x, (size_t)6 * nvox * 8));
   PLAN_TRY(dalloc(pl, &pl->r, (size_t)6 * nvox * 8));
   PLAN_TRY(dalloc(pl, &pl->p, (size_t)6 * nvox * 8));
+  pl->p2 = nullptr;
+  if (slab_fits(n1, n2)) PLAN_TRY(dalloc(pl, &pl->p2, (size_t)6 * nvox * 8));
   PLAN_TRY(dalloc(pl, &pl->ap, (size_t)6 * nvox * (pl->mixed ? 4 : 8)));
   pl->max_tiles = max_tiles_any(n0, n1, n2, nvox);
   PLAN_TRY(dalloc(pl, &pl->partial, (size_t)6 * pl->max_tiles * 8 + 64));
@@ -650,6 +682,8 @@ struct Group {
   LaunchCfg cfg;
   size_t lds_zf, lds_y, lds_x;          // FP64 launches
   size_t lds_zf32, lds_y32, lds_x32;    // FP32 launches
+  size_t lds_s = 0, lds_s32 = 0;        // slab passes (FP64, FP32)
+  int cg_par = 0;                       // slab passes: CG iteration parity (which p buffer is current)
   int total[P_NPASS];
   std::vector<RveDev> h;         // host copies
   RveDev* d;                     // device array
@@ -663,6 +697,7 @@ struct Group {
   std::vector<fftg_history> hists;
   bool own;                      // device arrays owned by the group
   double active_vox;             // voxels of the members not skipped
+  bool need_fin = false;         // some active member runs the CG steps in k_finalize
   int xcd_remap;
 };
 
@@ -679,6 +714,7 @@ static void fill_desc(RveDev& rv, fftg_plan pl, fftg_history h, const LaunchCfg&
   rv.buf[R_X] = pl->x;
   rv.buf[R_R] = pl->r;
   rv.buf[R_P] = pl->p;
+  rv.buf[R_P2] = pl->p2;
   rv.buf[R_AP] = pl->ap;
   if (h) {
     rv.buf[R_EPS_FL] = h->eps_fl;
@@ -694,6 +730,7 @@ static void fill_desc(RveDev& rv, fftg_plan pl, fftg_history h, const LaunchCfg&
   rv.mixed = pl->mixed;
   rv.cg = pl->cg;
   rv.partial = pl->partial;
+  rv.partial_rr = pl->partial + pl->max_tiles;
   compute_tiles(cfg, rv.n0, rv.n1, rv.n2, rv.nvox, rv.tiles);
 }
 
@@ -723,6 +760,8 @@ static void group_set_cfg(Group& g, const LaunchCfg& c) {
   g.lds_zf32 = lds_z(1, c.rows_per_tile, n2);
   g.lds_y32 = lds_y(1, c.lines_y, n1);
   g.lds_x32 = lds_x(1, c.lines_x, n0);
+  g.lds_s = lds_slab(0, n1, n2);
+  g.lds_s32 = lds_slab(1, n1, n2);
   for (auto& rv : g.h)
     if (!rv.skip) compute_tiles(c, rv.n0, rv.n1, rv.n2, rv.nvox, rv.tiles);
 }
@@ -751,6 +790,13 @@ static void group_totals(Group& g) {
     prof_end(pi_, g.stream, g.active_vox);           \
   } while (0)
 
+// The CG scalar steps (alpha from p.Ap, the stopping test and beta from
+// r.r) run inside the consumer kernels when every one of their tiles can
+// total the producer's partials cheaply: the L2 reads of that redundant sum
+// grow as (product tiles) x (vector tiles).  Larger RVEs use k_finalize.
+constexpr long long kFoldMax = 1LL << 23;
+static bool fold_ok(const RveDev& rv) { return (long long)rv.tiles[P_ZI] * rv.tiles[P_VEC] <= kFoldMax; }
+
 // Uploads the host descriptors (stream-ordered, through a pinned slot).
 static fftg_status group_upload(Group& g) {
   const size_t n = g.h.size();
@@ -758,7 +804,13 @@ static fftg_status group_upload(Group& g) {
   g.next = (g.next + 1) & 3;
   HIP_TRY(hipEventSynchronize(g.ev[slot]));
   char* st = reinterpret_cast<char*>(g.h_pinned) + slot * desc_bytes(n);
-  for (size_t i = 0; i < n; ++i) g.h[i].xcd_remap = g.xcd_remap;
+  g.need_fin = false;
+  for (size_t i = 0; i < n; ++i) {
+    RveDev& rv = g.h[i];
+    rv.xcd_remap = g.xcd_remap;
+    rv.fold = fold_ok(rv) ? 1 : 0;
+    if (!rv.skip && !rv.fold) g.need_fin = true;
+  }
   memcpy(st, g.h.data(), n * sizeof(RveDev));
   int* tab = reinterpret_cast<int*>(st + n * sizeof(RveDev));
   for (int p = 0; p < P_NPASS; ++p) {
@@ -788,21 +840,40 @@ static void set_skip(Group& g, size_t i, bool skip) {
 }
 
 // -------------------------------------------------------- apply sequences
-// G:(C:in) into the out mode; in_role / const dE input.
+// G:(C:in) into the out mode; in_role / const dE input.  With update_p the
+// product forms p <- r + beta p from p_in into p_out first (the 5-pass
+// schedule updates in place and takes p_in = p_out = R_P); the CG dot of
+// OUT_CG uses p_out.
 static fftg_status enqueue_apply(Group& g, int mixed, int in_mode, int in_role, int tan_mode, int want_norm,
-                                 int out_mode, int out_role, double scale, int check_done, int update_p = 0) {
+                                 int out_mode, int out_role, double scale, int check_done, int update_p = 0,
+                                 int p_in = R_P, int p_out = R_P) {
   const int nr = (int)g.h.size();
-  const size_t lz = mixed ? g.lds_zf32 : g.lds_zf, ly = mixed ? g.lds_y32 : g.lds_y;
   const size_t lx = mixed ? g.lds_x32 : g.lds_x;
-  PROF_LAUNCH(FFTG_KERNEL_ZFWD, launch_zfwd(mixed, g.d, nr, g.total[P_ZF], g.cfg, lz, in_mode, in_role, tan_mode,
-                                            want_norm, check_done, update_p, g.stream));
-  if (want_norm) PROF_LAUNCH(FFTG_KERNEL_FINALIZE, launch_finalize(g.d, nr, FIN_SNORM, g.stream));
-  PROF_LAUNCH(FFTG_KERNEL_Y_FWD, launch_ypass(mixed, -1, g.d, nr, g.total[P_Y], g.cfg, ly, check_done, g.stream));
+  if (g.cfg.slab) {
+    const size_t ls = mixed ? g.lds_s32 : g.lds_s;
+    PROF_LAUNCH(FFTG_KERNEL_ZFWD, launch_slab_fwd(mixed, g.d, nr, g.total[P_ZF], g.cfg, ls, in_mode, in_role,
+                                                  tan_mode, want_norm, check_done, update_p, p_in, p_out,
+                                                  g.stream));
+  } else {
+    const size_t lz = mixed ? g.lds_zf32 : g.lds_zf, ly = mixed ? g.lds_y32 : g.lds_y;
+    PROF_LAUNCH(FFTG_KERNEL_ZFWD, launch_zfwd(mixed, g.d, nr, g.total[P_ZF], g.cfg, lz, in_mode, in_role, tan_mode,
+                                              want_norm, check_done, update_p, g.stream));
+    if (want_norm) PROF_LAUNCH(FFTG_KERNEL_FINALIZE, launch_finalize(g.d, nr, FIN_SNORM, g.stream));
+    PROF_LAUNCH(FFTG_KERNEL_Y_FWD, launch_ypass(mixed, -1, g.d, nr, g.total[P_Y], g.cfg, ly, check_done, g.stream));
+  }
+  if (g.cfg.slab && want_norm) PROF_LAUNCH(FFTG_KERNEL_FINALIZE, launch_finalize(g.d, nr, FIN_SNORM, g.stream));
   PROF_LAUNCH(FFTG_KERNEL_X_PROJ, launch_xpass(mixed, g.d, nr, g.total[P_X], g.cfg, lx, scale, check_done, g.stream));
-  PROF_LAUNCH(FFTG_KERNEL_Y_INV, launch_ypass(mixed, 1, g.d, nr, g.total[P_Y], g.cfg, ly, check_done, g.stream));
-  PROF_LAUNCH(FFTG_KERNEL_ZINV, launch_zinv(mixed, g.d, nr, g.total[P_ZI], g.cfg, lz, out_mode, out_role,
-                                            check_done, g.stream));
-  if (out_mode == OUT_CG || out_mode == OUT_RESIDUAL)
+  if (g.cfg.slab) {
+    const size_t ls = mixed ? g.lds_s32 : g.lds_s;
+    PROF_LAUNCH(FFTG_KERNEL_ZINV, launch_slab_inv(mixed, g.d, nr, g.total[P_ZI], g.cfg, ls, out_mode, out_role,
+                                                  check_done, p_out, g.stream));
+  } else {
+    const size_t lz = mixed ? g.lds_zf32 : g.lds_zf, ly = mixed ? g.lds_y32 : g.lds_y;
+    PROF_LAUNCH(FFTG_KERNEL_Y_INV, launch_ypass(mixed, 1, g.d, nr, g.total[P_Y], g.cfg, ly, check_done, g.stream));
+    PROF_LAUNCH(FFTG_KERNEL_ZINV, launch_zinv(mixed, g.d, nr, g.total[P_ZI], g.cfg, lz, out_mode, out_role,
+                                              check_done, p_out, g.stream));
+  }
+  if (out_mode == OUT_RESIDUAL || (out_mode == OUT_CG && g.need_fin))
     PROF_LAUNCH(FFTG_KERNEL_FINALIZE,
                 launch_finalize(g.d, nr, out_mode == OUT_CG ? FIN_PAP : FIN_RESID, g.stream));
   return FFTG_OK;
@@ -811,11 +882,19 @@ static fftg_status enqueue_apply(Group& g, int mixed, int in_mode, int in_role, 
 static fftg_status enqueue_cg_iters(Group& g, int iters) {
   const int nr = (int)g.h.size();
   for (int i = 0; i < iters; ++i) {
-    // p <- r + beta p is fused into the first pass of the product
-    fftg_status st = enqueue_apply(g, g.mixed, IN_ROLE, R_P, TAN_CURRENT, 0, OUT_CG, R_AP, 1.0, 1, 1);
+    // p <- r + beta p is fused into the first pass of the product.  The slab
+    // passes own two components of a voxel per tile, so p alternates between
+    // two buffers (the residual pass leaves p in R_P at parity 0).
+    int p_in = R_P, p_out = R_P;
+    if (g.cfg.slab) {
+      p_in = g.cg_par ? R_P2 : R_P;
+      p_out = g.cg_par ? R_P : R_P2;
+      g.cg_par ^= 1;
+    }
+    fftg_status st = enqueue_apply(g, g.mixed, IN_ROLE, R_P, TAN_CURRENT, 0, OUT_CG, R_AP, 1.0, 1, 1, p_in, p_out);
     if (st != FFTG_OK) return st;
-    PROF_LAUNCH(FFTG_KERNEL_CG_XR, launch_cg_xr(g.mixed, g.d, nr, g.total[P_VEC], g.cfg, g.stream));
-    PROF_LAUNCH(FFTG_KERNEL_FINALIZE, launch_finalize(g.d, nr, FIN_RR, g.stream));
+    PROF_LAUNCH(FFTG_KERNEL_CG_XR, launch_cg_xr(g.mixed, g.d, nr, g.total[P_VEC], g.cfg, p_out, g.stream));
+    if (g.need_fin) PROF_LAUNCH(FFTG_KERNEL_FINALIZE, launch_finalize(g.d, nr, FIN_RR, g.stream));
   }
   return FFTG_OK;
 }
@@ -858,6 +937,7 @@ static double cg_remaining(const Group& g, const CgState* cs, int chunk_max) {
 // stopping exactly at convergence.
 static fftg_status run_cg(Group& g, int chunk_max) {
   const size_t n = g.h.size();
+  g.cg_par = 0;
   struct Snap {
     int slot;   // 1 or 2
     int after;  // iterations enqueued after this snapshot
@@ -1049,7 +1129,8 @@ static std::mutex g_tune_mutex;
 static std::string tune_key(const Group& g, const GridSum& gs) {
   int lg = 0;
   while ((1LL << (lg + 1)) <= gs.vox) ++lg;
-  return std::to_string(g.mixed) + ":" + std::to_string(env_long("FFTG_LDS_KB", 64)) + ":b" +
+  return std::to_string(g.mixed) + ":" + std::to_string(env_long("FFTG_LDS_KB", 64)) + ":s" +
+         std::to_string(slab_mode()) + ":b" +
          std::to_string(gs.big ? 1 : 0) + ":" + std::to_string(gs.n0) + "x" + std::to_string(gs.n1) + "x" +
          std::to_string(gs.n2) + ":n" + std::to_string(g.plans.size() > 1 ? 1 : 0) + ":v" + std::to_string(lg);
 }
@@ -1058,6 +1139,8 @@ static std::string tune_key(const Group& g, const GridSum& gs) {
 // (fields that describe the group itself, such as the codelet set and the
 // largest extents, always come from the group).
 static LaunchCfg with_tuned_tiles(LaunchCfg c, const LaunchCfg& t) {
+  c.slab = t.slab;
+  c.threads_s = t.threads_s;
   c.rows_per_tile = t.rows_per_tile;
   c.threads_z = t.threads_z;
   c.lines_y = t.lines_y;
@@ -1113,6 +1196,7 @@ static fftg_status group_autotune(Group& g) {
   const int thr[3] = {64, 128, 256};
   const int reps = gs.vox > 4000000 ? 2 : 4;
   fftg_status st;
+  double t_zpair = 1e30, t_y = 1e30;
   // z passes: rows per tile and threads (zfwd + zinv timed together)
   {
     double tbest = 1e30;
@@ -1130,7 +1214,7 @@ static fftg_status group_autotune(Group& g) {
           hipError_t e = launch_zfwd(mixed, g.d, nr, g.total[P_ZF], g.cfg, lz, IN_ROLE, R_P, TAN_ELASTIC, 0, 0, 0,
                                      g.stream);
           if (e != hipSuccess) return e;
-          return launch_zinv(mixed, g.d, nr, g.total[P_ZI], g.cfg, lz, OUT_PLAIN, R_AP, 0, g.stream);
+          return launch_zinv(mixed, g.d, nr, g.total[P_ZI], g.cfg, lz, OUT_PLAIN, R_AP, 0, R_P, g.stream);
         });
         if (ms < tbest) {
           tbest = ms;
@@ -1140,6 +1224,7 @@ static fftg_status group_autotune(Group& g) {
     }
     best.rows_per_tile = cb.rows_per_tile;
     best.threads_z = cb.threads_z;
+    t_zpair = tbest;
   }
   // y pass
   {
@@ -1165,6 +1250,7 @@ static fftg_status group_autotune(Group& g) {
     }
     best.lines_y = cb.lines_y;
     best.threads_y = cb.threads_y;
+    t_y = tbest;
   }
   // x pass
   {
@@ -1191,10 +1277,38 @@ static fftg_status group_autotune(Group& g) {
     best.lines_x = cb.lines_x;
     best.threads_x = cb.threads_x;
   }
+  // slab passes (z and y fused) against the z + y + y + z passes they replace
+  if (slab_mode() != 0 && slab_fits(gs.n1, gs.n2)) {
+    double tbest = 1e30;
+    LaunchCfg cb = best;
+    for (int t : {256, 512}) {
+      LaunchCfg c = best;
+      c.slab = 1;
+      c.threads_s = t;
+      group_set_cfg(g, c);
+      if ((st = group_upload(g)) != FFTG_OK) return st;
+      const size_t ls = mixed ? g.lds_s32 : g.lds_s;
+      const double ms = time_ms(g.stream, reps, [&]() {
+        hipError_t e = launch_slab_fwd(mixed, g.d, nr, g.total[P_ZF], g.cfg, ls, IN_ROLE, R_P, TAN_ELASTIC, 0, 0, 0,
+                                       R_P, R_P, g.stream);
+        if (e != hipSuccess) return e;
+        return launch_slab_inv(mixed, g.d, nr, g.total[P_ZI], g.cfg, ls, OUT_PLAIN, R_AP, 0, R_P, g.stream);
+      });
+      if (ms < tbest) {
+        tbest = ms;
+        cb = c;
+      }
+    }
+    if (slab_mode() == 2 || tbest < t_zpair + 2.0 * t_y) {
+      best.slab = 1;
+      best.threads_s = cb.threads_s;
+    }
+  }
   HIP_TRY(hipStreamSynchronize(g.stream));
   if (env_long("FFTG_VERBOSE", 0) == 1)
-    fprintf(stderr, "fftg autotune %s: rows %d/%d thr, y %d/%d, x %d/%d, vec %d\n", key.c_str(), best.rows_per_tile,
-            best.threads_z, best.lines_y, best.threads_y, best.lines_x, best.threads_x, best.vec_per_tile);
+    fprintf(stderr, "fftg autotune %s: rows %d/%d thr, y %d/%d, x %d/%d, vec %d, slab %d/%d\n", key.c_str(),
+            best.rows_per_tile, best.threads_z, best.lines_y, best.threads_y, best.lines_x, best.threads_x,
+            best.vec_per_tile, best.slab, best.threads_s);
   {
     std::lock_guard<std::mutex> lk(g_tune_mutex);
     g_tune_cache[key] = best;

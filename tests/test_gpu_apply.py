@@ -42,6 +42,28 @@ def test_projection_matches_oracle(shape):
     assert rel_err(got, ref) < 1e-12
 
 
+@pytest.mark.parametrize("slab", ["0", "2"])
+@pytest.mark.parametrize("shape", [(3, 5, 7), (1, 5, 7), (7, 5, 1), (15, 15, 15), (31, 31, 31), (61, 9, 53),
+                                   (5, 63, 63), (13, 17, 11)])
+def test_product_schedules_match_oracle(shape, slab, monkeypatch):
+    """The five-pass product (FFTG_SLAB=0) and the fused z-y slab passes
+    (FFTG_SLAB=2; every shape here fits) against the oracle, FP64 and FP32."""
+    import torch
+    from paper_1601_05970_amd import fftg
+    print("apply schedule", shape, "slab", slab, flush=True)
+    monkeypatch.setenv("FFTG_SLAB", slab)
+    ph = synth.bernoulli(shape, 0.5, 2)
+    mats = [(0.833, 0.386, 0.003, 0.004, 1.0), (2.0, 1.3, 0.006, 0.008, 1.0)]
+    p = synth.random_sym_tensor_field(shape, 4)
+    K, G, _, _, _ = j2.material_fields(ph, mats)
+    ref = t2m(apply_G(j2.ddot42(j2.elastic_stiffness(K, G), p)))
+    for prec, tol in ((0, 1e-12), (1, 2e-6)):
+        pl = _plan(shape, ph, mats, precision=prec)
+        d_out = pl.field(dtype=torch.float32 if prec else torch.float64)
+        pl.apply_GK(to_dev(t2m(p)), d_out, fftg.FFTG_TANGENT_ELASTIC)
+        assert rel_err(to_host(d_out).astype(np.float64), ref) < tol, prec
+
+
 @pytest.mark.parametrize("shape", [(19, 23, 29), (31, 31, 31), (61, 9, 53)])
 def test_projection_rader_path_matches_oracle(shape, monkeypatch):
     """Prime extents with smooth p-1 taken through Rader's algorithm instead

@@ -93,9 +93,12 @@ def test_laminate_matches_closed_form_and_oracle():
     _compare(h, s, 1e-10, stats[-1], st_ref[-1])
 
 
+@pytest.mark.parametrize("slab", ["0", "2"])
 @pytest.mark.parametrize("shape,seed", [((9, 7, 5), 21), ((15, 15, 15), 3), ((11, 13, 7), 5)])
-def test_lockstep_parity_with_oracle(shape, seed):
-    print("solve lockstep", shape, flush=True)
+def test_lockstep_parity_with_oracle(shape, seed, slab, monkeypatch):
+    """FFTG_SLAB=0 runs the five-pass product, 2 the fused z-y slab passes."""
+    print("solve lockstep", shape, "slab", slab, flush=True)
+    monkeypatch.setenv("FFTG_SLAB", slab)
     w = synth.small_random(shape, 0.35, seed, E_eq=0.01, n_inc=4)
     s = S.Solver(w.phase, w.materials, w.tol_newton, w.tol_cg)
     from paper_1601_05970_amd import fftg
@@ -136,7 +139,13 @@ def test_literal_algorithm_without_predictor():
     _compare(h, s, 1e-10, stats[0], st_ref)
 
 
-def test_mixed_precision_agrees_with_fp64_oracle():
+@pytest.mark.parametrize("slab", ["0", "2"])
+def test_mixed_precision_agrees_with_fp64_oracle(slab, monkeypatch):
+    monkeypatch.setenv("FFTG_SLAB", slab)
+    _mixed_vs_oracle()
+
+
+def _mixed_vs_oracle():
     print("solve mixed", flush=True)
     from paper_1601_05970_amd import fftg
     w = synth.small_random((15, 15, 15), 0.35, 9, E_eq=0.01, n_inc=4)

@@ -1,0 +1,94 @@
+"""GPU checks at the full sizes of the benchmark workloads, in the launch
+configuration the benchmark uses (default options, autotuned schedule).
+
+31^3 FP64 (the headline workload): lockstep parity with the FP64 oracle on
+its first increments, element by element.  127^3 mixed precision (too large
+for the oracle's full solve): properties that hold at any size -- zero-mean
+compatible fluctuation under the oracle's projection, the volume average of
+sigma, and the oracle's return map at sampled voxels from the committed
+history.
+"""
+import numpy as np
+import pytest
+
+import synth
+from oracle import j2, solver as S
+from oracle.projection import apply_G
+from tests.gpu_util import m2t, rel_err, t2m, tensor6, to_host
+
+pytestmark = pytest.mark.gpu
+
+
+def _opts(w):
+    from paper_1601_05970_amd import fftg
+    o = fftg.fftg_options_default()
+    o.tol_newton, o.tol_cg = w.tol_newton, w.tol_cg
+    o.precision = fftg.FFTG_MIXED if w.precision == "mixed" else fftg.FFTG_FP64
+    return o
+
+
+def test_random31_fp64_lockstep_first_increments():
+    from paper_1601_05970_amd import fftg
+    w = synth.random_31()
+    print("full size", w.name, w.shape, flush=True)
+    s = S.Solver(w.phase, w.materials, w.tol_newton, w.tol_cg)
+    pl = fftg.Plan(w.phase, w.materials, _opts(w))
+    h = fftg.History(pl)
+    for n in (1, 2, 3):
+        ref = s.solve_increment(w.E_at(n))
+        st = h.solve_increment(tensor6(w.dE(n)), ref.cg_iters)
+        print("increment", n, "cg", st["cg_iters"], flush=True)
+        assert st["cg_iters"] == ref.cg_iters
+        strain = to_host(h.get_field(fftg.FFTG_FIELD_STRAIN))
+        stress = to_host(h.get_field(fftg.FFTG_FIELD_STRESS))
+        assert rel_err(strain, t2m(s.strain())) < 1e-10
+        assert rel_err(stress, t2m(s.sigma)) < 1e-10
+        Sg, Sr = np.array(st["Sigma"]), np.array(tensor6(ref.Sigma))
+        assert np.max(np.abs(Sg - Sr)) <= 1e-10 * np.max(np.abs(Sr))
+    if np.max(s.epbar) > 0:
+        eb = to_host(h.get_field(fftg.FFTG_FIELD_EPBAR))[0]
+        assert rel_err(eb, s.epbar) < 1e-10
+
+
+def test_voronoi127_mixed_invariants_and_sampled_return_map():
+    from paper_1601_05970_amd import fftg
+    w = synth.voronoi_127(precision="mixed")
+    print("full size", w.name, w.shape, flush=True)
+    pl = fftg.Plan(w.phase, w.materials, _opts(w))
+    h = fftg.History(pl)
+    n_inc = 3
+    for n in range(1, n_inc):
+        h.solve_increment(tensor6(w.dE(n)))
+    eps_p_t = to_host(h.get_field(fftg.FFTG_FIELD_EPS_P))
+    epbar_t = to_host(h.get_field(fftg.FFTG_FIELD_EPBAR))[0]
+    st = h.solve_increment(tensor6(w.dE(n_inc)))
+    print("increment", n_inc, "newton", st["newton_iters"], "cg", st["cg_iters"], flush=True)
+    assert st["converged"]
+
+    E = w.E_at(n_inc)
+    fl = m2t(to_host(h.get_field(fftg.FFTG_FIELD_FLUCT)))
+    strain = m2t(to_host(h.get_field(fftg.FFTG_FIELD_STRAIN)))
+    stress = m2t(to_host(h.get_field(fftg.FFTG_FIELD_STRESS)))
+    nE = np.linalg.norm(E)
+    # zero-mean fluctuation; strain = E + fluctuation
+    assert np.max(np.abs(fl.mean(axis=(2, 3, 4)))) <= 1e-12 * nE
+    assert np.max(np.abs(strain - fl - E[:, :, None, None, None])) <= 1e-14 * nE
+    # compatibility: the oracle's G leaves the fluctuation unchanged
+    assert rel_err(apply_G(fl), fl) < 1e-9
+    # Sigma is the volume average of sigma
+    Sg = np.array(st["Sigma"])
+    Sm = np.array(tensor6(stress.mean(axis=(2, 3, 4))))
+    assert np.max(np.abs(Sg - Sm)) <= 1e-12 * np.max(np.abs(Sm))
+    # the oracle's return map at sampled voxels, from the committed history
+    rng = np.random.default_rng(127)
+    idx = tuple(rng.integers(0, n, 4000) for n in w.shape)
+    K, G, sy0, H, _ = j2.material_fields(w.phase[idx], w.materials)
+    sig, _, ep_new, eb_new, plastic = j2.return_map(
+        strain[(slice(None), slice(None)) + idx], m2t(eps_p_t)[(slice(None), slice(None)) + idx],
+        epbar_t[idx], K, G, sy0, H)
+    assert plastic.any() and not plastic.all()
+    assert rel_err(stress[(slice(None), slice(None)) + idx], sig) < 1e-12
+    eb = to_host(h.get_field(fftg.FFTG_FIELD_EPBAR))[0]
+    assert rel_err(eb[idx], eb_new) < 1e-12
+    ep = m2t(to_host(h.get_field(fftg.FFTG_FIELD_EPS_P)))
+    assert rel_err(ep[(slice(None), slice(None)) + idx], ep_new) < 1e-12

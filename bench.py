@@ -65,6 +65,24 @@ def x_pass_bytes_per_voxel(shape, real_bytes):
     return 2 * 6 * 2 * real_bytes * (n0 * n1 * H) / float(n0 * n1 * n2)
 
 
+def forward_pass_bytes_per_voxel(shape, real_bytes):
+    """Algorithmic HBM bytes per voxel of one forward product pass inside CG
+    (k_slab_fwd or k_zfwd): read r and p (6 FP64 each), the compact tangent
+    (7 reals of the apply precision) and the phase byte; write the new p (6
+    FP64) and the six complex half-spectrum planes.  The y transform of the
+    slab form stays in LDS and adds no HBM bytes."""
+    n0, n1, n2 = shape
+    H = (n2 + 1) // 2
+    return 6 * 8 * 3 + 7 * real_bytes + 1 + 6 * 2 * real_bytes * H / float(n2)
+
+
+ROOFLINE_KERNELS = {
+    0: ("forward product pass (k_slab_fwd, or k_zfwd in the five-pass schedule): p <- r + beta p, C:p, "
+        "DFT along z (and y)", forward_pass_bytes_per_voxel),
+    2: ("k_xpass (DFT x, G^(k) projection, inverse DFT x)", x_pass_bytes_per_voxel),
+}
+
+
 def kernel_source_hash():
     import hashlib
     h = hashlib.sha256()
@@ -74,9 +92,10 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(workload_name):
-    """HBM bytes per k_xpass launch from the committed FETCH_SIZE/WRITE_SIZE
-    summary, or None when it covers another workload or older kernels."""
+def measured_traffic(workload_name, kernel_id):
+    """HBM bytes per launch of the roofline kernel from the committed
+    FETCH_SIZE/WRITE_SIZE summary, or None when it covers another workload,
+    another kernel or older kernel sources."""
     path = os.path.join(ROOT, "profiles", "random31_fp64_hbm_traffic.md")
     if workload_name != "random_31" or not os.path.exists(path):
         return None
@@ -85,7 +104,7 @@ def measured_traffic(workload_name):
         if ":" in line and not line.startswith(("#", "|", "`")):
             k, v = line.split(":", 1)
             kv[k.strip()] = v.strip()
-    if kv.get("kernel_source_sha256_16") != kernel_source_hash():
+    if kv.get("kernel_source_sha256_16") != kernel_source_hash() or kv.get("kernel_id") != str(kernel_id):
         return None
     try:
         return float(kv["traffic_bytes_per_launch"])
@@ -116,7 +135,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="random_31")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--profile-kernel", type=int, default=2, help="fftg_kernel_id timed for the roofline")
+    ap.add_argument("--profile-kernel", type=int, default=0, choices=sorted(ROOFLINE_KERNELS),
+                    help="fftg_kernel_id timed for the roofline (0: forward product pass, 2: x pass)")
     ap.add_argument("--also", default="batch64_fp64,batch64_mixed",
                     help="extra workloads timed after the main one (1 warmup + 1 step each); '' for none")
     ap.add_argument("--max-increments", type=int, default=0,
@@ -157,7 +177,7 @@ def main():
                                 "dtype": r["dtype"], "ms_per_step": r["ms_per_step"],
                                 "rves": r["config"]["rves"], "voxels": r["config"]["voxels"],
                                 "roofline_frac": r["roofline"]["frac"],
-                                "x_pass_GBs": r["roofline"]["achieved"]})
+                                "roofline_kernel_GBs": r["roofline"]["achieved"]})
     print(json.dumps(out))
 
 
@@ -209,7 +229,8 @@ def measure(fftg, torch, name, steps, warmup, profile_kernel, max_inc=0):
 
     value = total_work / dt
     real_bytes = 4 if opts.precision == fftg.FFTG_MIXED else 8
-    bpv = float(np.dot(nvox, [x_pass_bytes_per_voxel(x.shape, real_bytes) for x in ws]) / nvox.sum())
+    kname, kbytes = ROOFLINE_KERNELS[profile_kernel]
+    bpv = float(np.dot(nvox, [kbytes(x.shape, real_bytes) for x in ws]) / nvox.sum())
     avg_ms = kms / max(klaunch, 1)
     bytes_per_launch = bpv * kvox / max(klaunch, 1)
     achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else 0.0
@@ -224,9 +245,9 @@ def measure(fftg, torch, name, steps, warmup, profile_kernel, max_inc=0):
                    "grid": list(w.shape) if len(ws) == 1 else "mixed", "increments": w.n_inc,
                    "tol_newton": w.tol_newton, "tol_cg": w.tol_cg,
                    "voxel_cg_iters_per_step": total_work / steps},
-        "roofline": {"kernel": "k_xpass (DFT x, G^(k) projection, inverse DFT x)", "bound": "hbm",
+        "roofline": {"kernel": kname, "bound": "hbm",
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(name),
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(name, profile_kernel),
                      "avg_launch_us": 1e3 * avg_ms, "launches": klaunch,
                      "bytes_per_launch": bytes_per_launch},
     }

@@ -629,8 +629,11 @@ static int prof_begin(int kid, hipStream_t s) {
   if (g_prof.kid != kid) return -1;
   if (g_prof.used + 2 > g_prof.pool.size()) {
     for (int i = 0; i < 64; ++i) {
+      // timing-only events: no system-scope fence (cache write-back and
+      // invalidate) around the bracketed launch; elapsed times are read
+      // after the stream has been synchronized
       hipEvent_t e;
-      if (hipEventCreate(&e) != hipSuccess) return -1;
+      if (hipEventCreateWithFlags(&e, hipEventDisableSystemFence) != hipSuccess) return -1;
       g_prof.pool.push_back(e);
     }
   }
@@ -1155,8 +1158,8 @@ static LaunchCfg with_tuned_tiles(LaunchCfg c, const LaunchCfg& t) {
 template <class F>
 static double time_ms(hipStream_t s, int reps, F&& launch) {
   hipEvent_t a, b;
-  if (hipEventCreate(&a) != hipSuccess) return 1e30;
-  if (hipEventCreate(&b) != hipSuccess) {
+  if (hipEventCreateWithFlags(&a, hipEventDisableSystemFence) != hipSuccess) return 1e30;
+  if (hipEventCreateWithFlags(&b, hipEventDisableSystemFence) != hipSuccess) {
     hipEventDestroy(a);
     return 1e30;
   }

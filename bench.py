@@ -198,42 +198,49 @@ def measure(fftg, torch, name, steps, warmup, profile_kernel, max_inc=0):
 
     def step():
         """One full solve of every RVE's load path from a fresh history;
-        returns sum over RVEs of voxels x CG iterations."""
+        returns the CG iterations of each RVE."""
         hs = [fftg.History(p) for p in plans]
-        work = 0.0
+        cg = np.zeros(len(ws))
         if len(ws) == 1:
             for n in range(1, w.n_inc + 1):
-                work += nvox[0] * hs[0].solve_increment(tensor6(w.dE(n)))["total_cg"]
+                cg[0] += hs[0].solve_increment(tensor6(w.dE(n)))["total_cg"]
         else:
             batch = fftg.Batch(plans, hs)
             for n in range(1, w.n_inc + 1):
                 dE = np.array([tensor6(x.dE(n)) for x in ws])
                 st = batch.solve_increment(dE)
-                work += float(np.dot(nvox, [s["total_cg"] for s in st]))
+                cg += np.array([s["total_cg"] for s in st], dtype=np.float64)
             batch.close()
         for h in hs:
             h.close()
-        return work
+        return cg
 
     for _ in range(warmup):
         step()
     torch.cuda.synchronize()
     fftg.fftg_profiler_start(profile_kernel)
     t0 = time.perf_counter()
-    total_work = 0.0
+    cg_iters = np.zeros(len(ws))
     for _ in range(steps):
-        total_work += step()
+        cg_iters += step()
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     kms, klaunch, kvox = fftg.fftg_profiler_stop()
 
+    total_work = float(np.dot(nvox, cg_iters))
     value = total_work / dt
     real_bytes = 4 if opts.precision == fftg.FFTG_MIXED else 8
     kname, kbytes = ROOFLINE_KERNELS[profile_kernel]
-    bpv = float(np.dot(nvox, [kbytes(x.shape, real_bytes) for x in ws]) / nvox.sum())
+    # Algorithmic bytes of the timed launches, counted from the work done: each
+    # CG iteration of an RVE moves its per-voxel bytes once through the kernel
+    # (in a batch, RVEs whose CG has stopped exit their tiles at once, so the
+    # launch count alone would overstate the bytes).  The kernel's few launches
+    # outside CG (residual, predictor) add time but are not counted: the
+    # achieved rate is a lower bound.
+    total_bytes = float(np.dot(nvox * cg_iters, [kbytes(x.shape, real_bytes) for x in ws]))
     avg_ms = kms / max(klaunch, 1)
-    bytes_per_launch = bpv * kvox / max(klaunch, 1)
-    achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else 0.0
+    bytes_per_launch = total_bytes / max(klaunch, 1)
+    achieved = total_bytes / (kms * 1e-3) / 1e9 if kms > 0 else 0.0
     for p in plans:
         p.close()
     return {

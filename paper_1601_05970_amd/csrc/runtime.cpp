@@ -321,17 +321,17 @@ void fftg_options_default(fftg_options* o) {
   o->cg_chunk = 16;
 }
 
-// Tile sizes fit the FP64 passes in an LDS budget (default 64 KB; mixed
+// Tile sizes fit the FP64 passes in an LDS budget (default 128 KB; mixed
 // plans also run the FP64 residual with the same configuration).  Starting
 // from the widest tile LDS allows, tiles shrink until a launch has at least
 // min_tiles workgroups (the chip has 256 CUs), so small RVEs still spread
 // over the device.  FFTG_LDS_KB and FFTG_MIN_TILES override the two knobs.
-static long env_long(const char* name, long dflt) {
+static long env_long(const char* name, long dflt, long lo = 0) {
   const char* s = getenv(name);
   if (!s || !*s) return dflt;
   char* end = nullptr;
   const long v = strtol(s, &end, 10);
-  return (end && *end == 0 && v > 0) ? v : dflt;
+  return (end && *end == 0 && v >= lo) ? v : dflt;
 }
 
 // The slab passes hold two y-z planes of one component pair in LDS; the
@@ -364,8 +364,8 @@ struct GridSum {
 
 static LaunchCfg choose_cfg(const GridSum& gs) {
   LaunchCfg c;
-  const size_t budget = (size_t)env_long("FFTG_LDS_KB", 64) * 1024;
-  const long long kMinTiles = env_long("FFTG_MIN_TILES", 2048);
+  const size_t budget = (size_t)env_long("FFTG_LDS_KB", 128, 1) * 1024;
+  const long long kMinTiles = env_long("FFTG_MIN_TILES", 2048, 1);
   const long long H = gs.hmax;
   int R = 8;
   while (R > 1 && lds_z(0, R, gs.n2) > budget) --R;
@@ -1132,7 +1132,7 @@ static std::mutex g_tune_mutex;
 static std::string tune_key(const Group& g, const GridSum& gs) {
   int lg = 0;
   while ((1LL << (lg + 1)) <= gs.vox) ++lg;
-  return std::to_string(g.mixed) + ":" + std::to_string(env_long("FFTG_LDS_KB", 64)) + ":s" +
+  return std::to_string(g.mixed) + ":" + std::to_string(env_long("FFTG_LDS_KB", 128, 1)) + ":s" +
          std::to_string(slab_mode()) + ":b" +
          std::to_string(gs.big ? 1 : 0) + ":" + std::to_string(gs.n0) + "x" + std::to_string(gs.n1) + "x" +
          std::to_string(gs.n2) + ":n" + std::to_string(g.plans.size() > 1 ? 1 : 0) + ":v" + std::to_string(lg);
@@ -1193,7 +1193,7 @@ static fftg_status group_autotune(Group& g) {
       return FFTG_OK;
     }
   }
-  const size_t budget = (size_t)env_long("FFTG_LDS_KB", 64) * 1024;
+  const size_t budget = (size_t)env_long("FFTG_LDS_KB", 128, 1) * 1024;
   const int nr = (int)g.h.size();
   const int mixed = g.mixed;
   const int thr[3] = {64, 128, 256};

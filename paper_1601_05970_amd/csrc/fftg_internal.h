@@ -79,7 +79,7 @@ enum Pass { P_ZF = 0, P_Y, P_X, P_ZI, P_VEC, P_NPASS };
 struct RveDev {
   int n0, n1, n2, H;
   long long nvox, nspec;
-  const AxisDev* ax[3];
+  AxisDev ax[3];             // transforms of axes x, y, z (by value: one load less per kernel)
   void* buf[R_NROLES];       // double* except R_AP / R_USER_OUT in mixed mode
   void* tang;                // 7 planes, double (FP64) or float (mixed)
   void* spec;                // 6 complex planes, sized for double

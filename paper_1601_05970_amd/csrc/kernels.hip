@@ -40,6 +40,10 @@ __device__ __forceinline__ int xcd_tile(int b, int n) {
 // own no tiles); a block finds its RVE by binary search over that table.
 __device__ __forceinline__ int find_rve(const RveDev* __restrict__ rv, int nrve, int pass, int& tile) {
   const int b = rv[0].xcd_remap ? xcd_tile(blockIdx.x, gridDim.x) : (int)blockIdx.x;
+  if (nrve == 1) {  // the grid is exactly the one RVE's tiles
+    tile = b;
+    return 0;
+  }
   const int* __restrict__ st = reinterpret_cast<const int*>(rv + nrve) + pass * (nrve + 1);
   if (b >= st[nrve]) {
     tile = -1;
@@ -105,6 +109,21 @@ __device__ __forceinline__ int done_flag(CgState* cg) {
   if (threadIdx.x == 0) s_done = __hip_atomic_load(&cg->done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   __syncthreads();
   return s_done;
+}
+
+// The same in two halves, so that the flag's load (issued by thread 0 at
+// kernel start) overlaps the loads of the axis tables that follow it: peek
+// returns the raw flag in thread 0, publish shares it through LDS (and its
+// barrier also publishes the tables).
+__device__ __forceinline__ int done_peek(int check_done, CgState* cg) {
+  return (check_done && threadIdx.x == 0) ? __hip_atomic_load(&cg->done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                                          : 0;
+}
+__device__ __forceinline__ int done_publish(int v) {
+  __shared__ int s_done2;
+  if (threadIdx.x == 0) s_done2 = v;
+  __syncthreads();
+  return s_done2;
 }
 
 template <class T>
@@ -225,7 +244,7 @@ template <class T>
 __device__ __forceinline__ void voxel_tau(const RveDev& rv, long long v, int in_mode, const double* __restrict__ in,
                                           int update_p, double beta, const double* __restrict__ rres,
                                           const double* p_old, double* p_new, int own_lo, int own_hi,
-                                          int tan_mode, T tau[6]) {
+                                          int tan_mode, const MatDev* __restrict__ mats, T tau[6]) {
   const long long nvox = rv.nvox;
   T p[6];
   if (in_mode == IN_CONST_DE) {
@@ -246,7 +265,7 @@ __device__ __forceinline__ void voxel_tau(const RveDev& rv, long long v, int in_
 #pragma unroll
     for (int c = 0; c < 6; ++c) tau[c] = p[c];
   } else {
-    const MatDev& mt = rv.mats[rv.phase[v]];
+    const MatDev& mt = mats[rv.phase[v]];
     const T* tg = (const T*)rv.tang;
     T g2, m[6];
     if (tan_mode == TAN_ELASTIC) {
@@ -273,14 +292,18 @@ __global__ void __launch_bounds__(256) k_zfwd(const RveDev* __restrict__ rvs, in
   const int ri = find_rve(rvs, nrve, P_ZF, tile);
   if (ri < 0) return;
   const RveDev& rv = rvs[ri];
-  if (rv.skip || (check_done && done_flag(rv.cg))) return;
+  if (rv.skip) return;
+  const int dn = done_peek(check_done, rv.cg);
   const int n2 = rv.n2, H = rv.H;
   const long long nspec = rv.nspec;
   const int nrows_tot = rv.n0 * rv.n1;
   const int row0 = tile * rows_per_tile;
   const int nrows = min(rows_per_tile, nrows_tot - row0);
   const int ld = n2;
-  TileLds<T> L(smem, 3 * rows_per_tile, ld, *rv.ax[2], ldmax);
+  TileLds<T> L(smem, 3 * rows_per_tile, ld, rv.ax[2], ldmax);
+  __shared__ MatDev s_mats[kMaxPhases];  // per-voxel material lookups from LDS
+  if (threadIdx.x < rv.n_phases) s_mats[threadIdx.x] = rv.mats[threadIdx.x];
+  if (done_publish(dn)) return;  // also publishes tables and materials
 
   const double* in = (const double*)rv.buf[in_role];
   // CG search direction update fused here: p <- r + beta p (in place: this
@@ -296,7 +319,7 @@ __global__ void __launch_bounds__(256) k_zfwd(const RveDev* __restrict__ rvs, in
     const int z = t - r * n2;
     const long long v = (long long)(row0 + r) * n2 + z;
     T tau[6];
-    voxel_tau<T>(rv, v, in_mode, in, update_p, beta, rres, pw, pw, 0, 6, tan_mode, tau);
+    voxel_tau<T>(rv, v, in_mode, in, update_p, beta, rres, pw, pw, 0, 6, tan_mode, s_mats, tau);
     if (want_norm) {
 #pragma unroll
       for (int c = 0; c < 6; ++c) nrm += double(tau[c]) * double(tau[c]);
@@ -335,7 +358,8 @@ __global__ void __launch_bounds__(256) k_ypass(const RveDev* __restrict__ rvs, i
   const int ri = find_rve(rvs, nrve, P_Y, tile);
   if (ri < 0) return;
   const RveDev& rv = rvs[ri];
-  if (rv.skip || (check_done && rv.cg->done)) return;
+  if (rv.skip) return;
+  const int dn = check_done ? rv.cg->done : 0;  // no writer during the launch; tested after the table loads
   const int n0 = rv.n0, n1 = rv.n1, H = rv.H;
   const int nhb = (H + lines_per_tile - 1) / lines_per_tile;
   const int c = tile / (n0 * nhb);
@@ -344,7 +368,8 @@ __global__ void __launch_bounds__(256) k_ypass(const RveDev* __restrict__ rvs, i
   const int h0 = (rem - i0 * nhb) * lines_per_tile;
   const int nh = min(lines_per_tile, H - h0);
   const int ld = n1;
-  TileLds<T> L(smem, lines_per_tile, ld, *rv.ax[1], ldmax);
+  TileLds<T> L(smem, lines_per_tile, ld, rv.ax[1], ldmax);
+  if (dn) return;
   cx<T>* base = (cx<T>*)rv.spec + c * rv.nspec + (long long)i0 * n1 * H + h0;
   const FastDiv fnh(nh);
   for (int t = threadIdx.x; t < n1 * nh; t += blockDim.x) {
@@ -370,7 +395,8 @@ __global__ void __launch_bounds__(256) k_xpass(const RveDev* __restrict__ rvs, i
   const int ri = find_rve(rvs, nrve, P_X, tile);
   if (ri < 0) return;
   const RveDev& rv = rvs[ri];
-  if (rv.skip || (check_done && rv.cg->done)) return;
+  if (rv.skip) return;
+  const int dn = check_done ? rv.cg->done : 0;  // no writer during the launch; tested after the table loads
   const int n0 = rv.n0, n1 = rv.n1, n2 = rv.n2, H = rv.H;
   const long long nspec = rv.nspec;
   const int nhb = (H + lines_per_tile - 1) / lines_per_tile;
@@ -379,7 +405,8 @@ __global__ void __launch_bounds__(256) k_xpass(const RveDev* __restrict__ rvs, i
   const int nh = min(lines_per_tile, H - h0);
   const int ld = n0;
   const int nl = 6 * nh;
-  TileLds<T> L(smem, 6 * lines_per_tile, ld, *rv.ax[0], ldmax);
+  TileLds<T> L(smem, 6 * lines_per_tile, ld, rv.ax[0], ldmax);
+  if (dn) return;
   cx<T>* spec = (cx<T>*)rv.spec;
   const long long rs = (long long)n1 * H;
   const long long off = (long long)i1 * H + h0;
@@ -436,14 +463,16 @@ __global__ void __launch_bounds__(256) k_zinv(const RveDev* __restrict__ rvs, in
   const int ri = find_rve(rvs, nrve, P_ZI, tile);
   if (ri < 0) return;
   const RveDev& rv = rvs[ri];
-  if (rv.skip || (check_done && rv.cg->done)) return;
+  if (rv.skip) return;
+  const int dn = check_done ? rv.cg->done : 0;  // no writer during the launch; tested after the table loads
   const int n2 = rv.n2, H = rv.H;
   const long long nvox = rv.nvox, nspec = rv.nspec;
   const int nrows_tot = rv.n0 * rv.n1;
   const int row0 = tile * rows_per_tile;
   const int nrows = min(rows_per_tile, nrows_tot - row0);
   const int ld = n2;
-  TileLds<T> L(smem, 3 * rows_per_tile, ld, *rv.ax[2], ldmax);
+  TileLds<T> L(smem, 3 * rows_per_tile, ld, rv.ax[2], ldmax);
+  if (dn) return;
   const cx<T>* spec = (const cx<T>*)rv.spec;
   // Z_k = A_k + i B_k, Z_{n-k} = conj(A_k) + i conj(B_k)
   const FastDiv fn2(n2), f3(3);
@@ -562,11 +591,15 @@ __global__ void __launch_bounds__(512) k_slab_fwd(const RveDev* __restrict__ rvs
   const int ri = find_rve(rvs, nrve, P_ZF, tile);
   if (ri < 0) return;
   const RveDev& rv = rvs[ri];
-  if (rv.skip || (check_done && done_flag(rv.cg))) return;
+  if (rv.skip) return;
+  const int dn = done_peek(check_done, rv.cg);
   const int n1 = rv.n1, n2 = rv.n2, H = rv.H;
   const long long nspec = rv.nspec;
   const int x = tile / 3, pr = tile - 3 * (tile / 3);
-  SlabLds<T> L(smem, n1max, n2max, *rv.ax[2], *rv.ax[1]);
+  SlabLds<T> L(smem, n1max, n2max, rv.ax[2], rv.ax[1]);
+  __shared__ MatDev s_mats[kMaxPhases];  // per-voxel material lookups from LDS
+  if (threadIdx.x < rv.n_phases) s_mats[threadIdx.x] = rv.mats[threadIdx.x];
+  if (done_publish(dn)) return;  // also publishes tables and materials
   double beta = 0.0;
   if (update_p && !cg_begin_iter(rv, tile, L.red, beta)) return;
   const double* in = (const double*)rv.buf[in_role];
@@ -578,7 +611,8 @@ __global__ void __launch_bounds__(512) k_slab_fwd(const RveDev* __restrict__ rvs
   double nrm = 0.0;
   for (int t = threadIdx.x; t < npl; t += blockDim.x) {
     T tau[6];
-    voxel_tau<T>(rv, v0 + t, in_mode, in, update_p, beta, rres, pin, pout, 2 * pr, 2 * pr + 2, tan_mode, tau);
+    voxel_tau<T>(rv, v0 + t, in_mode, in, update_p, beta, rres, pin, pout, 2 * pr, 2 * pr + 2, tan_mode, s_mats,
+                 tau);
     const T a = tau[2 * pr], b = tau[2 * pr + 1];
     if (want_norm) nrm += double(a) * double(a) + double(b) * double(b);
     L.b0[t] = cx<T>{a, b};  // z-line y at y * n2
@@ -619,11 +653,13 @@ __global__ void __launch_bounds__(512) k_slab_inv(const RveDev* __restrict__ rvs
   const int ri = find_rve(rvs, nrve, P_ZI, tile);
   if (ri < 0) return;
   const RveDev& rv = rvs[ri];
-  if (rv.skip || (check_done && done_flag(rv.cg))) return;
+  if (rv.skip) return;
+  const int dn = done_peek(check_done, rv.cg);
   const int n1 = rv.n1, n2 = rv.n2, H = rv.H;
   const long long nvox = rv.nvox, nspec = rv.nspec;
   const int x = tile / 3, pr = tile - 3 * (tile / 3);
-  SlabLds<T> L(smem, n1max, n2max, *rv.ax[2], *rv.ax[1]);
+  SlabLds<T> L(smem, n1max, n2max, rv.ax[2], rv.ax[1]);
+  if (check_done && done_publish(dn)) return;
   const cx<T>* spec = (const cx<T>*)rv.spec;
   const FastDiv fH(H), fn1(n1), fn2(n2);
   for (int t = threadIdx.x; t < 2 * n1 * H; t += blockDim.x) {

@@ -281,7 +281,7 @@ struct fftg_plan_s {
   MatDev mats[kMaxPhases];
   std::vector<void*> allocs;
   std::vector<AxisHost> axes;  // distinct lengths
-  AxisDev* d_ax[3];
+  AxisDev ax_dev[3];    // the transform of each axis (copied into every launch descriptor)
   uint8_t* d_phase;
   void* spec;
   double *sig, *x, *r, *p;
@@ -533,10 +533,7 @@ fftg_status fftg_plan_create(fftg_plan* out, int n0, int n1, int n2, const uint8
                   std::string(#expr) + ": " + hipGetErrorString(e));              \
     }                                                                             \
   } while (0)
-  for (int i = 0; i < 3; ++i) {
-    PLAN_TRY(dalloc(pl, &pl->d_ax[i], sizeof(AxisDev)));
-    PLAN_TRY(hipMemcpy(pl->d_ax[i], &pl->axes[idx[ns[i]]].dev, sizeof(AxisDev), hipMemcpyHostToDevice));
-  }
+  for (int i = 0; i < 3; ++i) pl->ax_dev[i] = pl->axes[idx[ns[i]]].dev;
   PLAN_TRY(dalloc(pl, &pl->d_phase, (size_t)nvox));
   PLAN_TRY(hipMemcpy(pl->d_phase, phase, (size_t)nvox, hipMemcpyHostToDevice));
   PLAN_TRY(dalloc(pl, &pl->spec, (size_t)6 * pl->nspec * 16));
@@ -712,7 +709,7 @@ static void fill_desc(RveDev& rv, fftg_plan pl, fftg_history h, const LaunchCfg&
   rv.H = pl->H;
   rv.nvox = pl->nvox;
   rv.nspec = pl->nspec;
-  for (int i = 0; i < 3; ++i) rv.ax[i] = pl->d_ax[i];
+  for (int i = 0; i < 3; ++i) rv.ax[i] = pl->ax_dev[i];
   rv.buf[R_SIG] = pl->sig;
   rv.buf[R_X] = pl->x;
   rv.buf[R_R] = pl->r;

@@ -104,17 +104,10 @@ __device__ double sum_partials(const double* __restrict__ p, int n, double* sh) 
 // The CG stop flag, read once per workgroup and shared through LDS: in the
 // kernels that apply a folded scalar step, tile 0 may set it while other
 // tiles of the same launch start, and all threads of a tile must agree.
-__device__ __forceinline__ int done_flag(CgState* cg) {
-  __shared__ int s_done;
-  if (threadIdx.x == 0) s_done = __hip_atomic_load(&cg->done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  __syncthreads();
-  return s_done;
-}
-
-// The same in two halves, so that the flag's load (issued by thread 0 at
-// kernel start) overlaps the loads of the axis tables that follow it: peek
-// returns the raw flag in thread 0, publish shares it through LDS (and its
-// barrier also publishes the tables).
+// In two halves, so that the flag's load (issued by thread 0 at kernel
+// start) overlaps the loads of the axis tables and partial sums that follow
+// it: peek returns the raw flag in thread 0, publish shares it through LDS
+// (and its barrier also publishes the tables).
 __device__ __forceinline__ int done_peek(int check_done, CgState* cg) {
   return (check_done && threadIdx.x == 0) ? __hip_atomic_load(&cg->done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
                                           : 0;
@@ -190,23 +183,28 @@ struct TileLds {
   }
 };
 
-// Start of a CG iteration in the kernel that forms p <- r + beta p.  With
+// Start of a CG iteration in the kernel that forms p <- r + beta p (dn: the
+// stop flag as peeked by thread 0 at kernel start; the decision reaches every
+// thread through LDS).  With
 // the scalar steps folded (rv.fold), every tile totals the r.r partials of
 // the last vector update (same order in each tile, so the same value),
 // applies the stopping test and forms beta; tile 0 publishes the state.
 // Other tiles of the launch read only rr_prev and iters, which it does not
 // write.  Returns false when the solve has stopped (the tile exits).  red
 // needs 10 doubles; called by the whole workgroup.
-__device__ bool cg_begin_iter(const RveDev& rv, int tile, double* red, double& beta) {
+__device__ bool cg_begin_iter(const RveDev& rv, int tile, int dn, double* red, double& beta) {
   CgState* cg = rv.cg;
   beta = 0.0;
   if (!rv.fold) {
+    if (done_publish(dn)) return false;
     beta = cg->beta;
     return true;
   }
-  if (cg->iters == 0) return true;  // the residual pass has set p = r
+  if (cg->iters == 0) return !done_publish(dn);  // the residual pass has set p = r
   const double rr = sum_partials(rv.partial_rr, rv.tiles[P_VEC], red);
-  if (threadIdx.x == 0) {
+  if (threadIdx.x == 0 && dn) {
+    red[8] = 1.0;  // stopped before this launch: no state change
+  } else if (threadIdx.x == 0) {
     const int it = cg->iters;
     int st = CG_RUNNING;
     if (cg->force >= 0) {
@@ -303,13 +301,17 @@ __global__ void __launch_bounds__(256) k_zfwd(const RveDev* __restrict__ rvs, in
   TileLds<T> L(smem, 3 * rows_per_tile, ld, rv.ax[2], ldmax);
   __shared__ MatDev s_mats[kMaxPhases];  // per-voxel material lookups from LDS
   if (threadIdx.x < rv.n_phases) s_mats[threadIdx.x] = rv.mats[threadIdx.x];
-  if (done_publish(dn)) return;  // also publishes tables and materials
 
   const double* in = (const double*)rv.buf[in_role];
   // CG search direction update fused here: p <- r + beta p (in place: this
-  // tile owns every component of its voxels)
+  // tile owns every component of its voxels).  Either branch ends in a
+  // barrier that also publishes the tables and materials.
   double beta = 0.0;
-  if (update_p && !cg_begin_iter(rv, tile, L.red, beta)) return;
+  if (update_p) {
+    if (!cg_begin_iter(rv, tile, dn, L.red, beta)) return;
+  } else if (done_publish(dn)) {
+    return;
+  }
   const double* rres = (const double*)rv.buf[R_R];
   double* pw = (double*)rv.buf[R_P];
   double nrm = 0.0;
@@ -599,9 +601,13 @@ __global__ void __launch_bounds__(512) k_slab_fwd(const RveDev* __restrict__ rvs
   SlabLds<T> L(smem, n1max, n2max, rv.ax[2], rv.ax[1]);
   __shared__ MatDev s_mats[kMaxPhases];  // per-voxel material lookups from LDS
   if (threadIdx.x < rv.n_phases) s_mats[threadIdx.x] = rv.mats[threadIdx.x];
-  if (done_publish(dn)) return;  // also publishes tables and materials
+  // either branch ends in a barrier that also publishes tables and materials
   double beta = 0.0;
-  if (update_p && !cg_begin_iter(rv, tile, L.red, beta)) return;
+  if (update_p) {
+    if (!cg_begin_iter(rv, tile, dn, L.red, beta)) return;
+  } else if (done_publish(dn)) {
+    return;
+  }
   const double* in = (const double*)rv.buf[in_role];
   const double* rres = (const double*)rv.buf[R_R];
   const double* pin = (const double*)rv.buf[p_in];
@@ -743,18 +749,22 @@ __global__ void __launch_bounds__(256) k_cg_xr(const RveDev* __restrict__ rvs, i
   const int ri = find_rve(rvs, nrve, P_VEC, tile);
   if (ri < 0) return;
   const RveDev& rv = rvs[ri];
-  if (rv.skip || done_flag(rv.cg)) return;
+  if (rv.skip) return;
+  const int dn = done_peek(1, rv.cg);  // overlaps the partial loads below
   const long long nvox = rv.nvox;
   CgState* cg = rv.cg;
   double alpha;
   if (!rv.fold) {
+    if (done_publish(dn)) return;
     alpha = cg->alpha;
   } else {
     // Folded step: every tile totals the p.Ap partials of the product and
     // forms alpha = r.r / p.Ap; tile 0 publishes the state (other tiles
     // read only rr, which no tile of this launch writes).
     const double pap = sum_partials(rv.partial, rv.tiles[P_ZI], red);
-    if (threadIdx.x == 0) {
+    if (threadIdx.x == 0 && dn) {
+      red[8] = 1.0;  // stopped before this launch: no state change
+    } else if (threadIdx.x == 0) {
       const double rr = cg->rr;
       const bool brk = !(pap > 0.0);
       red[8] = brk ? 1.0 : 0.0;

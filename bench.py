@@ -67,7 +67,7 @@ def x_pass_bytes_per_voxel(shape, real_bytes):
 
 def forward_pass_bytes_per_voxel(shape, real_bytes):
     """Algorithmic HBM bytes per voxel of one forward product pass inside CG
-    (k_slab_fwd or k_zfwd): read r and p (6 FP64 each), the compact tangent
+    (k_zfwd or k_slab_fwd): read r and p (6 FP64 each), the compact tangent
     (7 reals of the apply precision) and the phase byte; write the new p (6
     FP64) and the six complex half-spectrum planes.  The y transform of the
     slab form stays in LDS and adds no HBM bytes."""
@@ -77,7 +77,7 @@ def forward_pass_bytes_per_voxel(shape, real_bytes):
 
 
 ROOFLINE_KERNELS = {
-    0: ("forward product pass (k_slab_fwd, or k_zfwd in the five-pass schedule): p <- r + beta p, C:p, "
+    0: ("forward product pass k_zfwd (k_slab_fwd with the fused slab passes): p <- r + beta p, C:p, "
         "DFT along z (and y)", forward_pass_bytes_per_voxel),
     2: ("k_xpass (DFT x, G^(k) projection, inverse DFT x)", x_pass_bytes_per_voxel),
 }

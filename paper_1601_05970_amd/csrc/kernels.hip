@@ -1,7 +1,7 @@
 // HIP kernels of the Galerkin-FFT Newton--CG hot path (gfx950).
 //
 // One application of G:(C:p) (paper Eq. linear_system, with G = F^-1 G^ F of
-// Eq. discrete_projection) is four launches over a half spectrum:
+// Eq. discrete_projection) is five launches over a half spectrum:
 //   zf : tau = C(x):p(x) per voxel, then real-to-complex DFT along axis 2
 //        (two real rows packed into one complex line);
 //   y  : complex DFT along axis 1, per component;
@@ -9,13 +9,15 @@
 //        G^(k):tau^(k) evaluated on the fly from k (Appendix A,
 //        Eq. FT_projection, with G^(0) = 0), inverse DFT along axis 0;
 //   y  : inverse DFT along axis 1;
-//   zi : complex-to-real inverse DFT along axis 2, fused CG dot product.
-// The per-voxel J2 return map and consistent tangent (Sec. 4.2) and the
-// CG vector updates (Algorithm 1) are elementwise kernels.
+//   zi : complex-to-real inverse DFT along axis 2, fused CG dot product;
+// or, where a y-z plane fits in LDS, three (the slab passes fuse zf with y
+// and y with zi).  The per-voxel J2 return map and consistent tangent (Sec.
+// 4.2) and the CG vector updates (Algorithm 1) are elementwise kernels.
 //
 // Every kernel walks a list of tiles that may span several RVEs (batched
-// launches); a single solve is a batch of one.  Reductions are deterministic:
-// per-tile partial sums, summed in fixed order by the last tile to finish.
+// launches); a single solve is a batch of one.  Reductions are deterministic
+// and free of atomics: per-tile partial sums, totalled in a fixed order by
+// the consuming kernel (k_finalize, or every tile of the next kernel).
 #include <hip/hip_runtime.h>
 
 #include "fft_lds.h"

@@ -50,7 +50,7 @@ typedef enum {
   FFTG_E_NOMEM = -2,          /* device or pinned host allocation failed */
   FFTG_E_HIP = -3,            /* a HIP runtime call failed */
   FFTG_E_NOT_CONVERGED = -4,  /* Newton or CG iteration cap reached; stats filled */
-  FFTG_E_BREAKDOWN = -5,      /* CG met p.Ap <= 0 (indefinite tangent); stats filled */
+  FFTG_E_BREAKDOWN = -5,      /* CG met p.Ap <= 0 or not finite (indefinite tangent); stats filled */
   FFTG_E_UNSUPPORTED = -6     /* grid extent or material law not implemented */
 } fftg_status;
 
@@ -192,16 +192,15 @@ fftg_status fftg_batch_solve_increment(fftg_batch batch, const double* dE, fftg_
  * covered (sum over the RVEs each launch processed); any output may be
  * NULL.  Safe to call while other threads solve on distinct plans. */
 typedef enum {
-  FFTG_KERNEL_ZFWD = 0,        /* p update, tangent contraction, real-to-complex DFT along z */
+  FFTG_KERNEL_ZFWD = 0,        /* p update + p.(C:p), tangent contraction, real-to-complex DFT along z */
   FFTG_KERNEL_Y_FWD = 1,       /* DFT along y */
   FFTG_KERNEL_X_PROJ = 2,      /* DFT along x, G^(k) projection, inverse DFT along x */
   FFTG_KERNEL_Y_INV = 3,       /* inverse DFT along y */
-  FFTG_KERNEL_ZINV = 4,        /* complex-to-real inverse DFT along z + CG dot */
-  FFTG_KERNEL_CG_XR = 5,       /* x += alpha p, r -= alpha Ap, r.r */
-  FFTG_KERNEL_FINALIZE = 6,    /* per-RVE totals of tile partial sums, CG scalar steps */
-  FFTG_KERNEL_CONSTITUTIVE = 7,/* J2 return map + consistent tangent */
-  FFTG_KERNEL_NEWTON = 8,      /* eps* += d eps, ||d eps|| */
-  FFTG_KERNEL_COUNT = 9
+  FFTG_KERNEL_ZINV = 4,        /* complex-to-real inverse DFT along z + CG x, r update and r.r */
+  FFTG_KERNEL_FINALIZE = 5,    /* per-RVE totals of tile partial sums, CG scalar steps */
+  FFTG_KERNEL_CONSTITUTIVE = 6,/* J2 return map + consistent tangent */
+  FFTG_KERNEL_NEWTON = 7,      /* eps* += d eps, ||d eps|| */
+  FFTG_KERNEL_COUNT = 8
 } fftg_kernel_id;
 fftg_status fftg_profiler_start(int kernel_id);
 fftg_status fftg_profiler_stop(double* total_ms, long long* launches, double* voxels);

@@ -71,7 +71,7 @@ enum CgStatus { CG_RUNNING = 0, CG_CONVERGED = 1, CG_MAXITER = 2, CG_BREAKDOWN =
 
 // Buffer roles referenced by kernels through the descriptor.
 enum Role {
-  R_EPS_FL = 0, R_EPS_P, R_EPBAR, R_SIG, R_X, R_R, R_P, R_AP, R_P2, R_USER_IN, R_USER_OUT, R_NROLES
+  R_EPS_FL = 0, R_EPS_P, R_EPBAR, R_SIG, R_X, R_R, R_P, R_P2, R_USER_IN, R_USER_OUT, R_NROLES
 };
 
 enum Pass { P_ZF = 0, P_Y, P_X, P_ZI, P_VEC, P_NPASS };
@@ -80,7 +80,7 @@ struct RveDev {
   int n0, n1, n2, H;
   long long nvox, nspec;
   AxisDev ax[3];             // transforms of axes x, y, z (by value: one load less per kernel)
-  void* buf[R_NROLES];       // double* except R_AP / R_USER_OUT in mixed mode
+  void* buf[R_NROLES];       // double* except R_USER_OUT in mixed mode
   void* tang;                // 7 planes, double (FP64) or float (mixed)
   void* spec;                // 6 complex planes, sized for double
   const uint8_t* phase;
@@ -88,7 +88,7 @@ struct RveDev {
   int n_phases;
   int mixed;                 // apply precision: 0 double, 1 float
   CgState* cg;
-  double* partial;           // per-block partial sums, >= tiles of any pass
+  double* partial;           // per-block partial sums, >= tiles of any pass (p.(C:p) in CG)
   double* partial_rr;        // per-block partial sums of r.r in CG (disjoint from partial)
   double E[6];               // mean strain, Mandel
   double dE[6];              // load increment, Mandel
@@ -101,10 +101,17 @@ struct RveDev {
 // Apply modes (kernel flags)
 enum ApplyIn { IN_ROLE = 0, IN_CONST_DE = 1 };
 enum Tangent { TAN_CURRENT = 0, TAN_IDENTITY = 1, TAN_ELASTIC = 2 };
+// p update of the forward pass (kernel flag update_p)
+enum PUpdate {
+  PU_NONE = 0,   // product of the input role
+  PU_CG = 1,     // p <- r + beta p (stopping test and beta folded in), partials of p.(C:p)
+  PU_TIMING = 2  // as PU_CG with beta = 0, reading and writing no CG state (timing outside a solve)
+};
 enum ApplyOut {
-  OUT_CG = 0,        // write AP, dot p.AP -> pAp, alpha
-  OUT_RESIDUAL = 1,  // write R and P, zero X, dot r.r -> rr, bnorm2, target2
-  OUT_PLAIN = 2      // write the out role only
+  OUT_CG = 0,        // x += alpha p, r -= alpha G:(C:p) (alpha folded in), partials of r.r
+  OUT_RESIDUAL = 1,  // write R and P, zero X, partials of r.r -> rr, bnorm2, target2
+  OUT_PLAIN = 2,     // write the out role only
+  OUT_CG_TIMING = 3  // as OUT_CG with alpha = 0, reading and writing no CG state (timing outside a solve)
 };
 
 struct LaunchCfg {

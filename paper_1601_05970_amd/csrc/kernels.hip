@@ -9,10 +9,14 @@
 //        G^(k):tau^(k) evaluated on the fly from k (Appendix A,
 //        Eq. FT_projection, with G^(0) = 0), inverse DFT along axis 0;
 //   y  : inverse DFT along axis 1;
-//   zi : complex-to-real inverse DFT along axis 2, fused CG dot product;
+//   zi : complex-to-real inverse DFT along axis 2;
 // or, where a y-z plane fits in LDS, three (the slab passes fuse zf with y
-// and y with zi).  The per-voxel J2 return map and consistent tangent (Sec.
-// 4.2) and the CG vector updates (Algorithm 1) are elementwise kernels.
+// and y with zi).  Inside CG (Algorithm 1) the first pass also forms
+// p <- r + beta p and the partial sums of p.(C:p), and the last one applies
+// x += alpha p, r -= alpha G:(C:p) and sums r.r, so an iteration is the five
+// (or three) product launches and nothing else.  The per-voxel J2 return map
+// and consistent tangent (Sec. 4.2) and the Newton update are elementwise
+// kernels.
 //
 // Every kernel walks a list of tiles that may span several RVEs (batched
 // launches); a single solve is a batch of one.  Reductions are deterministic
@@ -88,8 +92,10 @@ __device__ __forceinline__ void put_partials(const double* vals, int nv, double*
 }
 
 // Sum of p[0..n) over the workgroup in a fixed order (four strided
-// accumulators per thread, then the block tree); valid in thread 0.
-__device__ double sum_partials(const double* __restrict__ p, int n, double* sh) {
+// accumulators per thread, then the block tree); valid in thread 0.  Split in
+// two so that a kernel can issue the loads of its own share early and reduce
+// later: thread_partials is the per-thread part, block_sum the rest.
+__device__ __forceinline__ double thread_partials(const double* __restrict__ p, int n) {
   const int st = blockDim.x;
   double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
   int t = threadIdx.x;
@@ -100,7 +106,10 @@ __device__ double sum_partials(const double* __restrict__ p, int n, double* sh) 
     a3 += p[t + 3 * st];
   }
   for (; t < n; t += st) a0 += p[t];
-  return block_sum((a0 + a1) + (a2 + a3), sh);
+  return (a0 + a1) + (a2 + a3);
+}
+__device__ double sum_partials(const double* __restrict__ p, int n, double* sh) {
+  return block_sum(thread_partials(p, n), sh);
 }
 
 // The CG stop flag, read once per workgroup and shared through LDS: in the
@@ -120,17 +129,6 @@ __device__ __forceinline__ int done_publish(int v) {
   __syncthreads();
   return s_done2;
 }
-
-template <class T>
-struct ApType;
-template <>
-struct ApType<double> {
-  typedef double type;
-};
-template <>
-struct ApType<float> {
-  typedef float type;
-};
 
 // Compact consistent tangent applied to a Mandel vector:
 // tau = (K - g2/3) tr(p) [1,1,1,0,0,0] + g2 p - (m.p) m.
@@ -191,25 +189,38 @@ struct TileLds {
 // the scalar steps folded (rv.fold), every tile totals the r.r partials of
 // the last vector update (same order in each tile, so the same value),
 // applies the stopping test and forms beta; tile 0 publishes the state.
-// Other tiles of the launch read only rr_prev and iters, which it does not
-// write.  Returns false when the solve has stopped (the tile exits).  red
-// needs 10 doubles; called by the whole workgroup.
-__device__ bool cg_begin_iter(const RveDev& rv, int tile, int dn, double* red, double& beta) {
+// Other tiles of the launch read only rr_prev, iters and status: tile 0
+// writes no rr_prev or iters, and it writes CG_BREAKDOWN, the one status
+// value tested, only where status already holds it (a breakdown is found by
+// the vector update, which must not write the stop flag that its own tiles
+// read; the solve stops here).  Returns
+// false when the solve has stopped (the tile exits).  red needs 10 doubles;
+// called by the whole workgroup.  PU_TIMING does the same loads and sums
+// with beta = 0 and no state.
+__device__ bool cg_begin_iter(const RveDev& rv, int tile, int dn, int mode, double* red, double& beta) {
   CgState* cg = rv.cg;
+  const bool timing = mode == PU_TIMING;
   beta = 0.0;
   if (!rv.fold) {
     if (done_publish(dn)) return false;
-    beta = cg->beta;
+    if (!timing) beta = cg->beta;
     return true;
   }
-  if (cg->iters == 0) return !done_publish(dn);  // the residual pass has set p = r
-  const double rr = sum_partials(rv.partial_rr, rv.tiles[P_VEC], red);
+  if (!timing && cg->iters == 0) return !done_publish(dn);  // the residual pass has set p = r
+  const double rr = sum_partials(rv.partial_rr, rv.tiles[P_ZI], red);
+  if (timing) {
+    if (threadIdx.x == 0) red[9] = rr;
+    __syncthreads();
+    return true;
+  }
   if (threadIdx.x == 0 && dn) {
     red[8] = 1.0;  // stopped before this launch: no state change
   } else if (threadIdx.x == 0) {
     const int it = cg->iters;
     int st = CG_RUNNING;
-    if (cg->force >= 0) {
+    if (cg->status == CG_BREAKDOWN) {
+      st = CG_BREAKDOWN;
+    } else if (cg->force >= 0) {
       if (it >= cg->force) st = CG_FORCED;
     } else if (rr <= cg->target2) {
       st = CG_CONVERGED;
@@ -237,16 +248,18 @@ __device__ bool cg_begin_iter(const RveDev& rv, int tile, int dn, double* red, d
 }
 
 // tau = C(x):p(x) at voxel v for the input modes of the forward pass.  With
-// update_p, p = r + beta p_old is formed here and its components
+// update_p, p = r + beta p_old is formed here, its components
 // [own_lo, own_hi) are stored to p_new (p_new may equal p_old when the
-// caller owns all six components of the voxel).
+// caller owns all six components of the voxel), and the return value is
+// their share of p.tau (else 0).
 template <class T>
-__device__ __forceinline__ void voxel_tau(const RveDev& rv, long long v, int in_mode, const double* __restrict__ in,
+__device__ __forceinline__ double voxel_tau(const RveDev& rv, long long v, int in_mode, const double* __restrict__ in,
                                           int update_p, double beta, const double* __restrict__ rres,
                                           const double* p_old, double* p_new, int own_lo, int own_hi,
                                           int tan_mode, const MatDev* __restrict__ mats, T tau[6]) {
   const long long nvox = rv.nvox;
   T p[6];
+  double pd[6];
   if (in_mode == IN_CONST_DE) {
 #pragma unroll
     for (int c = 0; c < 6; ++c) p[c] = T(rv.dE[c]);
@@ -255,6 +268,7 @@ __device__ __forceinline__ void voxel_tau(const RveDev& rv, long long v, int in_
     for (int c = 0; c < 6; ++c) {
       const double pn = rres[c * nvox + v] + beta * p_old[c * nvox + v];
       if (c >= own_lo && c < own_hi) p_new[c * nvox + v] = pn;
+      pd[c] = pn;
       p[c] = T(pn);
     }
   } else {
@@ -279,6 +293,13 @@ __device__ __forceinline__ void voxel_tau(const RveDev& rv, long long v, int in_
     }
     tangent_apply<T>(p, T(mt.K), g2, m, tau);
   }
+  double d = 0.0;
+  if (update_p) {
+#pragma unroll
+    for (int c = 0; c < 6; ++c)
+      if (c >= own_lo && c < own_hi) d += pd[c] * double(tau[c]);
+  }
+  return d;
 }
 
 // ------------------------------------------------------------- z forward
@@ -310,20 +331,20 @@ __global__ void __launch_bounds__(256) k_zfwd(const RveDev* __restrict__ rvs, in
   // barrier that also publishes the tables and materials.
   double beta = 0.0;
   if (update_p) {
-    if (!cg_begin_iter(rv, tile, dn, L.red, beta)) return;
+    if (!cg_begin_iter(rv, tile, dn, update_p, L.red, beta)) return;
   } else if (done_publish(dn)) {
     return;
   }
   const double* rres = (const double*)rv.buf[R_R];
   double* pw = (double*)rv.buf[R_P];
-  double nrm = 0.0;
+  double nrm = 0.0;  // ||tau||^2 (want_norm) or p.tau (update_p)
   const FastDiv fn2(n2), fH(H), f3(3);
   for (int t = threadIdx.x; t < nrows * n2; t += blockDim.x) {
     const int r = fn2.div(t);
     const int z = t - r * n2;
     const long long v = (long long)(row0 + r) * n2 + z;
     T tau[6];
-    voxel_tau<T>(rv, v, in_mode, in, update_p, beta, rres, pw, pw, 0, 6, tan_mode, s_mats, tau);
+    nrm += voxel_tau<T>(rv, v, in_mode, in, update_p, beta, rres, pw, pw, 0, 6, tan_mode, s_mats, tau);
     if (want_norm) {
 #pragma unroll
       for (int c = 0; c < 6; ++c) nrm += double(tau[c]) * double(tau[c]);
@@ -347,7 +368,7 @@ __global__ void __launch_bounds__(256) k_zfwd(const RveDev* __restrict__ rvs, in
     spec[(2 * pr) * nspec + o] = A;
     spec[(2 * pr + 1) * nspec + o] = B;
   }
-  if (want_norm) {
+  if (want_norm || update_p) {
     const double s = block_sum(nrm, L.red);
     put_partials(&s, 1, rv.partial, rv.tiles[P_ZF], tile);
   }
@@ -458,6 +479,57 @@ __global__ void __launch_bounds__(256) k_xpass(const RveDev* __restrict__ rvs, i
   }
 }
 
+// alpha = r.r / p.(C:p) for the CG vector update of the inverse z pass.  p is
+// compatible (a combination of outputs of G) and G is an orthogonal
+// projection, so p.(C:p) = (G p).(C:p) = p.G:(C:p) = p.Ap: the forward pass
+// sums it while p and C:p are in registers, and alpha is known before the
+// inverse transform ends.  Folded (rv.fold): every tile totals the forward
+// pass's partials (pa: this thread's share, loaded early by the caller; same
+// order in each tile, so the same value) and tile 0 publishes the state;
+// the other tiles read only rr, which no tile of this launch writes.  A
+// breakdown (p.(C:p) <= 0 or not finite) makes every tile exit unchanged and
+// is recorded in status only, for the next forward pass to stop the solve:
+// the stop flag is read by all threads of these tiles without a barrier.
+// Not folded: k_finalize formed alpha (and the stop flag, before this
+// launch).  Returns false when the tile must exit.  Called by the whole
+// workgroup (its barriers also publish the caller's LDS writes).  With
+// timing, the same loads and sums give alpha = 0 and touch no state.
+__device__ bool cg_alpha(const RveDev& rv, int tile, double pa, bool timing, double* red, double& alpha) {
+  CgState* cg = rv.cg;
+  alpha = 0.0;
+  if (!rv.fold) {
+    __syncthreads();
+    if (!timing) alpha = cg->alpha;
+    return true;
+  }
+  const double pap = block_sum(pa, red);
+  if (threadIdx.x == 0) {
+    if (timing) {
+      red[8] = 0.0;
+      red[9] = 0.0 * pap;
+    } else {
+      const double rr = cg->rr;
+      const bool brk = !(pap > 0.0) || !(pap < INFINITY);
+      red[8] = brk ? 1.0 : 0.0;
+      red[9] = rr / pap;
+      if (tile == 0) {
+        cg->pAp = pap;
+        if (brk) {
+          cg->status = CG_BREAKDOWN;
+        } else {
+          cg->alpha = rr / pap;
+          cg->rr_prev = rr;
+          cg->iters += 1;
+        }
+      }
+    }
+  }
+  __syncthreads();
+  if (red[8] != 0.0) return false;
+  alpha = red[9];
+  return true;
+}
+
 // ------------------------------------------------------------- z inverse
 template <class T, int BIG>
 __global__ void __launch_bounds__(256) k_zinv(const RveDev* __restrict__ rvs, int nrve, int rows_per_tile, int ldmax,
@@ -477,6 +549,9 @@ __global__ void __launch_bounds__(256) k_zinv(const RveDev* __restrict__ rvs, in
   const int ld = n2;
   TileLds<T> L(smem, 3 * rows_per_tile, ld, rv.ax[2], ldmax);
   if (dn) return;
+  const bool cg_out = out_mode == OUT_CG || out_mode == OUT_CG_TIMING;
+  // this thread's share of the p.(C:p) partials, loaded with the spectrum
+  const double pa = (cg_out && rv.fold) ? thread_partials(rv.partial, rv.tiles[P_ZF]) : 0.0;
   const cx<T>* spec = (const cx<T>*)rv.spec;
   // Z_k = A_k + i B_k, Z_{n-k} = conj(A_k) + i conj(B_k)
   const FastDiv fn2(n2), f3(3);
@@ -498,13 +573,19 @@ __global__ void __launch_bounds__(256) k_zinv(const RveDev* __restrict__ rvs, in
     }
     L.line[rp * ld + z] = Z;
   }
-  __syncthreads();
+  double alpha = 0.0;
+  if (cg_out) {
+    if (!cg_alpha(rv, tile, pa, out_mode == OUT_CG_TIMING, L.red, alpha)) return;
+  } else {
+    __syncthreads();
+  }
   cx<T>* res = line_fft<1, T, BIG>(L.line, L.scratch, ld, 3 * nrows, L.ax, L.dc);
   double dot = 0.0;
-  if (out_mode == OUT_CG) {
-    typedef typename ApType<T>::type AT;
-    AT* out = (AT*)rv.buf[R_AP];
-    const double* p = (const double*)rv.buf[p_role];
+  if (cg_out) {
+    // x += alpha p, r -= alpha G:(C:p), partials of the new r.r
+    double* __restrict__ xx = (double*)rv.buf[R_X];
+    double* __restrict__ rr = (double*)rv.buf[R_R];
+    const double* __restrict__ p = (const double*)rv.buf[p_role];
     for (int t = threadIdx.x; t < nrows * n2; t += blockDim.x) {
       const int r = fn2.div(t);
       const int z = t - r * n2;
@@ -512,12 +593,18 @@ __global__ void __launch_bounds__(256) k_zinv(const RveDev* __restrict__ rvs, in
 #pragma unroll
       for (int pr = 0; pr < 3; ++pr) {
         const cx<T> w = res[(3 * r + pr) * ld + z];
-        const AT a0 = AT(w.re), a1 = AT(w.im);
-        out[(2 * pr) * nvox + v] = a0;
-        out[(2 * pr + 1) * nvox + v] = a1;
-        dot += p[(2 * pr) * nvox + v] * double(a0) + p[(2 * pr + 1) * nvox + v] * double(a1);
+        const long long i0 = (2 * pr) * nvox + v, i1 = (2 * pr + 1) * nvox + v;
+        const double r0 = rr[i0] - alpha * double(w.re), r1 = rr[i1] - alpha * double(w.im);
+        xx[i0] += alpha * p[i0];
+        xx[i1] += alpha * p[i1];
+        rr[i0] = r0;
+        rr[i1] = r1;
+        dot += r0 * r0 + r1 * r1;
       }
     }
+    const double s = block_sum(dot, L.red);
+    put_partials(&s, 1, rv.partial_rr, rv.tiles[P_ZI], tile);
+    return;
   } else if (out_mode == OUT_RESIDUAL) {
     double* rr = (double*)rv.buf[R_R];
     double* pp = (double*)rv.buf[R_P];
@@ -606,7 +693,7 @@ __global__ void __launch_bounds__(512) k_slab_fwd(const RveDev* __restrict__ rvs
   // either branch ends in a barrier that also publishes tables and materials
   double beta = 0.0;
   if (update_p) {
-    if (!cg_begin_iter(rv, tile, dn, L.red, beta)) return;
+    if (!cg_begin_iter(rv, tile, dn, update_p, L.red, beta)) return;
   } else if (done_publish(dn)) {
     return;
   }
@@ -616,11 +703,11 @@ __global__ void __launch_bounds__(512) k_slab_fwd(const RveDev* __restrict__ rvs
   double* pout = (double*)rv.buf[p_out];
   const long long v0 = (long long)x * n1 * n2;
   const int npl = n1 * n2;
-  double nrm = 0.0;
+  double nrm = 0.0;  // ||tau||^2 (want_norm) or p.tau over the tile's components (update_p)
   for (int t = threadIdx.x; t < npl; t += blockDim.x) {
     T tau[6];
-    voxel_tau<T>(rv, v0 + t, in_mode, in, update_p, beta, rres, pin, pout, 2 * pr, 2 * pr + 2, tan_mode, s_mats,
-                 tau);
+    nrm += voxel_tau<T>(rv, v0 + t, in_mode, in, update_p, beta, rres, pin, pout, 2 * pr, 2 * pr + 2, tan_mode,
+                        s_mats, tau);
     const T a = tau[2 * pr], b = tau[2 * pr + 1];
     if (want_norm) nrm += double(a) * double(a) + double(b) * double(b);
     L.b0[t] = cx<T>{a, b};  // z-line y at y * n2
@@ -647,7 +734,7 @@ __global__ void __launch_bounds__(512) k_slab_fwd(const RveDev* __restrict__ rvs
     const int c2 = fn1.div(cy), y = cy - c2 * n1;
     spec[(2 * pr + c2) * nspec + ((long long)x * n1 + y) * H + k] = res2[(c2 * H + k) * n1 + y];
   }
-  if (want_norm) {
+  if (want_norm || update_p) {
     const double s = block_sum(nrm, L.red);
     put_partials(&s, 1, rv.partial, rv.tiles[P_ZF], tile);
   }
@@ -668,6 +755,9 @@ __global__ void __launch_bounds__(512) k_slab_inv(const RveDev* __restrict__ rvs
   const int x = tile / 3, pr = tile - 3 * (tile / 3);
   SlabLds<T> L(smem, n1max, n2max, rv.ax[2], rv.ax[1]);
   if (check_done && done_publish(dn)) return;
+  const bool cg_out = out_mode == OUT_CG || out_mode == OUT_CG_TIMING;
+  // this thread's share of the p.(C:p) partials, loaded with the spectrum
+  const double pa = (cg_out && rv.fold) ? thread_partials(rv.partial, rv.tiles[P_ZF]) : 0.0;
   const cx<T>* spec = (const cx<T>*)rv.spec;
   const FastDiv fH(H), fn1(n1), fn2(n2);
   for (int t = threadIdx.x; t < 2 * n1 * H; t += blockDim.x) {
@@ -676,7 +766,12 @@ __global__ void __launch_bounds__(512) k_slab_inv(const RveDev* __restrict__ rvs
     const int c2 = fn1.div(cy), y = cy - c2 * n1;
     L.b0[(c2 * H + k) * n1 + y] = spec[(2 * pr + c2) * nspec + ((long long)x * n1 + y) * H + k];
   }
-  __syncthreads();
+  double alpha = 0.0;
+  if (cg_out) {
+    if (!cg_alpha(rv, tile, pa, out_mode == OUT_CG_TIMING, L.red, alpha)) return;
+  } else {
+    __syncthreads();
+  }
   cx<T>* res = line_fft<1, T, BIG>(L.b0, L.b1, n1, 2 * H, L.ay, L.dc);
   cx<T>* oth = (res == L.b0) ? L.b1 : L.b0;
   // z-line y: Z_z = A_z + i B_z, Z_{n2-k} = conj(A_k) + i conj(B_k)
@@ -699,18 +794,25 @@ __global__ void __launch_bounds__(512) k_slab_inv(const RveDev* __restrict__ rvs
   const long long v0 = (long long)x * n1 * n2;
   const int c0 = 2 * pr, c1 = 2 * pr + 1;
   double dot = 0.0;
-  if (out_mode == OUT_CG) {
-    typedef typename ApType<T>::type AT;
-    AT* out = (AT*)rv.buf[R_AP];
-    const double* p = (const double*)rv.buf[p_role];
+  if (cg_out) {
+    // x += alpha p, r -= alpha G:(C:p) on the tile's two components, partials of r.r
+    double* __restrict__ xx = (double*)rv.buf[R_X];
+    double* __restrict__ rr = (double*)rv.buf[R_R];
+    const double* __restrict__ p = (const double*)rv.buf[p_role];
     for (int t = threadIdx.x; t < n1 * n2; t += blockDim.x) {
       const long long v = v0 + t;
       const cx<T> w = res2[t];
-      const AT a0 = AT(w.re), a1 = AT(w.im);
-      out[c0 * nvox + v] = a0;
-      out[c1 * nvox + v] = a1;
-      dot += p[c0 * nvox + v] * double(a0) + p[c1 * nvox + v] * double(a1);
+      const long long i0 = c0 * nvox + v, i1 = c1 * nvox + v;
+      const double r0 = rr[i0] - alpha * double(w.re), r1 = rr[i1] - alpha * double(w.im);
+      xx[i0] += alpha * p[i0];
+      xx[i1] += alpha * p[i1];
+      rr[i0] = r0;
+      rr[i1] = r1;
+      dot += r0 * r0 + r1 * r1;
     }
+    const double s = block_sum(dot, L.red);
+    put_partials(&s, 1, rv.partial_rr, rv.tiles[P_ZI], tile);
+    return;
   } else if (out_mode == OUT_RESIDUAL) {
     double* rr = (double*)rv.buf[R_R];
     double* pp = (double*)rv.buf[R_P];
@@ -741,81 +843,7 @@ __global__ void __launch_bounds__(512) k_slab_inv(const RveDev* __restrict__ rvs
   put_partials(&s, 1, rv.partial, rv.tiles[P_ZI], tile);
 }
 
-// ------------------------------------------------------ CG vector updates
-// x += alpha p; r -= alpha Ap; per-tile partials of r.r.
-template <class AT>
-__global__ void __launch_bounds__(256) k_cg_xr(const RveDev* __restrict__ rvs, int nrve, int vox_per_tile,
-                                               int p_role) {
-  __shared__ double red[16];
-  int tile;
-  const int ri = find_rve(rvs, nrve, P_VEC, tile);
-  if (ri < 0) return;
-  const RveDev& rv = rvs[ri];
-  if (rv.skip) return;
-  const int dn = done_peek(1, rv.cg);  // overlaps the partial loads below
-  const long long nvox = rv.nvox;
-  CgState* cg = rv.cg;
-  double alpha;
-  if (!rv.fold) {
-    if (done_publish(dn)) return;
-    alpha = cg->alpha;
-  } else {
-    // Folded step: every tile totals the p.Ap partials of the product and
-    // forms alpha = r.r / p.Ap; tile 0 publishes the state (other tiles
-    // read only rr, which no tile of this launch writes).
-    const double pap = sum_partials(rv.partial, rv.tiles[P_ZI], red);
-    if (threadIdx.x == 0 && dn) {
-      red[8] = 1.0;  // stopped before this launch: no state change
-    } else if (threadIdx.x == 0) {
-      const double rr = cg->rr;
-      const bool brk = !(pap > 0.0);
-      red[8] = brk ? 1.0 : 0.0;
-      red[9] = rr / pap;
-      if (tile == 0) {
-        cg->pAp = pap;
-        if (brk) {
-          cg->status = CG_BREAKDOWN;
-          __hip_atomic_store(&cg->done, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        } else {
-          cg->alpha = rr / pap;
-          cg->rr_prev = rr;
-          cg->iters += 1;
-        }
-      }
-    }
-    __syncthreads();
-    if (red[8] != 0.0) return;
-    alpha = red[9];
-  }
-  double* __restrict__ x = (double*)rv.buf[R_X];
-  double* __restrict__ r = (double*)rv.buf[R_R];
-  const double* __restrict__ p = (const double*)rv.buf[p_role];
-  const AT* __restrict__ ap = (const AT*)rv.buf[R_AP];
-  const long long v0 = (long long)tile * vox_per_tile;
-  const int nv = (int)min((long long)vox_per_tile, nvox - v0);
-  double acc = 0.0;
-  for (int t = threadIdx.x; t < nv; t += blockDim.x) {
-    const long long v = v0 + t;
-    double xv[6], rv6[6], pv[6], av[6];
-#pragma unroll
-    for (int c = 0; c < 6; ++c) {
-      xv[c] = x[c * nvox + v];
-      rv6[c] = r[c * nvox + v];
-      pv[c] = p[c * nvox + v];
-      av[c] = double(ap[c * nvox + v]);
-    }
-#pragma unroll
-    for (int c = 0; c < 6; ++c) {
-      const double rn = rv6[c] - alpha * av[c];
-      x[c * nvox + v] = xv[c] + alpha * pv[c];
-      r[c * nvox + v] = rn;
-      acc += rn * rn;
-    }
-  }
-  const double s = block_sum(acc, red);
-  put_partials(&s, 1, rv.partial_rr, rv.tiles[P_VEC], tile);
-}
-
+// ------------------------------------------------------- Newton update
 // eps* += x (Algorithm 1, iterative update) and ||x||^2.
 __global__ void __launch_bounds__(256) k_newton_update(const RveDev* __restrict__ rvs, int nrve, int vox_per_tile) {
   __shared__ double red[16];
@@ -944,8 +972,9 @@ __global__ void __launch_bounds__(256) k_constitutive(const RveDev* __restrict__
 // kernel in a fixed order and applies the scalar step that uses the total.
 //   FIN_SNORM  ||C:dE||^2 of the right-hand side floor
 //   FIN_RESID  b.b of the CG right-hand side: target, start or skip of CG
-//   FIN_PAP    p.Ap: alpha = r.r / p.Ap (breakdown when p.Ap <= 0)
-//   FIN_RR     r.r after the update: iteration count, stopping test, beta
+//   FIN_PAP    p.(C:p) = p.Ap of the forward pass: alpha = r.r / p.Ap
+//              (breakdown when p.Ap <= 0 or not finite)
+//   FIN_RR     r.r after the vector update: iteration count, stopping test, beta
 //   FIN_DNORM  ||d eps||^2 of the Newton update
 //   FIN_SIGMA  volume average of sigma (six sums)
 __global__ void __launch_bounds__(256) k_finalize(const RveDev* __restrict__ rvs, int nrve, int step) {
@@ -956,7 +985,8 @@ __global__ void __launch_bounds__(256) k_finalize(const RveDev* __restrict__ rvs
   if (rv.skip) return;
   CgState* cg = rv.cg;
   if ((step == FIN_PAP || step == FIN_RR) && (rv.fold || cg->done)) return;
-  const int pass = step == FIN_SNORM ? P_ZF : ((step == FIN_RESID || step == FIN_PAP) ? P_ZI : P_VEC);
+  const int pass = (step == FIN_SNORM || step == FIN_PAP) ? P_ZF
+                   : ((step == FIN_RESID || step == FIN_RR) ? P_ZI : P_VEC);
   const int nt = rv.tiles[pass];
   const int nv = step == FIN_SIGMA ? 6 : 1;
   const double* part = step == FIN_RR ? rv.partial_rr : rv.partial;
@@ -986,7 +1016,7 @@ __global__ void __launch_bounds__(256) k_finalize(const RveDev* __restrict__ rvs
     }
     case FIN_PAP:
       cg->pAp = t;
-      if (!(t > 0.0)) {
+      if (!(t > 0.0) || !(t < INFINITY)) {
         cg->done = 1;
         cg->status = CG_BREAKDOWN;
       } else {
@@ -1185,16 +1215,6 @@ hipError_t launch_slab_inv(int mixed, const RveDev* rv, int nrve, int tiles, con
   if (tiles <= 0) return hipSuccess;
   DISPATCH_TB(slab_inv_go, dim3(tiles), dim3(cfg.threads_s), lds, s, rv, nrve, cfg.n1max, cfg.n2max, out_mode,
               out_role, check_done, p_role);
-  return hipGetLastError();
-}
-
-hipError_t launch_cg_xr(int mixed, const RveDev* rv, int nrve, int tiles, const LaunchCfg& cfg, int p_role,
-                        hipStream_t s) {
-  if (tiles <= 0) return hipSuccess;
-  if (mixed)
-    hipLaunchKernelGGL(k_cg_xr<float>, dim3(tiles), dim3(cfg.threads_v), 0, s, rv, nrve, cfg.vec_per_tile, p_role);
-  else
-    hipLaunchKernelGGL(k_cg_xr<double>, dim3(tiles), dim3(cfg.threads_v), 0, s, rv, nrve, cfg.vec_per_tile, p_role);
   return hipGetLastError();
 }
 

@@ -38,8 +38,6 @@ hipError_t launch_slab_fwd(int mixed, const RveDev* rv, int nrve, int tiles, con
                            int p_in, int p_out, hipStream_t s);
 hipError_t launch_slab_inv(int mixed, const RveDev* rv, int nrve, int tiles, const LaunchCfg& cfg, size_t lds,
                            int out_mode, int out_role, int check_done, int p_role, hipStream_t s);
-hipError_t launch_cg_xr(int mixed, const RveDev* rv, int nrve, int tiles, const LaunchCfg& cfg, int p_role,
-                        hipStream_t s);
 hipError_t launch_newton_update(const RveDev* rv, int nrve, int tiles, const LaunchCfg& cfg, hipStream_t s);
 hipError_t launch_finalize(const RveDev* rv, int nrve, int step, hipStream_t s);
 hipError_t launch_constitutive(int mixed, const RveDev* rv, int nrve, int tiles, const LaunchCfg& cfg,
@@ -286,7 +284,6 @@ struct fftg_plan_s {
   void* spec;
   double *sig, *x, *r, *p;
   double* p2;        // second search-direction buffer (slab passes only; else null)
-  void* ap;
   double* partial;
   CgState* cg;
   RveDev* d_rv;       // single-RVE descriptor slot
@@ -431,7 +428,6 @@ static size_t plan_bytes(int n0, int n1, int n2, int mixed) {
   b += 6 * nspec * 16;                   // spectrum (complex double)
   b += 4 * 6 * nvox * 8;                 // sig, x, r, p
   if (slab_fits(n1, n2)) b += 6 * nvox * 8;  // second p buffer
-  b += 6 * nvox * (mixed ? 4 : 8);       // Ap
   b += nvox;                             // phase
   b += 6 * (size_t)max_tiles_any(n0, n1, n2, nvox) * 8 + 4096;
   return b;
@@ -546,7 +542,6 @@ fftg_status fftg_plan_create(fftg_plan* out, int n0, int n1, int n2, const uint8
   PLAN_TRY(dalloc(pl, &pl->p, (size_t)6 * nvox * 8));
   pl->p2 = nullptr;
   if (slab_fits(n1, n2)) PLAN_TRY(dalloc(pl, &pl->p2, (size_t)6 * nvox * 8));
-  PLAN_TRY(dalloc(pl, &pl->ap, (size_t)6 * nvox * (pl->mixed ? 4 : 8)));
   pl->max_tiles = max_tiles_any(n0, n1, n2, nvox);
   PLAN_TRY(dalloc(pl, &pl->partial, (size_t)6 * pl->max_tiles * 8 + 64));
   PLAN_TRY(dalloc(pl, &pl->cg, sizeof(CgState)));
@@ -718,7 +713,6 @@ static void fill_desc(RveDev& rv, fftg_plan pl, fftg_history h, const LaunchCfg&
   rv.buf[R_R] = pl->r;
   rv.buf[R_P] = pl->p;
   rv.buf[R_P2] = pl->p2;
-  rv.buf[R_AP] = pl->ap;
   if (h) {
     rv.buf[R_EPS_FL] = h->eps_fl;
     rv.buf[R_EPS_P] = h->eps_p;
@@ -796,9 +790,10 @@ static void group_totals(Group& g) {
 // The CG scalar steps (alpha from p.Ap, the stopping test and beta from
 // r.r) run inside the consumer kernels when every one of their tiles can
 // total the producer's partials cheaply: the L2 reads of that redundant sum
-// grow as (product tiles) x (vector tiles).  Larger RVEs use k_finalize.
+// grow as (forward-pass tiles) x (inverse-pass tiles).  Larger RVEs use
+// k_finalize.
 constexpr long long kFoldMax = 1LL << 23;
-static bool fold_ok(const RveDev& rv) { return (long long)rv.tiles[P_ZI] * rv.tiles[P_VEC] <= kFoldMax; }
+static bool fold_ok(const RveDev& rv) { return (long long)rv.tiles[P_ZF] * rv.tiles[P_ZI] <= kFoldMax; }
 
 // Uploads the host descriptors (stream-ordered, through a pinned slot).
 static fftg_status group_upload(Group& g) {
@@ -845,8 +840,9 @@ static void set_skip(Group& g, size_t i, bool skip) {
 // -------------------------------------------------------- apply sequences
 // G:(C:in) into the out mode; in_role / const dE input.  With update_p the
 // product forms p <- r + beta p from p_in into p_out first (the 5-pass
-// schedule updates in place and takes p_in = p_out = R_P); the CG dot of
-// OUT_CG uses p_out.
+// schedule updates in place and takes p_in = p_out = R_P) and sums p.(C:p);
+// the CG vector update of OUT_CG uses p_out.  Where the scalar steps are not
+// folded, k_finalize forms alpha between the passes and beta after them.
 static fftg_status enqueue_apply(Group& g, int mixed, int in_mode, int in_role, int tan_mode, int want_norm,
                                  int out_mode, int out_role, double scale, int check_done, int update_p = 0,
                                  int p_in = R_P, int p_out = R_P) {
@@ -858,13 +854,16 @@ static fftg_status enqueue_apply(Group& g, int mixed, int in_mode, int in_role, 
                                                   tan_mode, want_norm, check_done, update_p, p_in, p_out,
                                                   g.stream));
   } else {
-    const size_t lz = mixed ? g.lds_zf32 : g.lds_zf, ly = mixed ? g.lds_y32 : g.lds_y;
+    const size_t lz = mixed ? g.lds_zf32 : g.lds_zf;
     PROF_LAUNCH(FFTG_KERNEL_ZFWD, launch_zfwd(mixed, g.d, nr, g.total[P_ZF], g.cfg, lz, in_mode, in_role, tan_mode,
                                               want_norm, check_done, update_p, g.stream));
-    if (want_norm) PROF_LAUNCH(FFTG_KERNEL_FINALIZE, launch_finalize(g.d, nr, FIN_SNORM, g.stream));
+  }
+  if (want_norm) PROF_LAUNCH(FFTG_KERNEL_FINALIZE, launch_finalize(g.d, nr, FIN_SNORM, g.stream));
+  if (update_p == PU_CG && g.need_fin) PROF_LAUNCH(FFTG_KERNEL_FINALIZE, launch_finalize(g.d, nr, FIN_PAP, g.stream));
+  if (!g.cfg.slab) {
+    const size_t ly = mixed ? g.lds_y32 : g.lds_y;
     PROF_LAUNCH(FFTG_KERNEL_Y_FWD, launch_ypass(mixed, -1, g.d, nr, g.total[P_Y], g.cfg, ly, check_done, g.stream));
   }
-  if (g.cfg.slab && want_norm) PROF_LAUNCH(FFTG_KERNEL_FINALIZE, launch_finalize(g.d, nr, FIN_SNORM, g.stream));
   PROF_LAUNCH(FFTG_KERNEL_X_PROJ, launch_xpass(mixed, g.d, nr, g.total[P_X], g.cfg, lx, scale, check_done, g.stream));
   if (g.cfg.slab) {
     const size_t ls = mixed ? g.lds_s32 : g.lds_s;
@@ -878,7 +877,7 @@ static fftg_status enqueue_apply(Group& g, int mixed, int in_mode, int in_role, 
   }
   if (out_mode == OUT_RESIDUAL || (out_mode == OUT_CG && g.need_fin))
     PROF_LAUNCH(FFTG_KERNEL_FINALIZE,
-                launch_finalize(g.d, nr, out_mode == OUT_CG ? FIN_PAP : FIN_RESID, g.stream));
+                launch_finalize(g.d, nr, out_mode == OUT_CG ? FIN_RR : FIN_RESID, g.stream));
   return FFTG_OK;
 }
 
@@ -894,10 +893,11 @@ static fftg_status enqueue_cg_iters(Group& g, int iters) {
       p_out = g.cg_par ? R_P : R_P2;
       g.cg_par ^= 1;
     }
-    fftg_status st = enqueue_apply(g, g.mixed, IN_ROLE, R_P, TAN_CURRENT, 0, OUT_CG, R_AP, 1.0, 1, 1, p_in, p_out);
+    // one iteration of Algorithm 1 (CG part) is one product: the forward
+    // pass forms p and p.Ap, the inverse pass updates x and r and sums r.r
+    fftg_status st =
+        enqueue_apply(g, g.mixed, IN_ROLE, R_P, TAN_CURRENT, 0, OUT_CG, R_X, 1.0, 1, PU_CG, p_in, p_out);
     if (st != FFTG_OK) return st;
-    PROF_LAUNCH(FFTG_KERNEL_CG_XR, launch_cg_xr(g.mixed, g.d, nr, g.total[P_VEC], g.cfg, p_out, g.stream));
-    if (g.need_fin) PROF_LAUNCH(FFTG_KERNEL_FINALIZE, launch_finalize(g.d, nr, FIN_RR, g.stream));
   }
   return FFTG_OK;
 }
@@ -910,12 +910,12 @@ static fftg_status read_states(Group& g) {
 }
 
 // Iterations still needed by the slowest active member after a snapshot of
-// the CG states (0 when every active member is done): the forced count in
+// the CG states (0 when every active member is done or broke down): the forced count in
 // lockstep mode, else extrapolated from the residual decay so far.
 static double cg_remaining(const Group& g, const CgState* cs, int chunk_max) {
   double need = 0.0;
   for (size_t i = 0; i < g.h.size(); ++i) {
-    if (g.h[i].skip || cs[i].done) continue;
+    if (g.h[i].skip || cs[i].done || cs[i].status == CG_BREAKDOWN) continue;
     const CgState& c = cs[i];
     double n;
     if (c.force >= 0) {
@@ -1113,7 +1113,7 @@ static fftg_status group_increment(Group& g, const double* dE_tensor, const int*
         ret = FFTG_E_NOT_CONVERGED;
     }
   }
-  if (ret == FFTG_E_BREAKDOWN) g_err = "CG breakdown (p.Ap <= 0)";
+  if (ret == FFTG_E_BREAKDOWN) g_err = "CG breakdown (p.Ap <= 0 or not finite)";
   if (ret == FFTG_E_NOT_CONVERGED) g_err = "Newton iteration cap reached";
   return ret;
 }
@@ -1201,9 +1201,10 @@ static fftg_status group_autotune(Group& g) {
   fftg_status st;
   double t_zpair = 1e30, t_y = 1e30;
   // z passes: rows per tile and threads (zfwd + zinv timed together, in the
-  // form they take inside CG: the p update with its folded scalar step and
-  // the CG output.  Before a solve this only scribbles on p, Ap and the CG
-  // state, which the residual pass and the CG set-up initialise.)
+  // form they take inside CG: the p update, the vector update and their
+  // folded sums, in the timing variant that uses no CG state.  Before a
+  // solve this only scribbles on p, x and r, which the residual pass
+  // initialises.)
   {
     double tbest = 1e30;
     LaunchCfg cb = best;
@@ -1217,10 +1218,10 @@ static fftg_status group_autotune(Group& g) {
         if ((st = group_upload(g)) != FFTG_OK) return st;
         const size_t lz = mixed ? g.lds_zf32 : g.lds_zf;
         const double ms = time_ms(g.stream, reps, [&]() {
-          hipError_t e = launch_zfwd(mixed, g.d, nr, g.total[P_ZF], g.cfg, lz, IN_ROLE, R_P, TAN_ELASTIC, 0, 0, 1,
-                                     g.stream);
+          hipError_t e = launch_zfwd(mixed, g.d, nr, g.total[P_ZF], g.cfg, lz, IN_ROLE, R_P, TAN_ELASTIC, 0, 0,
+                                     PU_TIMING, g.stream);
           if (e != hipSuccess) return e;
-          return launch_zinv(mixed, g.d, nr, g.total[P_ZI], g.cfg, lz, OUT_CG, R_AP, 0, R_P, g.stream);
+          return launch_zinv(mixed, g.d, nr, g.total[P_ZI], g.cfg, lz, OUT_CG_TIMING, R_X, 0, R_P, g.stream);
         });
         if (ms < 0.97 * tbest) {  // a later candidate must win clearly (stable choices)
           tbest = ms;
@@ -1295,10 +1296,10 @@ static fftg_status group_autotune(Group& g) {
       if ((st = group_upload(g)) != FFTG_OK) return st;
       const size_t ls = mixed ? g.lds_s32 : g.lds_s;
       const double ms = time_ms(g.stream, reps, [&]() {
-        hipError_t e = launch_slab_fwd(mixed, g.d, nr, g.total[P_ZF], g.cfg, ls, IN_ROLE, R_P, TAN_ELASTIC, 0, 0, 0,
-                                       R_P, R_P, g.stream);
+        hipError_t e = launch_slab_fwd(mixed, g.d, nr, g.total[P_ZF], g.cfg, ls, IN_ROLE, R_P, TAN_ELASTIC, 0, 0,
+                                       PU_TIMING, R_P, R_P2, g.stream);
         if (e != hipSuccess) return e;
-        return launch_slab_inv(mixed, g.d, nr, g.total[P_ZI], g.cfg, ls, OUT_PLAIN, R_AP, 0, R_P, g.stream);
+        return launch_slab_inv(mixed, g.d, nr, g.total[P_ZI], g.cfg, ls, OUT_CG_TIMING, R_X, 0, R_P2, g.stream);
       });
       if (ms < 0.97 * tbest) {  // a later candidate must win clearly (stable choices)
         tbest = ms;

@@ -42,7 +42,7 @@ EXPORTS = [
     "fftg_profiler_start", "fftg_profiler_stop", "fftg_last_error",
 ]
 FFTG_KERNEL_ZFWD, FFTG_KERNEL_Y_FWD, FFTG_KERNEL_X_PROJ, FFTG_KERNEL_Y_INV, FFTG_KERNEL_ZINV = range(5)
-FFTG_KERNEL_CG_XR, FFTG_KERNEL_FINALIZE, FFTG_KERNEL_CONSTITUTIVE, FFTG_KERNEL_NEWTON = range(5, 9)
+FFTG_KERNEL_FINALIZE, FFTG_KERNEL_CONSTITUTIVE, FFTG_KERNEL_NEWTON = range(5, 8)
 
 
 class fftg_material(C.Structure):

@@ -134,6 +134,28 @@ def test_dense_matrix_from_dft_definition_matches_fft_path(shape):
     assert np.max(np.abs(Finv @ F - np.eye(n))) < 1e-12
 
 
+@pytest.mark.parametrize("shape", [(5, 5, 5), (3, 5, 7)])
+def test_curvature_along_compatible_direction_needs_no_projection(shape):
+    """p.G(C:p) = (G p).(C:p) = p.(C:p) for compatible p, G being a symmetric
+    projection: the CG denominator p.Ap can be taken before the transforms.
+    The consistent tangent C is a plastic one of the oracle's return map; a
+    direction with an equilibrated part must break the identity."""
+    from oracle import j2
+    phase = synth.bernoulli(shape, 0.4, 3)
+    K, G, sy0, H, _ = j2.material_fields(phase, [synth.SOFT, synth.HARD])
+    E = np.diag([0.004, -0.002, -0.002])  # about 60 % of the voxels yield
+    eps = E[:, :, None, None, None] + 0.0003 * compatible_field(shape, 10)
+    _, C, _, _, plastic = j2.return_map(eps, np.zeros_like(eps), np.zeros(shape), K, G, sy0, H)
+    assert plastic.any() and not plastic.all()
+    p = compatible_field(shape, 11)
+    Cp = j2.ddot42(C, p)
+    lhs, rhs = np.sum(p * P.apply_G(Cp)), np.sum(p * Cp)
+    assert rhs > 0 and abs(lhs - rhs) <= 1e-12 * rhs
+    q = p + equilibrated_field(shape, 12)
+    Cq = j2.ddot42(C, q)
+    assert abs(np.sum(q * P.apply_G(Cq)) - np.sum(q * Cq)) > 1e-3 * np.sum(q * Cq)
+
+
 def test_even_grid_rejected():
     with pytest.raises(ValueError):
         P.int_freq(4)

@@ -21,6 +21,57 @@ template <int R>
 struct RadixConst;
 #include "radix_consts.h"
 
+// Global-memory view of a device pointer.  Pointers read from a launch
+// descriptor are generic, and loads through them compile to flat loads: the
+// compiler must then assume that they may alias LDS (so each is waited for
+// before the next LDS store) and they count against the LDS wait counter
+// too.  Through this view they are global loads, which can be issued in
+// batches ahead of the stores that consume them.
+#define FFTG_GLOBAL __attribute__((address_space(1)))
+template <class V>
+__device__ __forceinline__ FFTG_GLOBAL V* gmem(V* p) {
+  return (FFTG_GLOBAL V*)p;
+}
+// Element loads and stores through such views (complex values component by
+// component: the compiler merges them into one wide access).
+template <class V>
+__device__ __forceinline__ V gload(const FFTG_GLOBAL V* p) {
+  return *p;
+}
+template <class T>
+__device__ __forceinline__ cx<T> gload(const FFTG_GLOBAL cx<T>* p) {
+  const FFTG_GLOBAL T* q = (const FFTG_GLOBAL T*)p;
+  return cx<T>{q[0], q[1]};
+}
+template <class T>
+__device__ __forceinline__ void gstore(FFTG_GLOBAL cx<T>* p, cx<T> v) {
+  FFTG_GLOBAL T* q = (FFTG_GLOBAL T*)p;
+  q[0] = v.re;
+  q[1] = v.im;
+}
+
+// lds[dst(t)] = g[src(t)] for t < n (n >= 1) over the workgroup; each
+// thread issues the loads of up to U elements before it stores any of them.
+// Indices past the end repeat element n - 1 (the same value to the same
+// place), so that no load or store sits behind a branch: the compiler would
+// otherwise sink each load next to its guarded store and wait for them one
+// at a time.
+template <int U, class V, class Src, class Dst>
+__device__ __forceinline__ void lds_gather(V* lds, const FFTG_GLOBAL V* g, int n, Src src, Dst dst) {
+  const int bd = blockDim.x;
+  for (int t0 = threadIdx.x; t0 < n; t0 += U * bd) {
+    V v[U];
+    int ti[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      ti[u] = min(t0 + u * bd, n - 1);
+      v[u] = gload(g + src(ti[u]));
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) lds[dst(ti[u])] = v[u];
+  }
+}
+
 template <class T>
 __device__ __forceinline__ cx<T> cadd(cx<T> a, cx<T> b) { return {a.re + b.re, a.im + b.im}; }
 template <class T>
@@ -191,6 +242,7 @@ struct AxisLds {
   int* pout;
   cx<T>* bf;     // Rader DFT_M(b)/M, forward and inverse
   cx<T>* bi;
+  const cx<T>* g_tw;  // root table in global memory
 };
 
 // LDS bytes of the tables of an axis of length <= N.
@@ -199,10 +251,9 @@ __host__ __device__ constexpr size_t axis_lds_bytes(int N) {
   return (((size_t)N * (3 * sizeof(cx<T>) + 2 * sizeof(int))) + 15) / 16 * 16;
 }
 
-// Carves the tables out of base and loads them (whole workgroup; the
-// caller's next __syncthreads publishes them).
+// Carves the tables out of base and reads the axis fields (no table loads).
 template <class T>
-__device__ void load_axis_lds(const AxisDev& P, char* base, AxisLds<T>& A) {
+__device__ __forceinline__ void axis_lds_setup(const AxisDev& P, char* base, AxisLds<T>& A) {
   A.dev = &P;
   A.M = P.M;
   A.nst = P.nst;
@@ -213,18 +264,63 @@ __device__ void load_axis_lds(const AxisDev& P, char* base, AxisLds<T>& A) {
   A.bi = A.bf + N;
   A.pin = reinterpret_cast<int*>(A.bi + N);
   A.pout = A.pin + N;
-  const cx<T>* tw = axis_tw<T>(P);
-  for (int t = threadIdx.x; t < P.M; t += blockDim.x) A.tw[t] = tw[t];
-  if (P.rader == AX_RADER) {
-    const cx<T>* bf = rader_bhat<T>(P, -1);
-    const cx<T>* bi = rader_bhat<T>(P, 1);
-    for (int t = threadIdx.x; t < P.M; t += blockDim.x) {
-      A.bf[t] = bf[t];
-      A.bi[t] = bi[t];
-      A.pin[t] = P.perm_in[t];
-      A.pout[t] = P.perm_out[t];
+  A.g_tw = axis_tw<T>(P);
+}
+
+// The table copy in two halves: fetch loads this thread's first roots into
+// registers, store writes them and copies the rest (and the Rader tables).
+// A kernel issues its own data loads in between, so that both wait for one
+// memory round trip instead of two; the caller's next __syncthreads
+// publishes the tables.
+template <class T>
+struct AxisFetch {
+  cx<T> v[2];
+  int t[2];
+};
+template <class T>
+__device__ __forceinline__ AxisFetch<T> axis_lds_fetch(const AxisLds<T>& A) {
+  AxisFetch<T> f;
+  const FFTG_GLOBAL cx<T>* g = gmem(A.g_tw);
+  const int bd = blockDim.x;
+#pragma unroll
+  for (int u = 0; u < 2; ++u) {
+    f.t[u] = min((int)threadIdx.x + u * bd, A.M - 1);
+    f.v[u] = gload(g + f.t[u]);
+  }
+  return f;
+}
+template <class T>
+__device__ __forceinline__ void axis_lds_store(const AxisLds<T>& A, const AxisFetch<T>& f) {
+  const int bd = blockDim.x;
+#pragma unroll
+  for (int u = 0; u < 2; ++u) A.tw[f.t[u]] = f.v[u];
+  const int M = A.M;
+  if (M > 2 * bd) {
+    const FFTG_GLOBAL cx<T>* g = gmem(A.g_tw);
+    for (int t = threadIdx.x + 2 * bd; t < M; t += bd) A.tw[t] = gload(g + t);
+  }
+  if (A.rader == AX_RADER) {
+    const AxisDev& P = *A.dev;
+    const FFTG_GLOBAL cx<T>* bf = gmem(rader_bhat<T>(P, -1));
+    const FFTG_GLOBAL cx<T>* bi = gmem(rader_bhat<T>(P, 1));
+    const FFTG_GLOBAL int* qi = gmem(P.perm_in);
+    const FFTG_GLOBAL int* qo = gmem(P.perm_out);
+    for (int t = threadIdx.x; t < M; t += bd) {
+      const cx<T> b = gload(bf + t), c = gload(bi + t);
+      const int d = qi[t], e = qo[t];
+      A.bf[t] = b;
+      A.bi[t] = c;
+      A.pin[t] = d;
+      A.pout[t] = e;
     }
   }
+}
+
+// Setup and whole copy at once.
+template <class T>
+__device__ __forceinline__ void load_axis_lds(const AxisDev& P, char* base, AxisLds<T>& A) {
+  axis_lds_setup<T>(P, base, A);
+  axis_lds_store<T>(A, axis_lds_fetch<T>(A));
 }
 
 // Runs the Stockham chain of P on a (result ends in a; buffers are swapped).

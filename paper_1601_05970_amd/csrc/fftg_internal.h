@@ -76,6 +76,10 @@ enum Role {
 
 enum Pass { P_ZF = 0, P_Y, P_X, P_ZI, P_VEC, P_NPASS };
 
+// Flag in the member-count argument of the tiled kernels: blocks are mapped
+// to tiles XCD-contiguously.
+constexpr int kLaunchRemap = 1 << 30;
+
 struct RveDev {
   int n0, n1, n2, H;
   long long nvox, nspec;
@@ -95,7 +99,6 @@ struct RveDev {
   int tiles[P_NPASS];        // tiles of each pass for this RVE
   int skip;                  // 1: RVE masked out of batched launches
   int fold;                  // 1: CG scalar steps folded into the consumer kernels
-  int xcd_remap;             // (first descriptor of a launch) spread tiles XCD-contiguously
 };
 
 // Apply modes (kernel flags)
@@ -123,6 +126,7 @@ struct LaunchCfg {
   int slab;            // 1: z and y transforms fused per y-z plane (k_slab_fwd / k_slab_inv)
   int threads_s;       // slab passes
   int big_radix;       // 1 when some axis needs the radix-11/13/17 codelets
+  int xcd_remap;       // 1: blocks mapped to tiles XCD-contiguously
   int n0max, n1max, n2max;  // largest extents of the launch (LDS table sizing)
 };
 

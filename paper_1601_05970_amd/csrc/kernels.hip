@@ -41,11 +41,17 @@ __device__ __forceinline__ int xcd_tile(int b, int n) {
   return x * q + min(x, r) + i;
 }
 
-// The descriptor array of a launch is followed by a prefix table of tile
-// offsets, starts[pass][r] for r = 0..nrve (members skipped from a launch
-// own no tiles); a block finds its RVE by binary search over that table.
-__device__ __forceinline__ int find_rve(const RveDev* __restrict__ rv, int nrve, int pass, int& tile) {
-  const int b = rv[0].xcd_remap ? xcd_tile(blockIdx.x, gridDim.x) : (int)blockIdx.x;
+// A kernel's nrve argument is the member count, with kLaunchRemap set when
+// tiles are spread XCD-contiguously (an argument, so that it arrives with
+// the first load of the kernel).  The descriptor array of a launch is
+// followed by a prefix table of tile offsets, starts[pass][r] for
+// r = 0..nrve; a block finds its RVE by binary search over that table.
+// Members skipped from a launch own no tiles, so no block reaches them.
+__device__ __forceinline__ bool launch_single(int nrve_arg) { return (nrve_arg & ~kLaunchRemap) == 1; }
+__device__ __forceinline__ int find_rve(const RveDev* __restrict__ rv, int nrve_arg, int pass, int& tile) {
+  const int nrve = nrve_arg & ~kLaunchRemap;
+  const int br = xcd_tile(blockIdx.x, gridDim.x);  // formed unconditionally: no branch before the loads
+  const int b = (nrve_arg & kLaunchRemap) ? br : (int)blockIdx.x;
   if (nrve == 1) {  // the grid is exactly the one RVE's tiles
     tile = b;
     return 0;
@@ -91,22 +97,29 @@ __device__ __forceinline__ void put_partials(const double* vals, int nv, double*
     for (int i = 0; i < nv; ++i) partial[i * ntiles + tile] = vals[i];
 }
 
-// Sum of p[0..n) over the workgroup in a fixed order (four strided
-// accumulators per thread, then the block tree); valid in thread 0.  Split in
-// two so that a kernel can issue the loads of its own share early and reduce
-// later: thread_partials is the per-thread part, block_sum the rest.
-__device__ __forceinline__ double thread_partials(const double* __restrict__ p, int n) {
+// Sum of p[0..n) over the workgroup in a fixed order (two accumulators per
+// thread, then the block tree); valid in thread 0.  Split in two so that a
+// kernel can issue the loads of its own share early and reduce later:
+// thread_partials is the per-thread part, block_sum the rest.  Each round
+// issues sixteen loads before any add (indices past the end load element
+// n - 1 and add zero), so up to 16 x blockDim partials cost one memory round
+// trip.
+__device__ __forceinline__ double thread_partials(const double* __restrict__ pp, int n) {
+  const FFTG_GLOBAL double* p = gmem(pp);
   const int st = blockDim.x;
-  double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-  int t = threadIdx.x;
-  for (; t + 3 * st < n; t += 4 * st) {
-    a0 += p[t];
-    a1 += p[t + st];
-    a2 += p[t + 2 * st];
-    a3 += p[t + 3 * st];
+  constexpr int U = 16;
+  double a0 = 0.0, a1 = 0.0;
+  for (int t = threadIdx.x; t < n; t += U * st) {
+    double v[U];
+#pragma unroll
+    for (int k = 0; k < U; ++k) v[k] = p[min(t + k * st, n - 1)];
+#pragma unroll
+    for (int k = 0; k < U; k += 2) {
+      a0 += (t + k * st < n) ? v[k] : 0.0;
+      a1 += (t + (k + 1) * st < n) ? v[k + 1] : 0.0;
+    }
   }
-  for (; t < n; t += st) a0 += p[t];
-  return (a0 + a1) + (a2 + a3);
+  return a0 + a1;
 }
 __device__ double sum_partials(const double* __restrict__ p, int n, double* sh) {
   return block_sum(thread_partials(p, n), sh);
@@ -174,8 +187,11 @@ struct TileLds {
   cx<T>* scratch;
   cx<T>* dc;
   double* red;
-  __device__ TileLds(char* base, int nl, int ld, const AxisDev& P, int ldmax) {
-    load_axis_lds<T>(P, base, ax);
+  // With defer, the tables are only carved out: the kernel copies them with
+  // axis_lds_fetch / axis_lds_store around its own loads.
+  __device__ TileLds(char* base, int nl, int ld, const AxisDev& P, int ldmax, bool defer = false) {
+    if (defer) axis_lds_setup<T>(P, base, ax);
+    else load_axis_lds<T>(P, base, ax);
     line = reinterpret_cast<cx<T>*>(base + axis_lds_bytes<T>(ldmax));
     scratch = line + (size_t)nl * ld;
     dc = scratch + (size_t)nl * ld;
@@ -197,47 +213,71 @@ struct TileLds {
 // false when the solve has stopped (the tile exits).  red needs 10 doubles;
 // called by the whole workgroup.  PU_TIMING does the same loads and sums
 // with beta = 0 and no state.
-__device__ bool cg_begin_iter(const RveDev& rv, int tile, int dn, int mode, double* red, double& beta) {
+// CG scalars read at the start of an iteration, loaded by every thread with
+// the kernel's other loads and used by thread 0 only (no thread waits for
+// them on its own).  The address passes through a vector register (an empty
+// asm): values loaded from a uniform address are otherwise moved to scalar
+// registers, and so waited for, right where they are loaded.
+struct CgPeekB {
+  int done, iters, status, force, max_iter;
+  double rr_prev, target2, beta;
+};
+__device__ __forceinline__ const FFTG_GLOBAL CgState* cg_vaddr(CgState* cg) {
+  __asm__ volatile("" : "+v"(cg));
+  return gmem(cg);
+}
+__device__ __forceinline__ CgPeekB cg_peek_b(CgState* cg) {
+  const FFTG_GLOBAL CgState* g = cg_vaddr(cg);
+  return CgPeekB{g->done, g->iters, g->status, g->force, g->max_iter, g->rr_prev, g->target2, g->beta};
+}
+
+// (dn: the stop flag of this launch's test, as thread 0 holds it; pk: the
+// scalars above; pa: this thread's share of the r.r partials, loaded by the
+// caller with its data when folded.)
+__device__ bool cg_begin_iter(const RveDev& rv, int tile, int dn, const CgPeekB& pk, double pa, int mode,
+                              double* red, double& beta) {
   CgState* cg = rv.cg;
   const bool timing = mode == PU_TIMING;
-  beta = 0.0;
-  if (!rv.fold) {
-    if (done_publish(dn)) return false;
-    if (!timing) beta = cg->beta;
-    return true;
-  }
-  if (!timing && cg->iters == 0) return !done_publish(dn);  // the residual pass has set p = r
-  const double rr = sum_partials(rv.partial_rr, rv.tiles[P_ZI], red);
-  if (timing) {
-    if (threadIdx.x == 0) red[9] = rr;
-    __syncthreads();
-    return true;
-  }
-  if (threadIdx.x == 0 && dn) {
-    red[8] = 1.0;  // stopped before this launch: no state change
-  } else if (threadIdx.x == 0) {
-    const int it = cg->iters;
-    int st = CG_RUNNING;
-    if (cg->status == CG_BREAKDOWN) {
-      st = CG_BREAKDOWN;
-    } else if (cg->force >= 0) {
-      if (it >= cg->force) st = CG_FORCED;
-    } else if (rr <= cg->target2) {
-      st = CG_CONVERGED;
-    } else if (it >= cg->max_iter) {
-      st = CG_MAXITER;
-    }
-    const double b = rr / cg->rr_prev;
-    red[8] = st != CG_RUNNING ? 1.0 : 0.0;
-    red[9] = b;
-    if (tile == 0) {
-      cg->rr = rr;
-      cg->rr_new = rr;
-      cg->status = st;
-      if (st != CG_RUNNING) {
-        __hip_atomic_store(&cg->done, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      } else {
-        cg->beta = b;
+  // Every decision that depends on the CG scalars is thread 0's, shared
+  // through LDS: a branch of all threads on them would make each thread wait
+  // for their loads as soon as they are issued.
+  const double rr = rv.fold ? block_sum(pa, red) : 0.0;
+  if (threadIdx.x == 0) {
+    if (dn) {
+      red[8] = 1.0;  // stopped before this launch: no state change
+    } else if (timing) {
+      red[8] = 0.0;
+      red[9] = 0.0 * rr;
+    } else if (pk.iters == 0) {
+      red[8] = 0.0;  // iteration 0: the residual pass has set p = r
+      red[9] = 0.0;
+    } else if (!rv.fold) {
+      red[8] = 0.0;  // k_finalize took the step
+      red[9] = pk.beta;
+    } else {
+      const int it = pk.iters;
+      int st = CG_RUNNING;
+      if (pk.status == CG_BREAKDOWN) {
+        st = CG_BREAKDOWN;
+      } else if (pk.force >= 0) {
+        if (it >= pk.force) st = CG_FORCED;
+      } else if (rr <= pk.target2) {
+        st = CG_CONVERGED;
+      } else if (it >= pk.max_iter) {
+        st = CG_MAXITER;
+      }
+      const double b = rr / pk.rr_prev;
+      red[8] = st != CG_RUNNING ? 1.0 : 0.0;
+      red[9] = b;
+      if (tile == 0) {
+        cg->rr = rr;
+        cg->rr_new = rr;
+        cg->status = st;
+        if (st != CG_RUNNING) {
+          __hip_atomic_store(&cg->done, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+          cg->beta = b;
+        }
       }
     }
   }
@@ -247,49 +287,80 @@ __device__ bool cg_begin_iter(const RveDev& rv, int tile, int dn, int mode, doub
   return true;
 }
 
-// tau = C(x):p(x) at voxel v for the input modes of the forward pass.  With
-// update_p, p = r + beta p_old is formed here, its components
-// [own_lo, own_hi) are stored to p_new (p_new may equal p_old when the
-// caller owns all six components of the voxel), and the return value is
-// their share of p.tau (else 0).
+// Inputs of the forward pass at one voxel: the input (or r and the old p),
+// the phase and the consistent tangent.  voxel_load only loads, so that a
+// kernel can issue them before it waits on anything else.
 template <class T>
-__device__ __forceinline__ double voxel_tau(const RveDev& rv, long long v, int in_mode, const double* __restrict__ in,
-                                          int update_p, double beta, const double* __restrict__ rres,
-                                          const double* p_old, double* p_new, int own_lo, int own_hi,
-                                          int tan_mode, const MatDev* __restrict__ mats, T tau[6]) {
-  const long long nvox = rv.nvox;
+struct VoxIn {
+  double a[6], b[6];
+  T g2, m[6];
+  int ph;
+};
+template <class T>
+__device__ __forceinline__ void voxel_load(long long v, long long nvox, int in_mode, const double* in, int update_p,
+                                           const double* rres, const double* p_old, int tan_mode, const void* tang,
+                                           const uint8_t* phase, VoxIn<T>& vi) {
+  if (in_mode != IN_CONST_DE) {
+    const FFTG_GLOBAL double* a = gmem(update_p ? rres : in);
+#pragma unroll
+    for (int c = 0; c < 6; ++c) vi.a[c] = a[c * nvox + v];
+    if (update_p) {
+      const FFTG_GLOBAL double* b = gmem(p_old);
+#pragma unroll
+      for (int c = 0; c < 6; ++c) vi.b[c] = b[c * nvox + v];
+    }
+  }
+  if (tan_mode != TAN_IDENTITY) vi.ph = gmem(phase)[v];
+  if (tan_mode == TAN_CURRENT) {
+    const FFTG_GLOBAL T* tg = gmem((const T*)tang);
+    vi.g2 = tg[v];
+#pragma unroll
+    for (int c = 0; c < 6; ++c) vi.m[c] = tg[(c + 1) * nvox + v];
+  }
+}
+
+// tau = C(x):p(x) at voxel v from its loaded inputs.  With update_p,
+// p = r + beta p_old is formed here, its components [own_lo, own_hi) are
+// stored to p_new (p_new may equal p_old when the caller owns all six
+// components of the voxel), and the return value is their share of p.tau
+// (else 0).
+template <class T>
+__device__ __forceinline__ double voxel_compute(const VoxIn<T>& vi, long long v, long long nvox, int in_mode,
+                                                const double* dE, int update_p, double beta, double* p_new,
+                                                int own_lo, int own_hi, int tan_mode,
+                                                const MatDev* __restrict__ mats, T tau[6]) {
   T p[6];
   double pd[6];
   if (in_mode == IN_CONST_DE) {
 #pragma unroll
-    for (int c = 0; c < 6; ++c) p[c] = T(rv.dE[c]);
+    for (int c = 0; c < 6; ++c) p[c] = T(dE[c]);
   } else if (update_p) {
+    FFTG_GLOBAL double* pw = gmem(p_new);
 #pragma unroll
     for (int c = 0; c < 6; ++c) {
-      const double pn = rres[c * nvox + v] + beta * p_old[c * nvox + v];
-      if (c >= own_lo && c < own_hi) p_new[c * nvox + v] = pn;
+      const double pn = vi.a[c] + beta * vi.b[c];
+      if (c >= own_lo && c < own_hi) pw[c * nvox + v] = pn;
       pd[c] = pn;
       p[c] = T(pn);
     }
   } else {
 #pragma unroll
-    for (int c = 0; c < 6; ++c) p[c] = T(in[c * nvox + v]);
+    for (int c = 0; c < 6; ++c) p[c] = T(vi.a[c]);
   }
   if (tan_mode == TAN_IDENTITY) {
 #pragma unroll
     for (int c = 0; c < 6; ++c) tau[c] = p[c];
   } else {
-    const MatDev& mt = mats[rv.phase[v]];
-    const T* tg = (const T*)rv.tang;
+    const MatDev& mt = mats[vi.ph];
     T g2, m[6];
     if (tan_mode == TAN_ELASTIC) {
       g2 = T(2.0 * mt.G);
 #pragma unroll
       for (int c = 0; c < 6; ++c) m[c] = T(0);
     } else {
-      g2 = tg[v];
+      g2 = vi.g2;
 #pragma unroll
-      for (int c = 0; c < 6; ++c) m[c] = tg[(c + 1) * nvox + v];
+      for (int c = 0; c < 6; ++c) m[c] = vi.m[c];
     }
     tangent_apply<T>(p, T(mt.K), g2, m, tau);
   }
@@ -300,6 +371,30 @@ __device__ __forceinline__ double voxel_tau(const RveDev& rv, long long v, int i
       if (c >= own_lo && c < own_hi) d += pd[c] * double(tau[c]);
   }
   return d;
+}
+
+// Both at once (kernels with nothing to overlap).
+template <class T>
+__device__ __forceinline__ double voxel_tau(const RveDev& rv, long long v, int in_mode, const double* __restrict__ in,
+                                          int update_p, double beta, const double* __restrict__ rres,
+                                          const double* p_old, double* p_new, int own_lo, int own_hi,
+                                          int tan_mode, const MatDev* __restrict__ mats, T tau[6]) {
+  VoxIn<T> vi;
+  voxel_load<T>(v, rv.nvox, in_mode, in, update_p, rres, p_old, tan_mode, rv.tang, rv.phase, vi);
+  return voxel_compute<T>(vi, v, rv.nvox, in_mode, rv.dE, update_p, beta, p_new, own_lo, own_hi, tan_mode, mats,
+                          tau);
+}
+
+// Material table of a launch member into LDS, in two halves like the axis
+// tables (threads past n fetch and store entry n - 1 again, so that no load
+// sits behind a branch).
+__device__ __forceinline__ MatDev mats_fetch(const MatDev* mats, int n) {
+  const int i = min((int)threadIdx.x, n - 1);
+  const FFTG_GLOBAL double* m = gmem(&mats[i].K);
+  return MatDev{m[0], m[1], m[2], m[3]};
+}
+__device__ __forceinline__ void mats_store(const MatDev& m, int n, MatDev* s_mats) {
+  s_mats[min((int)threadIdx.x, n - 1)] = m;
 }
 
 // ------------------------------------------------------------- z forward
@@ -313,49 +408,86 @@ __global__ void __launch_bounds__(256) k_zfwd(const RveDev* __restrict__ rvs, in
   const int ri = find_rve(rvs, nrve, P_ZF, tile);
   if (ri < 0) return;
   const RveDev& rv = rvs[ri];
-  if (rv.skip) return;
-  const int dn = done_peek(check_done, rv.cg);
-  const int n2 = rv.n2, H = rv.H;
+  // descriptor fields, all loaded in one batch (the empty asm keeps the
+  // compiler from deferring any of them past the first use of another)
+  int n0 = rv.n0, n1 = rv.n1, n2 = rv.n2, H = rv.H, nph = rv.n_phases, fold = rv.fold, nti = rv.tiles[P_ZI];
+  long long nvox = rv.nvox;
   const long long nspec = rv.nspec;
-  const int nrows_tot = rv.n0 * rv.n1;
+  CgState* cg = rv.cg;
+  const double* in = (const double*)rv.buf[in_role];
+  const double* rres = (const double*)rv.buf[R_R];
+  double* pw = (double*)rv.buf[R_P];
+  const void* tang = rv.tang;
+  const uint8_t* phase = rv.phase;
+  const double* prr = rv.partial_rr;
+  const MatDev* mats = rv.mats;
+  TileLds<T> L(smem, 3 * rows_per_tile, n2, rv.ax[2], ldmax, true);
+  __asm__ volatile(""
+                   : "+s"(n0), "+s"(n1), "+s"(n2), "+s"(H), "+s"(nph), "+s"(fold), "+s"(nti), "+s"(nvox), "+s"(cg),
+                     "+s"(in), "+s"(rres), "+s"(pw), "+s"(tang), "+s"(phase), "+s"(prr), "+s"(L.ax.M),
+                     "+s"(L.ax.g_tw)
+                   :
+                   : "memory");
+  const int nrows_tot = n0 * n1;
   const int row0 = tile * rows_per_tile;
   const int nrows = min(rows_per_tile, nrows_tot - row0);
   const int ld = n2;
-  TileLds<T> L(smem, 3 * rows_per_tile, ld, rv.ax[2], ldmax);
+  const int nvt = nrows * n2;
+  const int bd = blockDim.x;
+  const FastDiv fn2(n2), fH(H), f3(3);
   __shared__ MatDev s_mats[kMaxPhases];  // per-voxel material lookups from LDS
-  if (threadIdx.x < rv.n_phases) s_mats[threadIdx.x] = rv.mats[threadIdx.x];
-
-  const double* in = (const double*)rv.buf[in_role];
+  // Loads in program order before anything that waits: tables, this
+  // thread's first voxel, the material table, the CG scalars, then the r.r
+  // partials (a loop that waits as it sums); the LDS stores come after.
   // CG search direction update fused here: p <- r + beta p (in place: this
-  // tile owns every component of its voxels).  Either branch ends in a
-  // barrier that also publishes the tables and materials.
+  // tile owns every component of its voxels).
+  const AxisFetch<T> tf = axis_lds_fetch<T>(L.ax);
+  auto vox_of = [&](int t) {
+    const int r = fn2.div(t);
+    return (long long)(row0 + r) * n2 + (t - r * n2);
+  };
+  VoxIn<T> vi0;
+  voxel_load<T>(vox_of(min((int)threadIdx.x, nvt - 1)), nvox, in_mode, in, update_p, rres, pw, tan_mode, tang, phase,
+                vi0);
+  const MatDev mt = mats_fetch(mats, nph);
+  const CgPeekB pk = cg_peek_b(cg);
+  const double pa = (update_p && fold) ? thread_partials(prr, nti) : 0.0;
+  axis_lds_store<T>(L.ax, tf);
+  mats_store(mt, nph, s_mats);
+  // Either branch ends in a barrier that also publishes the tables and
+  // materials.  The stop flag is thread 0's copy, shared through LDS: in
+  // the CG form tile 0 may set it while other tiles of the launch start.
+  const int dn = check_done ? pk.done : 0;
   double beta = 0.0;
   if (update_p) {
-    if (!cg_begin_iter(rv, tile, dn, update_p, L.red, beta)) return;
+    if (!cg_begin_iter(rv, tile, dn, pk, pa, update_p, L.red, beta)) return;
   } else if (done_publish(dn)) {
     return;
   }
-  const double* rres = (const double*)rv.buf[R_R];
-  double* pw = (double*)rv.buf[R_P];
   double nrm = 0.0;  // ||tau||^2 (want_norm) or p.tau (update_p)
-  const FastDiv fn2(n2), fH(H), f3(3);
-  for (int t = threadIdx.x; t < nrows * n2; t += blockDim.x) {
+  auto process = [&](const VoxIn<T>& vi, int t) {
     const int r = fn2.div(t);
     const int z = t - r * n2;
     const long long v = (long long)(row0 + r) * n2 + z;
     T tau[6];
-    nrm += voxel_tau<T>(rv, v, in_mode, in, update_p, beta, rres, pw, pw, 0, 6, tan_mode, s_mats, tau);
+    nrm += voxel_compute<T>(vi, v, nvox, in_mode, rv.dE, update_p, beta, pw, 0, 6, tan_mode, s_mats, tau);
     if (want_norm) {
 #pragma unroll
       for (int c = 0; c < 6; ++c) nrm += double(tau[c]) * double(tau[c]);
     }
 #pragma unroll
     for (int pr = 0; pr < 3; ++pr) L.line[(3 * r + pr) * ld + z] = cx<T>{tau[2 * pr], tau[2 * pr + 1]};
+  };
+  if ((int)threadIdx.x < nvt) process(vi0, threadIdx.x);
+  for (int t = threadIdx.x + bd; t < nvt; t += bd) {
+    VoxIn<T> vi;
+    voxel_load<T>(vox_of(t), nvox, in_mode, in, update_p, rres, pw, tan_mode, tang, phase, vi);
+    process(vi, t);
   }
   __syncthreads();
   cx<T>* res = line_fft<-1, T, BIG>(L.line, L.scratch, ld, 3 * nrows, L.ax, L.dc);
   // untangle two real transforms: A_k = (Z_k + conj Z_-k)/2, B_k = (Z_k - conj Z_-k)/(2i)
-  cx<T>* spec = (cx<T>*)rv.spec;
+  FFTG_GLOBAL cx<T>* spec = gmem((cx<T>*)rv.spec);
   for (int t = threadIdx.x; t < nrows * 3 * H; t += blockDim.x) {
     const int rp = fH.div(t);
     const int k = t - rp * H;
@@ -365,8 +497,8 @@ __global__ void __launch_bounds__(256) k_zfwd(const RveDev* __restrict__ rvs, in
     const cx<T> A = {T(0.5) * (zk.re + zm.re), T(0.5) * (zk.im - zm.im)};
     const cx<T> B = {T(0.5) * (zk.im + zm.im), T(-0.5) * (zk.re - zm.re)};
     const long long o = (long long)(row0 + r) * H + k;
-    spec[(2 * pr) * nspec + o] = A;
-    spec[(2 * pr + 1) * nspec + o] = B;
+    gstore(spec + (2 * pr) * nspec + o, A);
+    gstore(spec + (2 * pr + 1) * nspec + o, B);
   }
   if (want_norm || update_p) {
     const double s = block_sum(nrm, L.red);
@@ -383,31 +515,48 @@ __global__ void __launch_bounds__(256) k_ypass(const RveDev* __restrict__ rvs, i
   const int ri = find_rve(rvs, nrve, P_Y, tile);
   if (ri < 0) return;
   const RveDev& rv = rvs[ri];
-  if (rv.skip) return;
-  const int dn = check_done ? rv.cg->done : 0;  // no writer during the launch; tested after the table loads
-  const int n0 = rv.n0, n1 = rv.n1, H = rv.H;
+  // descriptor fields, all loaded in one batch (the empty asm keeps the
+  // compiler from deferring any of them past the first use of another)
+  int n0 = rv.n0, n1 = rv.n1, H = rv.H;
+  const long long nspec = rv.nspec;
+  cx<T>* const spec = (cx<T>*)rv.spec;
+  CgState* const cg = rv.cg;
+  TileLds<T> L(smem, lines_per_tile, n1, rv.ax[1], ldmax, true);
+  __asm__ volatile("" : "+s"(n0), "+s"(n1), "+s"(H) : : "memory");
+  const int ld = n1;
   const int nhb = (H + lines_per_tile - 1) / lines_per_tile;
   const int c = tile / (n0 * nhb);
   const int rem = tile - c * n0 * nhb;
   const int i0 = rem / nhb;
   const int h0 = (rem - i0 * nhb) * lines_per_tile;
   const int nh = min(lines_per_tile, H - h0);
-  const int ld = n1;
-  TileLds<T> L(smem, lines_per_tile, ld, rv.ax[1], ldmax);
-  if (dn) return;
-  cx<T>* base = (cx<T>*)rv.spec + c * rv.nspec + (long long)i0 * n1 * H + h0;
+  // Stop flag (no writer during the launch): a launch over several RVEs
+  // tests it before the loads, so that members that have stopped move no
+  // data.  A launch over one RVE does not wait for it: after the solve has
+  // stopped this pass only transforms the spectrum, which no later step
+  // reads before overwriting it, and the test would put one more memory
+  // round trip before the loads of every launch.
+  if (check_done && !launch_single(nrve) && *gmem(&cg->done)) return;
+  const AxisFetch<T> tf = axis_lds_fetch<T>(L.ax);
+  FFTG_GLOBAL cx<T>* base = gmem(spec) + c * nspec + (long long)i0 * n1 * H + h0;
   const FastDiv fnh(nh);
-  for (int t = threadIdx.x; t < n1 * nh; t += blockDim.x) {
-    const int y = fnh.div(t);
-    const int hh = t - y * nh;
-    L.line[hh * ld + y] = base[(long long)y * H + hh];
-  }
+  lds_gather<4>(
+      L.line, base, n1 * nh,
+      [=](int t) {
+        const int y = fnh.div(t);
+        return (long long)y * H + (t - y * nh);
+      },
+      [=](int t) {
+        const int y = fnh.div(t);
+        return (t - y * nh) * ld + y;
+      });
+  axis_lds_store<T>(L.ax, tf);
   __syncthreads();
   cx<T>* res = line_fft<DIR, T, BIG>(L.line, L.scratch, ld, nh, L.ax, L.dc);
   for (int t = threadIdx.x; t < n1 * nh; t += blockDim.x) {
     const int y = fnh.div(t);
     const int hh = t - y * nh;
-    base[(long long)y * H + hh] = res[hh * ld + y];
+    gstore(base + (long long)y * H + hh, res[hh * ld + y]);
   }
 }
 
@@ -420,34 +569,46 @@ __global__ void __launch_bounds__(256) k_xpass(const RveDev* __restrict__ rvs, i
   const int ri = find_rve(rvs, nrve, P_X, tile);
   if (ri < 0) return;
   const RveDev& rv = rvs[ri];
-  if (rv.skip) return;
-  const int dn = check_done ? rv.cg->done : 0;  // no writer during the launch; tested after the table loads
-  const int n0 = rv.n0, n1 = rv.n1, n2 = rv.n2, H = rv.H;
-  const long long nspec = rv.nspec;
+  // descriptor fields, all loaded in one batch (the empty asm keeps the
+  // compiler from deferring any of them past the first use of another)
+  int n0 = rv.n0, n1 = rv.n1, n2 = rv.n2, H = rv.H;
+  const long long nspec = rv.nspec, nvox = rv.nvox;
+  FFTG_GLOBAL cx<T>* const spec = gmem((cx<T>*)rv.spec);
+  CgState* const cg = rv.cg;
+  TileLds<T> L(smem, 6 * lines_per_tile, n0, rv.ax[0], ldmax, true);
+  __asm__ volatile("" : "+s"(n0), "+s"(n1), "+s"(n2), "+s"(H) : : "memory");
   const int nhb = (H + lines_per_tile - 1) / lines_per_tile;
   const int i1 = tile / nhb;
   const int h0 = (tile - i1 * nhb) * lines_per_tile;
   const int nh = min(lines_per_tile, H - h0);
   const int ld = n0;
   const int nl = 6 * nh;
-  TileLds<T> L(smem, 6 * lines_per_tile, ld, rv.ax[0], ldmax);
-  if (dn) return;
-  cx<T>* spec = (cx<T>*)rv.spec;
+  // stop flag: as in the y pass (tested first only over several RVEs)
+  if (check_done && !launch_single(nrve) && *gmem(&cg->done)) return;
+  const AxisFetch<T> tf = axis_lds_fetch<T>(L.ax);
   const long long rs = (long long)n1 * H;
   const long long off = (long long)i1 * H + h0;
   const FastDiv fxn(n0 * nh), fnh(nh);
-  for (int t = threadIdx.x; t < 6 * n0 * nh; t += blockDim.x) {
-    const int cx_ = fxn.div(t);
-    const int r = t - cx_ * n0 * nh;
-    const int x = fnh.div(r);
-    const int hh = r - x * nh;
-    L.line[(cx_ * nh + hh) * ld + x] = spec[cx_ * nspec + x * rs + off + hh];
-  }
+  lds_gather<4>(
+      L.line, spec, 6 * n0 * nh,
+      [=](int t) {
+        const int cx_ = fxn.div(t);
+        const int r = t - cx_ * n0 * nh;
+        const int x = fnh.div(r);
+        return cx_ * nspec + x * rs + off + (r - x * nh);
+      },
+      [=](int t) {
+        const int cx_ = fxn.div(t);
+        const int r = t - cx_ * n0 * nh;
+        const int x = fnh.div(r);
+        return (cx_ * nh + (r - x * nh)) * ld + x;
+      });
+  axis_lds_store<T>(L.ax, tf);
   __syncthreads();
   cx<T>* res = line_fft<-1, T, BIG>(L.line, L.scratch, ld, nl, L.ax, L.dc);
   cx<T>* oth = (res == L.line) ? L.scratch : L.line;
   // projection on every frequency (k0, k1, k2) of the tile; xi_i = k_i / L_i, L_i = n_i
-  const T scale = T(scale_in / double(rv.nvox));   // inverse DFT normalisation 1/|N|
+  const T scale = T(scale_in / double(nvox));   // inverse DFT normalisation 1/|N|
   const double k1 = double(sfreq(i1, n1)) / double(n1);
   for (int t = threadIdx.x; t < n0 * nh; t += blockDim.x) {
     const int x = fnh.div(t);
@@ -475,7 +636,7 @@ __global__ void __launch_bounds__(256) k_xpass(const RveDev* __restrict__ rvs, i
     const int r = t - cx_ * n0 * nh;
     const int x = fnh.div(r);
     const int hh = r - x * nh;
-    spec[cx_ * nspec + x * rs + off + hh] = res2[(cx_ * nh + hh) * ld + x];
+    gstore(spec + cx_ * nspec + x * rs + off + hh, res2[(cx_ * nh + hh) * ld + x]);
   }
 }
 
@@ -491,24 +652,47 @@ __global__ void __launch_bounds__(256) k_xpass(const RveDev* __restrict__ rvs, i
 // is recorded in status only, for the next forward pass to stop the solve:
 // the stop flag is read by all threads of these tiles without a barrier.
 // Not folded: k_finalize formed alpha (and the stop flag, before this
-// launch).  Returns false when the tile must exit.  Called by the whole
+// launch).  dn is the stop flag as thread 0 loaded it at kernel start (0 when
+// the caller has tested it already); the decision reaches every thread
+// through LDS.  Returns false when the tile must exit.  Called by the whole
 // workgroup (its barriers also publish the caller's LDS writes).  With
 // timing, the same loads and sums give alpha = 0 and touch no state.
-__device__ bool cg_alpha(const RveDev& rv, int tile, double pa, bool timing, double* red, double& alpha) {
+// CG scalars read by the vector update, loaded by every thread with the
+// kernel's other loads (none is written during the launch) and used by
+// thread 0 only, so that no thread waits for them on its own.
+struct CgPeek {
+  int done;
+  double rr, alpha;
+};
+__device__ __forceinline__ CgPeek cg_peek(CgState* cg) {
+  const FFTG_GLOBAL CgState* g = cg_vaddr(cg);
+  return CgPeek{g->done, g->rr, g->alpha};
+}
+
+__device__ bool cg_alpha(const RveDev& rv, int tile, const CgPeek& pk, bool check_done, double pa, bool timing,
+                         double* red, double& alpha) {
   CgState* cg = rv.cg;
+  const int dn = check_done ? pk.done : 0;
   alpha = 0.0;
   if (!rv.fold) {
+    if (threadIdx.x == 0) {
+      red[8] = dn ? 1.0 : 0.0;
+      red[9] = timing ? 0.0 : pk.alpha;
+    }
     __syncthreads();
-    if (!timing) alpha = cg->alpha;
+    if (red[8] != 0.0) return false;
+    alpha = red[9];
     return true;
   }
   const double pap = block_sum(pa, red);
   if (threadIdx.x == 0) {
-    if (timing) {
+    if (dn) {
+      red[8] = 1.0;  // stopped before this launch: no state change
+    } else if (timing) {
       red[8] = 0.0;
       red[9] = 0.0 * pap;
     } else {
-      const double rr = cg->rr;
+      const double rr = pk.rr;
       const bool brk = !(pap > 0.0) || !(pap < INFINITY);
       red[8] = brk ? 1.0 : 0.0;
       red[9] = rr / pap;
@@ -539,43 +723,77 @@ __global__ void __launch_bounds__(256) k_zinv(const RveDev* __restrict__ rvs, in
   const int ri = find_rve(rvs, nrve, P_ZI, tile);
   if (ri < 0) return;
   const RveDev& rv = rvs[ri];
-  if (rv.skip) return;
-  const int dn = check_done ? rv.cg->done : 0;  // no writer during the launch; tested after the table loads
-  const int n2 = rv.n2, H = rv.H;
-  const long long nvox = rv.nvox, nspec = rv.nspec;
-  const int nrows_tot = rv.n0 * rv.n1;
+  // descriptor fields, all loaded in one batch (the empty asm keeps the
+  // compiler from deferring any of them past the first use of another)
+  int n0 = rv.n0, n1 = rv.n1, n2 = rv.n2, H = rv.H;
+  long long nspec = rv.nspec;
+  const long long nvox = rv.nvox;
+  const cx<T>* specp = (const cx<T>*)rv.spec;
+  CgState* cg = rv.cg;
+  int fold = rv.fold, ntz = rv.tiles[P_ZF];
+  const double* part = rv.partial;
+  TileLds<T> L(smem, 3 * rows_per_tile, n2, rv.ax[2], ldmax, true);
+  __asm__ volatile(""
+                   : "+s"(n0), "+s"(n1), "+s"(n2), "+s"(H), "+s"(nspec), "+s"(specp), "+s"(cg), "+s"(fold),
+                     "+s"(ntz), "+s"(part), "+s"(L.ax.M), "+s"(L.ax.g_tw)
+                   :
+                   : "memory");
+  const FFTG_GLOBAL cx<T>* const spec = gmem(specp);
+  const int nrows_tot = n0 * n1;
   const int row0 = tile * rows_per_tile;
   const int nrows = min(rows_per_tile, nrows_tot - row0);
   const int ld = n2;
-  TileLds<T> L(smem, 3 * rows_per_tile, ld, rv.ax[2], ldmax);
-  if (dn) return;
   const bool cg_out = out_mode == OUT_CG || out_mode == OUT_CG_TIMING;
-  // this thread's share of the p.(C:p) partials, loaded with the spectrum
-  const double pa = (cg_out && rv.fold) ? thread_partials(rv.partial, rv.tiles[P_ZF]) : 0.0;
-  const cx<T>* spec = (const cx<T>*)rv.spec;
-  // Z_k = A_k + i B_k, Z_{n-k} = conj(A_k) + i conj(B_k)
+  // Stop flag (no writer during the launch).  The CG form over one RVE
+  // loads it in thread 0 with the data and decides at the alpha barrier;
+  // otherwise it is tested before any load, so that members of a batch that
+  // have stopped move no data.
+  const bool late = cg_out && launch_single(nrve);
+  if (check_done && !late && *gmem(&cg->done)) return;
+  const AxisFetch<T> tf = axis_lds_fetch<T>(L.ax);
+  // Z_k = A_k + i B_k, Z_{n-k} = conj(A_k) + i conj(B_k).  Loads are issued
+  // in program order before anything that waits: this thread's first two
+  // elements, then the partials (a loop that waits as it sums), then the
+  // stop flag; the LDS stores come after.
   const FastDiv fn2(n2), f3(3);
-  for (int t = threadIdx.x; t < nrows * 3 * n2; t += blockDim.x) {
-    const int rp = fn2.div(t);
-    const int z = t - rp * n2;
-    const int r = f3.div(rp), pr = rp - 3 * r;
-    const long long rowo = (long long)(row0 + r) * H;
-    cx<T> Z;
-    if (z < H) {
-      const cx<T> A = spec[(2 * pr) * nspec + rowo + z];
-      const cx<T> B = spec[(2 * pr + 1) * nspec + rowo + z];
-      Z = cx<T>{A.re - B.im, A.im + B.re};
-    } else {
-      const int k = n2 - z;
-      const cx<T> A = spec[(2 * pr) * nspec + rowo + k];
-      const cx<T> B = spec[(2 * pr + 1) * nspec + rowo + k];
-      Z = cx<T>{A.re + B.im, -A.im + B.re};
+  const int ne = nrows * 3 * n2;
+  const int bd = blockDim.x;
+  cx<T> A[2], B[2];
+  int ti[2];
+  auto load2 = [&](int t0) {
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      ti[u] = min(t0 + u * bd, ne - 1);
+      const int rp = fn2.div(ti[u]);
+      const int z = ti[u] - rp * n2;
+      const int r = f3.div(rp), pr = rp - 3 * r;
+      const long long o = (long long)(row0 + r) * H + (z < H ? z : n2 - z);
+      A[u] = gload(spec + (2 * pr) * nspec + o);
+      B[u] = gload(spec + (2 * pr + 1) * nspec + o);
     }
-    L.line[rp * ld + z] = Z;
+  };
+  auto store2 = [&]() {
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int rp = fn2.div(ti[u]);
+      const int z = ti[u] - rp * n2;
+      L.line[rp * ld + z] = z < H ? cx<T>{A[u].re - B[u].im, A[u].im + B[u].re}
+                                  : cx<T>{A[u].re + B[u].im, -A[u].im + B[u].re};
+    }
+  };
+  load2(threadIdx.x);
+  const CgPeek pk = cg_peek(cg);
+  // this thread's share of the p.(C:p) partials
+  const double pa = (cg_out && fold) ? thread_partials(part, ntz) : 0.0;
+  store2();
+  for (int t0 = threadIdx.x + 2 * bd; t0 < ne; t0 += 2 * bd) {
+    load2(t0);
+    store2();
   }
+  axis_lds_store<T>(L.ax, tf);
   double alpha = 0.0;
   if (cg_out) {
-    if (!cg_alpha(rv, tile, pa, out_mode == OUT_CG_TIMING, L.red, alpha)) return;
+    if (!cg_alpha(rv, tile, pk, check_done && late, pa, out_mode == OUT_CG_TIMING, L.red, alpha)) return;
   } else {
     __syncthreads();
   }
@@ -583,9 +801,9 @@ __global__ void __launch_bounds__(256) k_zinv(const RveDev* __restrict__ rvs, in
   double dot = 0.0;
   if (cg_out) {
     // x += alpha p, r -= alpha G:(C:p), partials of the new r.r
-    double* __restrict__ xx = (double*)rv.buf[R_X];
-    double* __restrict__ rr = (double*)rv.buf[R_R];
-    const double* __restrict__ p = (const double*)rv.buf[p_role];
+    FFTG_GLOBAL double* __restrict__ xx = gmem((double*)rv.buf[R_X]);
+    FFTG_GLOBAL double* __restrict__ rr = gmem((double*)rv.buf[R_R]);
+    const FFTG_GLOBAL double* __restrict__ p = gmem((const double*)rv.buf[p_role]);
     for (int t = threadIdx.x; t < nrows * n2; t += blockDim.x) {
       const int r = fn2.div(t);
       const int z = t - r * n2;
@@ -606,9 +824,9 @@ __global__ void __launch_bounds__(256) k_zinv(const RveDev* __restrict__ rvs, in
     put_partials(&s, 1, rv.partial_rr, rv.tiles[P_ZI], tile);
     return;
   } else if (out_mode == OUT_RESIDUAL) {
-    double* rr = (double*)rv.buf[R_R];
-    double* pp = (double*)rv.buf[R_P];
-    double* xx = (double*)rv.buf[R_X];
+    FFTG_GLOBAL double* rr = gmem((double*)rv.buf[R_R]);
+    FFTG_GLOBAL double* pp = gmem((double*)rv.buf[R_P]);
+    FFTG_GLOBAL double* xx = gmem((double*)rv.buf[R_X]);
     for (int t = threadIdx.x; t < nrows * n2; t += blockDim.x) {
       const int r = fn2.div(t);
       const int z = t - r * n2;
@@ -627,7 +845,7 @@ __global__ void __launch_bounds__(256) k_zinv(const RveDev* __restrict__ rvs, in
       }
     }
   } else {
-    T* out = (T*)rv.buf[out_role];
+    FFTG_GLOBAL T* out = gmem((T*)rv.buf[out_role]);
     for (int t = threadIdx.x; t < nrows * n2; t += blockDim.x) {
       const int r = fn2.div(t);
       const int z = t - r * n2;
@@ -682,7 +900,6 @@ __global__ void __launch_bounds__(512) k_slab_fwd(const RveDev* __restrict__ rvs
   const int ri = find_rve(rvs, nrve, P_ZF, tile);
   if (ri < 0) return;
   const RveDev& rv = rvs[ri];
-  if (rv.skip) return;
   const int dn = done_peek(check_done, rv.cg);
   const int n1 = rv.n1, n2 = rv.n2, H = rv.H;
   const long long nspec = rv.nspec;
@@ -693,7 +910,8 @@ __global__ void __launch_bounds__(512) k_slab_fwd(const RveDev* __restrict__ rvs
   // either branch ends in a barrier that also publishes tables and materials
   double beta = 0.0;
   if (update_p) {
-    if (!cg_begin_iter(rv, tile, dn, update_p, L.red, beta)) return;
+    const double pa = rv.fold ? thread_partials(rv.partial_rr, rv.tiles[P_ZI]) : 0.0;
+    if (!cg_begin_iter(rv, tile, dn, cg_peek_b(rv.cg), pa, update_p, L.red, beta)) return;
   } else if (done_publish(dn)) {
     return;
   }
@@ -748,7 +966,6 @@ __global__ void __launch_bounds__(512) k_slab_inv(const RveDev* __restrict__ rvs
   const int ri = find_rve(rvs, nrve, P_ZI, tile);
   if (ri < 0) return;
   const RveDev& rv = rvs[ri];
-  if (rv.skip) return;
   const int dn = done_peek(check_done, rv.cg);
   const int n1 = rv.n1, n2 = rv.n2, H = rv.H;
   const long long nvox = rv.nvox, nspec = rv.nspec;
@@ -768,7 +985,7 @@ __global__ void __launch_bounds__(512) k_slab_inv(const RveDev* __restrict__ rvs
   }
   double alpha = 0.0;
   if (cg_out) {
-    if (!cg_alpha(rv, tile, pa, out_mode == OUT_CG_TIMING, L.red, alpha)) return;
+    if (!cg_alpha(rv, tile, cg_peek(rv.cg), false, pa, out_mode == OUT_CG_TIMING, L.red, alpha)) return;
   } else {
     __syncthreads();
   }
@@ -851,7 +1068,6 @@ __global__ void __launch_bounds__(256) k_newton_update(const RveDev* __restrict_
   const int ri = find_rve(rvs, nrve, P_VEC, tile);
   if (ri < 0) return;
   const RveDev& rv = rvs[ri];
-  if (rv.skip) return;
   const long long nvox = rv.nvox;
   double* __restrict__ e = (double*)rv.buf[R_EPS_FL];
   const double* __restrict__ x = (const double*)rv.buf[R_X];
@@ -890,7 +1106,6 @@ __global__ void __launch_bounds__(256) k_constitutive(const RveDev* __restrict__
   const int ri = find_rve(rvs, nrve, P_VEC, tile);
   if (ri < 0) return;
   const RveDev& rv = rvs[ri];
-  if (rv.skip) return;
   const long long nvox = rv.nvox;
   const double* ein = (const double*)rv.buf[eps_role];
   const bool add_E = (eps_role == R_EPS_FL);
@@ -1141,6 +1356,9 @@ static void slab_inv_go(dim3 G, dim3 B, size_t lds, hipStream_t s, const RveDev*
                      p_role);
 }
 
+// Member count with the tile-mapping flag for the tiled kernels.
+static int nrve_arg(int nrve, const LaunchCfg& cfg) { return nrve | (cfg.xcd_remap ? kLaunchRemap : 0); }
+
 #define DISPATCH_TB(fn, ...)                          \
   do {                                                \
     if (mixed) {                                      \
@@ -1156,7 +1374,8 @@ hipError_t launch_zfwd(int mixed, const RveDev* rv, int nrve, int tiles, const L
                        int in_mode, int in_role, int tan_mode, int want_norm, int check_done, int update_p,
                        hipStream_t s) {
   if (tiles <= 0) return hipSuccess;
-  DISPATCH_TB(zfwd_go, dim3(tiles), dim3(cfg.threads_z), lds, s, rv, nrve, cfg.rows_per_tile, cfg.n2max, in_mode,
+  const int nr = nrve_arg(nrve, cfg);
+  DISPATCH_TB(zfwd_go, dim3(tiles), dim3(cfg.threads_z), lds, s, rv, nr, cfg.rows_per_tile, cfg.n2max, in_mode,
               in_role, tan_mode, want_norm, check_done, update_p);
   return hipGetLastError();
 }
@@ -1164,22 +1383,23 @@ hipError_t launch_zfwd(int mixed, const RveDev* rv, int nrve, int tiles, const L
 hipError_t launch_ypass(int mixed, int dir, const RveDev* rv, int nrve, int tiles, const LaunchCfg& cfg,
                         size_t lds, int check_done, hipStream_t s) {
   if (tiles <= 0) return hipSuccess;
+  const int nr = nrve_arg(nrve, cfg);
   const dim3 G(tiles), B(cfg.threads_y);
   if (mixed) {
     if (cfg.big_radix) {
-      if (dir < 0) ypass_go<float, -1, 1>(G, B, lds, s, rv, nrve, cfg.lines_y, cfg.n1max, check_done);
-      else ypass_go<float, 1, 1>(G, B, lds, s, rv, nrve, cfg.lines_y, cfg.n1max, check_done);
+      if (dir < 0) ypass_go<float, -1, 1>(G, B, lds, s, rv, nr, cfg.lines_y, cfg.n1max, check_done);
+      else ypass_go<float, 1, 1>(G, B, lds, s, rv, nr, cfg.lines_y, cfg.n1max, check_done);
     } else {
-      if (dir < 0) ypass_go<float, -1, 0>(G, B, lds, s, rv, nrve, cfg.lines_y, cfg.n1max, check_done);
-      else ypass_go<float, 1, 0>(G, B, lds, s, rv, nrve, cfg.lines_y, cfg.n1max, check_done);
+      if (dir < 0) ypass_go<float, -1, 0>(G, B, lds, s, rv, nr, cfg.lines_y, cfg.n1max, check_done);
+      else ypass_go<float, 1, 0>(G, B, lds, s, rv, nr, cfg.lines_y, cfg.n1max, check_done);
     }
   } else {
     if (cfg.big_radix) {
-      if (dir < 0) ypass_go<double, -1, 1>(G, B, lds, s, rv, nrve, cfg.lines_y, cfg.n1max, check_done);
-      else ypass_go<double, 1, 1>(G, B, lds, s, rv, nrve, cfg.lines_y, cfg.n1max, check_done);
+      if (dir < 0) ypass_go<double, -1, 1>(G, B, lds, s, rv, nr, cfg.lines_y, cfg.n1max, check_done);
+      else ypass_go<double, 1, 1>(G, B, lds, s, rv, nr, cfg.lines_y, cfg.n1max, check_done);
     } else {
-      if (dir < 0) ypass_go<double, -1, 0>(G, B, lds, s, rv, nrve, cfg.lines_y, cfg.n1max, check_done);
-      else ypass_go<double, 1, 0>(G, B, lds, s, rv, nrve, cfg.lines_y, cfg.n1max, check_done);
+      if (dir < 0) ypass_go<double, -1, 0>(G, B, lds, s, rv, nr, cfg.lines_y, cfg.n1max, check_done);
+      else ypass_go<double, 1, 0>(G, B, lds, s, rv, nr, cfg.lines_y, cfg.n1max, check_done);
     }
   }
   return hipGetLastError();
@@ -1188,7 +1408,8 @@ hipError_t launch_ypass(int mixed, int dir, const RveDev* rv, int nrve, int tile
 hipError_t launch_xpass(int mixed, const RveDev* rv, int nrve, int tiles, const LaunchCfg& cfg, size_t lds,
                         double scale, int check_done, hipStream_t s) {
   if (tiles <= 0) return hipSuccess;
-  DISPATCH_TB(xpass_go, dim3(tiles), dim3(cfg.threads_x), lds, s, rv, nrve, cfg.lines_x, cfg.n0max, scale,
+  const int nr = nrve_arg(nrve, cfg);
+  DISPATCH_TB(xpass_go, dim3(tiles), dim3(cfg.threads_x), lds, s, rv, nr, cfg.lines_x, cfg.n0max, scale,
               check_done);
   return hipGetLastError();
 }
@@ -1196,7 +1417,8 @@ hipError_t launch_xpass(int mixed, const RveDev* rv, int nrve, int tiles, const 
 hipError_t launch_zinv(int mixed, const RveDev* rv, int nrve, int tiles, const LaunchCfg& cfg, size_t lds,
                        int out_mode, int out_role, int check_done, int p_role, hipStream_t s) {
   if (tiles <= 0) return hipSuccess;
-  DISPATCH_TB(zinv_go, dim3(tiles), dim3(cfg.threads_z), lds, s, rv, nrve, cfg.rows_per_tile, cfg.n2max, out_mode,
+  const int nr = nrve_arg(nrve, cfg);
+  DISPATCH_TB(zinv_go, dim3(tiles), dim3(cfg.threads_z), lds, s, rv, nr, cfg.rows_per_tile, cfg.n2max, out_mode,
               out_role, check_done, p_role);
   return hipGetLastError();
 }
@@ -1205,7 +1427,8 @@ hipError_t launch_slab_fwd(int mixed, const RveDev* rv, int nrve, int tiles, con
                            int in_mode, int in_role, int tan_mode, int want_norm, int check_done, int update_p,
                            int p_in, int p_out, hipStream_t s) {
   if (tiles <= 0) return hipSuccess;
-  DISPATCH_TB(slab_fwd_go, dim3(tiles), dim3(cfg.threads_s), lds, s, rv, nrve, cfg.n1max, cfg.n2max, in_mode,
+  const int nr = nrve_arg(nrve, cfg);
+  DISPATCH_TB(slab_fwd_go, dim3(tiles), dim3(cfg.threads_s), lds, s, rv, nr, cfg.n1max, cfg.n2max, in_mode,
               in_role, tan_mode, want_norm, check_done, update_p, p_in, p_out);
   return hipGetLastError();
 }
@@ -1213,25 +1436,28 @@ hipError_t launch_slab_fwd(int mixed, const RveDev* rv, int nrve, int tiles, con
 hipError_t launch_slab_inv(int mixed, const RveDev* rv, int nrve, int tiles, const LaunchCfg& cfg, size_t lds,
                            int out_mode, int out_role, int check_done, int p_role, hipStream_t s) {
   if (tiles <= 0) return hipSuccess;
-  DISPATCH_TB(slab_inv_go, dim3(tiles), dim3(cfg.threads_s), lds, s, rv, nrve, cfg.n1max, cfg.n2max, out_mode,
+  const int nr = nrve_arg(nrve, cfg);
+  DISPATCH_TB(slab_inv_go, dim3(tiles), dim3(cfg.threads_s), lds, s, rv, nr, cfg.n1max, cfg.n2max, out_mode,
               out_role, check_done, p_role);
   return hipGetLastError();
 }
 
 hipError_t launch_newton_update(const RveDev* rv, int nrve, int tiles, const LaunchCfg& cfg, hipStream_t s) {
   if (tiles <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_newton_update, dim3(tiles), dim3(cfg.threads_v), 0, s, rv, nrve, cfg.vec_per_tile);
+  const int nr = nrve_arg(nrve, cfg);
+  hipLaunchKernelGGL(k_newton_update, dim3(tiles), dim3(cfg.threads_v), 0, s, rv, nr, cfg.vec_per_tile);
   return hipGetLastError();
 }
 
 hipError_t launch_constitutive(int mixed, const RveDev* rv, int nrve, int tiles, const LaunchCfg& cfg,
                                int eps_role, int commit, hipStream_t s) {
   if (tiles <= 0) return hipSuccess;
+  const int nr = nrve_arg(nrve, cfg);
   if (mixed)
-    hipLaunchKernelGGL(k_constitutive<float>, dim3(tiles), dim3(cfg.threads_v), 0, s, rv, nrve, cfg.vec_per_tile,
+    hipLaunchKernelGGL(k_constitutive<float>, dim3(tiles), dim3(cfg.threads_v), 0, s, rv, nr, cfg.vec_per_tile,
                        eps_role, commit);
   else
-    hipLaunchKernelGGL(k_constitutive<double>, dim3(tiles), dim3(cfg.threads_v), 0, s, rv, nrve,
+    hipLaunchKernelGGL(k_constitutive<double>, dim3(tiles), dim3(cfg.threads_v), 0, s, rv, nr,
                        cfg.vec_per_tile, eps_role, commit);
   return hipGetLastError();
 }

@@ -390,6 +390,7 @@ static LaunchCfg choose_cfg(const GridSum& gs) {
   c.slab = (slab_mode() == 2 && slab_fits(gs.n1, gs.n2)) ? 1 : 0;
   c.threads_s = 256;
   c.big_radix = gs.big;
+  c.xcd_remap = env_long("FFTG_XCD_REMAP", 1) == 1 ? 1 : 0;
   c.n0max = gs.n0;
   c.n1max = gs.n1;
   c.n2max = gs.n2;
@@ -696,7 +697,6 @@ struct Group {
   bool own;                      // device arrays owned by the group
   double active_vox;             // voxels of the members not skipped
   bool need_fin = false;         // some active member runs the CG steps in k_finalize
-  int xcd_remap;
 };
 
 static void fill_desc(RveDev& rv, fftg_plan pl, fftg_history h, const LaunchCfg& cfg) {
@@ -766,7 +766,6 @@ static void group_set_cfg(Group& g, const LaunchCfg& c) {
 static void group_config(Group& g) {
   g.cfg = choose_cfg(group_gridsum(g));
   group_set_cfg(g, g.cfg);
-  g.xcd_remap = (int)env_long("FFTG_XCD_REMAP", 1) == 1;
 }
 
 static void group_totals(Group& g) {
@@ -805,7 +804,6 @@ static fftg_status group_upload(Group& g) {
   g.need_fin = false;
   for (size_t i = 0; i < n; ++i) {
     RveDev& rv = g.h[i];
-    rv.xcd_remap = g.xcd_remap;
     rv.fold = fold_ok(rv) ? 1 : 0;
     if (!rv.skip && !rv.fold) g.need_fin = true;
   }

@@ -203,7 +203,16 @@ typedef enum {
   FFTG_KERNEL_COUNT = 8
 } fftg_kernel_id;
 fftg_status fftg_profiler_start(int kernel_id);
+/* As fftg_profiler_start, but brackets only launches 0, every, 2 every, ...
+ * of that kind (every >= 1; FFTG_E_INVALID otherwise): each pair of events
+ * adds a few microseconds of queue processing between kernels, which
+ * sampling keeps out of most of a timed run.  stop then reports the
+ * bracketed launches only; fftg_profiler_seen gives all of them. */
+fftg_status fftg_profiler_start_every(int kernel_id, int every);
 fftg_status fftg_profiler_stop(double* total_ms, long long* launches, double* voxels);
+/* Launches of the profiled kind since the last start, bracketed or not
+ * (kept after stop until the next start). */
+long long fftg_profiler_seen(void);
 
 const char* fftg_last_error(void);
 

@@ -532,12 +532,13 @@ __global__ void __launch_bounds__(256) k_ypass(const RveDev* __restrict__ rvs, i
   const int nh = min(lines_per_tile, H - h0);
   // Stop flag (no writer during the launch): a launch over several RVEs
   // tests it before the loads, so that members that have stopped move no
-  // data.  A launch over one RVE does not wait for it: after the solve has
-  // stopped this pass only transforms the spectrum, which no later step
-  // reads before overwriting it, and the test would put one more memory
-  // round trip before the loads of every launch.
-  if (check_done && !launch_single(nrve) && *gmem(&cg->done)) return;
+  // data.  A launch over one RVE loads it with the data (as a per-thread
+  // value, so that nothing waits for it alone) and skips the transform and
+  // the stores once the data have arrived.
+  const bool single = launch_single(nrve);
+  if (check_done && !single && *gmem(&cg->done)) return;
   const AxisFetch<T> tf = axis_lds_fetch<T>(L.ax);
+  const int dn1 = cg_vaddr(cg)->done;  // unconditional: a guarded load would be waited for at its guard
   FFTG_GLOBAL cx<T>* base = gmem(spec) + c * nspec + (long long)i0 * n1 * H + h0;
   const FastDiv fnh(nh);
   lds_gather<4>(
@@ -551,6 +552,7 @@ __global__ void __launch_bounds__(256) k_ypass(const RveDev* __restrict__ rvs, i
         return (t - y * nh) * ld + y;
       });
   axis_lds_store<T>(L.ax, tf);
+  if (check_done && single && dn1) return;
   __syncthreads();
   cx<T>* res = line_fft<DIR, T, BIG>(L.line, L.scratch, ld, nh, L.ax, L.dc);
   for (int t = threadIdx.x; t < n1 * nh; t += blockDim.x) {
@@ -584,8 +586,10 @@ __global__ void __launch_bounds__(256) k_xpass(const RveDev* __restrict__ rvs, i
   const int ld = n0;
   const int nl = 6 * nh;
   // stop flag: as in the y pass (tested first only over several RVEs)
-  if (check_done && !launch_single(nrve) && *gmem(&cg->done)) return;
+  const bool single = launch_single(nrve);
+  if (check_done && !single && *gmem(&cg->done)) return;
   const AxisFetch<T> tf = axis_lds_fetch<T>(L.ax);
+  const int dn1 = cg_vaddr(cg)->done;  // unconditional: a guarded load would be waited for at its guard
   const long long rs = (long long)n1 * H;
   const long long off = (long long)i1 * H + h0;
   const FastDiv fxn(n0 * nh), fnh(nh);
@@ -604,6 +608,7 @@ __global__ void __launch_bounds__(256) k_xpass(const RveDev* __restrict__ rvs, i
         return (cx_ * nh + (r - x * nh)) * ld + x;
       });
   axis_lds_store<T>(L.ax, tf);
+  if (check_done && single && dn1) return;
   __syncthreads();
   cx<T>* res = line_fft<-1, T, BIG>(L.line, L.scratch, ld, nl, L.ax, L.dc);
   cx<T>* oth = (res == L.line) ? L.scratch : L.line;

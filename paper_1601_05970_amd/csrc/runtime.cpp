@@ -614,7 +614,9 @@ struct Profiler {
   std::vector<hipEvent_t> pool;   // 2 per recorded launch
   size_t used = 0;
   double voxels = 0.0;
-  long long launches = 0;
+  long long launches = 0;  // bracketed
+  long long seen = 0;      // all launches of the kind
+  int every = 1;           // bracket one launch in every
 };
 static Profiler g_prof;
 static std::mutex g_prof_mutex;
@@ -623,6 +625,7 @@ static int prof_begin(int kid, hipStream_t s) {
   if (g_prof.kid != kid) return -1;  // racy read is benign: profiling is off or on for one kind
   std::lock_guard<std::mutex> lk(g_prof_mutex);
   if (g_prof.kid != kid) return -1;
+  if (g_prof.seen++ % g_prof.every != 0) return -1;
   if (g_prof.used + 2 > g_prof.pool.size()) {
     for (int i = 0; i < 64; ++i) {
       // timing-only events: no system-scope fence (cache write-back and
@@ -647,14 +650,24 @@ static void prof_end(int idx, hipStream_t s, double voxels) {
   g_prof.voxels += voxels;
 }
 
-fftg_status fftg_profiler_start(int kernel_id) {
+fftg_status fftg_profiler_start_every(int kernel_id, int every) {
   if (kernel_id < 0 || kernel_id >= FFTG_KERNEL_COUNT) return fail(FFTG_E_INVALID, "bad kernel id");
+  if (every < 1) return fail(FFTG_E_INVALID, "every must be >= 1");
   std::lock_guard<std::mutex> lk(g_prof_mutex);
   g_prof.kid = kernel_id;
   g_prof.used = 0;
   g_prof.voxels = 0.0;
   g_prof.launches = 0;
+  g_prof.seen = 0;
+  g_prof.every = every;
   return FFTG_OK;
+}
+
+fftg_status fftg_profiler_start(int kernel_id) { return fftg_profiler_start_every(kernel_id, 1); }
+
+long long fftg_profiler_seen(void) {
+  std::lock_guard<std::mutex> lk(g_prof_mutex);
+  return g_prof.seen;
 }
 
 fftg_status fftg_profiler_stop(double* total_ms, long long* launches, double* voxels) {

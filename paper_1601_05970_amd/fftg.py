@@ -39,7 +39,8 @@ EXPORTS = [
     "fftg_history_destroy", "fftg_solve_increment", "fftg_apply_GK", "fftg_eval_constitutive",
     "fftg_get_field", "fftg_set_field", "fftg_history_get_E", "fftg_history_save", "fftg_history_restore",
     "fftg_footprint_bytes", "fftg_batch_create", "fftg_batch_destroy", "fftg_batch_solve_increment",
-    "fftg_profiler_start", "fftg_profiler_stop", "fftg_last_error",
+    "fftg_profiler_start", "fftg_profiler_start_every", "fftg_profiler_stop", "fftg_profiler_seen",
+    "fftg_last_error",
 ]
 FFTG_KERNEL_ZFWD, FFTG_KERNEL_Y_FWD, FFTG_KERNEL_X_PROJ, FFTG_KERNEL_Y_INV, FFTG_KERNEL_ZINV = range(5)
 FFTG_KERNEL_FINALIZE, FFTG_KERNEL_CONSTITUTIVE, FFTG_KERNEL_NEWTON = range(5, 8)
@@ -113,13 +114,17 @@ def lib():
     L.fftg_batch_destroy.restype = None
     L.fftg_batch_solve_increment.argtypes = [vp, dp, C.POINTER(fftg_stats)]
     L.fftg_profiler_start.argtypes = [ip]
+    L.fftg_profiler_start_every.argtypes = [ip, ip]
+    L.fftg_profiler_seen.argtypes = []
+    L.fftg_profiler_seen.restype = C.c_longlong
     L.fftg_profiler_stop.argtypes = [dp, C.POINTER(C.c_longlong), dp]
     L.fftg_last_error.argtypes = []
     L.fftg_last_error.restype = C.c_char_p
     for name in ("fftg_plan_create", "fftg_history_create", "fftg_solve_increment", "fftg_apply_GK",
                  "fftg_eval_constitutive", "fftg_get_field", "fftg_set_field", "fftg_history_get_E",
                  "fftg_history_save", "fftg_history_restore", "fftg_batch_create",
-                 "fftg_batch_solve_increment", "fftg_profiler_start", "fftg_profiler_stop"):
+                 "fftg_batch_solve_increment", "fftg_profiler_start", "fftg_profiler_start_every",
+                 "fftg_profiler_stop"):
         getattr(L, name).restype = C.c_int
     _lib = L
     return L
@@ -164,6 +169,14 @@ def tensor_to_mandel_components(t6: Sequence[float]) -> np.ndarray:
 
 def fftg_profiler_start(kernel_id: int):
     check(lib().fftg_profiler_start(kernel_id))
+
+
+def fftg_profiler_start_every(kernel_id: int, every: int):
+    check(lib().fftg_profiler_start_every(kernel_id, every))
+
+
+def fftg_profiler_seen() -> int:
+    return int(lib().fftg_profiler_seen())
 
 
 def fftg_profiler_stop():

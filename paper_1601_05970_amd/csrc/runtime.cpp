@@ -948,10 +948,12 @@ static double cg_remaining(const Group& g, const CgState* cs, int chunk_max) {
 // drains while the host inspects the older snapshot; the next chunk is sized
 // from the residual decay minus the iterations already queued.  Launches
 // that start after convergence exit at once, so the result equals that of
-// stopping exactly at convergence.
+// stopping exactly at convergence.  It returns without waiting for the
+// stream: whatever the caller enqueues next runs after those launches.
 static fftg_status run_cg(Group& g, int chunk_max) {
   const size_t n = g.h.size();
   g.cg_par = 0;
+  int queued = 0;
   struct Snap {
     int slot;   // 1 or 2
     int after;  // iterations enqueued after this snapshot
@@ -961,6 +963,7 @@ static fftg_status run_cg(Group& g, int chunk_max) {
   auto push_chunk = [&](int c) -> fftg_status {
     fftg_status st = enqueue_cg_iters(g, c);
     if (st != FFTG_OK) return st;
+    queued += c;
     for (int i = 0; i < nq; ++i) q[i].after += c;
     const int slot = (nq == 0) ? 1 : 3 - q[nq - 1].slot;
     HIP_TRY(hipMemcpyAsync(g.h_cg + slot * n, g.d_cg, n * sizeof(CgState), hipMemcpyDeviceToHost, g.stream));
@@ -968,15 +971,23 @@ static fftg_status run_cg(Group& g, int chunk_max) {
     q[nq++] = {slot, 0};
     return FFTG_OK;
   };
-  fftg_status st = push_chunk(chunk_max);
+  // The first snapshot is the state the residual pass left, with a short
+  // first chunk behind it: a right-hand side already under the target then
+  // costs a few early-exit iterations instead of two chunks.
+  fftg_status st = push_chunk(0);
   if (st != FFTG_OK) return st;
-  if ((st = push_chunk(chunk_max)) != FFTG_OK) return st;
+  if ((st = push_chunk(std::min(chunk_max, 8))) != FFTG_OK) return st;
   for (;;) {
     const Snap old = q[0];
     HIP_TRY(hipEventSynchronize(g.snap_ev[old.slot - 1]));
     const double need = cg_remaining(g, g.h_cg + old.slot * n, chunk_max);
     if (need == 0.0) {
-      HIP_TRY(hipStreamSynchronize(g.stream));
+      if (env_long("FFTG_VERBOSE", 0) >= 2) {
+        int most = 0;
+        for (size_t i = 0; i < n; ++i)
+          if (!g.h[i].skip) most = std::max(most, g.h_cg[old.slot * n + i].iters);
+        fprintf(stderr, "fftg cg: %d iterations enqueued, %d needed\n", queued, most);
+      }
       return FFTG_OK;
     }
     q[0] = q[1];

@@ -365,9 +365,14 @@ __device__ cx<T>* line_fft(cx<T>* line, cx<T>* scratch, int ld, int nl, const Ax
     return a;
   }
   if (P.rader == AX_DIRECT) {
-    // X_k = sum_j x_j w^(jk), w = exp(-+ 2 pi i / N), N odd.  One thread forms the
-    // pair X_k, X_(N-k) (k = 1 .. (N-1)/2; slot 0 forms X_0): both use the
-    // products of x_j with the same root w^(jk), taken conjugated for N-k.
+    // X_k = sum_j x_j w^(jk), w = exp(-+ 2 pi i / N), N odd.  With
+    // s_j = x_j + x_(N-j) and d_j = x_j - x_(N-j) (j = 1 .. (N-1)/2) and
+    // theta = 2 pi j k / N,
+    //   X_k = A + DIR i B,  X_(N-k) = A - DIR i B,
+    //   A = x_0 + sum_j s_j cos theta,  B = sum_j d_j sin theta,
+    // so one thread forms the pair X_k, X_(N-k) (k = 1 .. (N-1)/2; slot 0
+    // forms X_0) with four multiply-adds per j.  The root table holds
+    // exp(-i theta) = (cos theta, -sin theta).
     const int N = P.M;
     const int Hn = (N + 1) / 2;
     const FastDiv fh(Hn);
@@ -375,23 +380,25 @@ __device__ cx<T>* line_fft(cx<T>* line, cx<T>* scratch, int ld, int nl, const Ax
       const int l = fh.div(t);
       const int k = t - l * Hn;
       const cx<T>* x = line + l * ld;
-      T pr = T(0), pi = T(0), mr = T(0), mi = T(0);  // X_k and X_(N-k)
+      const cx<T> x0 = x[0];
+      T ar = x0.re, ai = x0.im, cr = T(0), ci = T(0);  // A and C = -B = sum_j d_j (-sin theta)
       int idx = 0;
-      for (int j = 0; j < N; ++j) {
-        const cx<T> w = P.tw[idx];
-        const T s = DIR > 0 ? -w.im : w.im;
-        const cx<T> a = x[j];
-        pr += a.re * w.re;
-        pr -= a.im * s;
-        pi += a.re * s;
-        pi += a.im * w.re;
-        mr += a.re * w.re;
-        mr += a.im * s;
-        mi += a.im * w.re;
-        mi -= a.re * s;
+#pragma unroll 4
+      for (int j = 1; j < Hn; ++j) {
         idx += k;
         idx -= (idx >= N) ? N : 0;
+        const cx<T> w = P.tw[idx];
+        const cx<T> a = x[j], b = x[N - j];
+        ar += (a.re + b.re) * w.re;
+        ai += (a.im + b.im) * w.re;
+        cr += (a.re - b.re) * w.im;
+        ci += (a.im - b.im) * w.im;
       }
+      // i B = -i C = (C.im, -C.re)
+      const T pr = DIR > 0 ? ar + ci : ar - ci;
+      const T pi = DIR > 0 ? ai - cr : ai + cr;
+      const T mr = DIR > 0 ? ar - ci : ar + ci;
+      const T mi = DIR > 0 ? ai + cr : ai - cr;
       cx<T>* o = scratch + l * ld;
       o[k] = cx<T>{pr, pi};
       if (k > 0) o[N - k] = cx<T>{mr, mi};

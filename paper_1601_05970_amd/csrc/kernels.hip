@@ -790,6 +790,21 @@ __global__ void __launch_bounds__(256) k_zinv(const RveDev* __restrict__ rvs, in
   const CgPeek pk = cg_peek(cg);
   // this thread's share of the p.(C:p) partials
   const double pa = (cg_out && fold) ? thread_partials(part, ntz) : 0.0;
+  // the vector update's inputs at this thread's first voxel (v = row0 n2 + t)
+  const int nvt = nrows * n2;
+  double xv0[6], rv0[6], pv0[6];
+  if (cg_out) {
+    const long long v = (long long)row0 * n2 + min((int)threadIdx.x, nvt - 1);
+    const FFTG_GLOBAL double* gx = gmem((const double*)rv.buf[R_X]);
+    const FFTG_GLOBAL double* gr = gmem((const double*)rv.buf[R_R]);
+    const FFTG_GLOBAL double* gp = gmem((const double*)rv.buf[p_role]);
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+      xv0[c] = gx[c * nvox + v];
+      rv0[c] = gr[c * nvox + v];
+      pv0[c] = gp[c * nvox + v];
+    }
+  }
   store2();
   for (int t0 = threadIdx.x + 2 * bd; t0 < ne; t0 += 2 * bd) {
     load2(t0);
@@ -809,21 +824,33 @@ __global__ void __launch_bounds__(256) k_zinv(const RveDev* __restrict__ rvs, in
     FFTG_GLOBAL double* __restrict__ xx = gmem((double*)rv.buf[R_X]);
     FFTG_GLOBAL double* __restrict__ rr = gmem((double*)rv.buf[R_R]);
     const FFTG_GLOBAL double* __restrict__ p = gmem((const double*)rv.buf[p_role]);
-    for (int t = threadIdx.x; t < nrows * n2; t += blockDim.x) {
+    auto update = [&](int t, const double* xv, const double* rv6, const double* pv) {
       const int r = fn2.div(t);
       const int z = t - r * n2;
       const long long v = (long long)(row0 + r) * n2 + z;
 #pragma unroll
       for (int pr = 0; pr < 3; ++pr) {
         const cx<T> w = res[(3 * r + pr) * ld + z];
-        const long long i0 = (2 * pr) * nvox + v, i1 = (2 * pr + 1) * nvox + v;
-        const double r0 = rr[i0] - alpha * double(w.re), r1 = rr[i1] - alpha * double(w.im);
-        xx[i0] += alpha * p[i0];
-        xx[i1] += alpha * p[i1];
-        rr[i0] = r0;
-        rr[i1] = r1;
+        const int c0 = 2 * pr, c1 = 2 * pr + 1;
+        const double r0 = rv6[c0] - alpha * double(w.re), r1 = rv6[c1] - alpha * double(w.im);
+        xx[c0 * nvox + v] = xv[c0] + alpha * pv[c0];
+        xx[c1 * nvox + v] = xv[c1] + alpha * pv[c1];
+        rr[c0 * nvox + v] = r0;
+        rr[c1 * nvox + v] = r1;
         dot += r0 * r0 + r1 * r1;
       }
+    };
+    if ((int)threadIdx.x < nvt) update(threadIdx.x, xv0, rv0, pv0);
+    for (int t = threadIdx.x + blockDim.x; t < nvt; t += blockDim.x) {
+      const long long v = (long long)row0 * n2 + t;
+      double xv[6], rv6[6], pv[6];
+#pragma unroll
+      for (int c = 0; c < 6; ++c) {
+        xv[c] = xx[c * nvox + v];
+        rv6[c] = rr[c * nvox + v];
+        pv[c] = p[c * nvox + v];
+      }
+      update(t, xv, rv6, pv);
     }
     const double s = block_sum(dot, L.red);
     put_partials(&s, 1, rv.partial_rr, rv.tiles[P_ZI], tile);

@@ -909,10 +909,12 @@ struct SlabLds {
   cx<T>* b1;
   cx<T>* dc;
   double* red;
+  // The tables are only carved out: the kernels copy them with
+  // axis_lds_fetch / axis_lds_store around their own loads.
   __device__ SlabLds(char* base, int n1max, int n2max, const AxisDev& Pz, const AxisDev& Py) {
-    load_axis_lds<T>(Pz, base, az);
+    axis_lds_setup<T>(Pz, base, az);
     char* q = base + axis_lds_bytes<T>(n2max);
-    load_axis_lds<T>(Py, q, ay);
+    axis_lds_setup<T>(Py, q, ay);
     q += axis_lds_bytes<T>(n1max);
     const size_t S = (size_t)n1max * (n2max + 1);
     b0 = reinterpret_cast<cx<T>*>(q);
@@ -932,35 +934,67 @@ __global__ void __launch_bounds__(512) k_slab_fwd(const RveDev* __restrict__ rvs
   const int ri = find_rve(rvs, nrve, P_ZF, tile);
   if (ri < 0) return;
   const RveDev& rv = rvs[ri];
-  const int dn = done_peek(check_done, rv.cg);
-  const int n1 = rv.n1, n2 = rv.n2, H = rv.H;
+  // descriptor fields, all loaded in one batch (the empty asm keeps the
+  // compiler from deferring any of them past the first use of another)
+  int n1 = rv.n1, n2 = rv.n2, H = rv.H, nph = rv.n_phases, fold = rv.fold, nti = rv.tiles[P_ZI];
+  long long nvox = rv.nvox;
   const long long nspec = rv.nspec;
-  const int x = tile / 3, pr = tile - 3 * (tile / 3);
-  SlabLds<T> L(smem, n1max, n2max, rv.ax[2], rv.ax[1]);
-  __shared__ MatDev s_mats[kMaxPhases];  // per-voxel material lookups from LDS
-  if (threadIdx.x < rv.n_phases) s_mats[threadIdx.x] = rv.mats[threadIdx.x];
-  // either branch ends in a barrier that also publishes tables and materials
-  double beta = 0.0;
-  if (update_p) {
-    const double pa = rv.fold ? thread_partials(rv.partial_rr, rv.tiles[P_ZI]) : 0.0;
-    if (!cg_begin_iter(rv, tile, dn, cg_peek_b(rv.cg), pa, update_p, L.red, beta)) return;
-  } else if (done_publish(dn)) {
-    return;
-  }
+  CgState* cg = rv.cg;
   const double* in = (const double*)rv.buf[in_role];
   const double* rres = (const double*)rv.buf[R_R];
   const double* pin = (const double*)rv.buf[p_in];
   double* pout = (double*)rv.buf[p_out];
+  const void* tang = rv.tang;
+  const uint8_t* phase = rv.phase;
+  const double* prr = rv.partial_rr;
+  const MatDev* mats = rv.mats;
+  SlabLds<T> L(smem, n1max, n2max, rv.ax[2], rv.ax[1]);
+  __asm__ volatile(""
+                   : "+s"(n1), "+s"(n2), "+s"(H), "+s"(nph), "+s"(nvox), "+s"(cg), "+s"(in), "+s"(rres), "+s"(pin),
+                     "+s"(tang), "+s"(phase), "+s"(prr), "+s"(L.az.g_tw), "+s"(L.ay.g_tw)
+                   :
+                   : "memory");
+  const int x = tile / 3, pr = tile - 3 * (tile / 3);
   const long long v0 = (long long)x * n1 * n2;
   const int npl = n1 * n2;
+  __shared__ MatDev s_mats[kMaxPhases];  // per-voxel material lookups from LDS
+  // Loads in program order before anything that waits (as in the z pass):
+  // tables, this thread's first voxel, materials, CG scalars, partials.
+  const AxisFetch<T> tfz = axis_lds_fetch<T>(L.az);
+  const AxisFetch<T> tfy = axis_lds_fetch<T>(L.ay);
+  VoxIn<T> vi0;
+  voxel_load<T>(v0 + min((int)threadIdx.x, npl - 1), nvox, in_mode, in, update_p, rres, pin, tan_mode, tang, phase,
+                vi0);
+  const MatDev mt = mats_fetch(mats, nph);
+  const CgPeekB pk = cg_peek_b(cg);
+  const double pa = (update_p && fold) ? thread_partials(prr, nti) : 0.0;
+  axis_lds_store<T>(L.az, tfz);
+  axis_lds_store<T>(L.ay, tfy);
+  mats_store(mt, nph, s_mats);
+  // either branch ends in a barrier that also publishes tables and materials
+  const int dn = check_done ? pk.done : 0;
+  double beta = 0.0;
+  if (update_p) {
+    if (!cg_begin_iter(rv, tile, dn, pk, pa, update_p, L.red, beta)) return;
+  } else if (done_publish(dn)) {
+    return;
+  }
   double nrm = 0.0;  // ||tau||^2 (want_norm) or p.tau over the tile's components (update_p)
-  for (int t = threadIdx.x; t < npl; t += blockDim.x) {
+  auto process = [&](const VoxIn<T>& vi, int t) {
     T tau[6];
-    nrm += voxel_tau<T>(rv, v0 + t, in_mode, in, update_p, beta, rres, pin, pout, 2 * pr, 2 * pr + 2, tan_mode,
-                        s_mats, tau);
-    const T a = tau[2 * pr], b = tau[2 * pr + 1];
+    nrm += voxel_compute<T>(vi, v0 + t, nvox, in_mode, rv.dE, update_p, beta, pout, 2 * pr, 2 * pr + 2, tan_mode,
+                            s_mats, tau);
+    // selects, not an indexed read: a runtime index into tau would put it in scratch
+    const T a = pr == 0 ? tau[0] : (pr == 1 ? tau[2] : tau[4]);
+    const T b = pr == 0 ? tau[1] : (pr == 1 ? tau[3] : tau[5]);
     if (want_norm) nrm += double(a) * double(a) + double(b) * double(b);
     L.b0[t] = cx<T>{a, b};  // z-line y at y * n2
+  };
+  if ((int)threadIdx.x < npl) process(vi0, threadIdx.x);
+  for (int t = threadIdx.x + blockDim.x; t < npl; t += blockDim.x) {
+    VoxIn<T> vi;
+    voxel_load<T>(v0 + t, nvox, in_mode, in, update_p, rres, pin, tan_mode, tang, phase, vi);
+    process(vi, t);
   }
   __syncthreads();
   cx<T>* res = line_fft<-1, T, BIG>(L.b0, L.b1, n2, n1, L.az, L.dc);
@@ -977,12 +1011,12 @@ __global__ void __launch_bounds__(512) k_slab_fwd(const RveDev* __restrict__ rvs
   }
   __syncthreads();
   cx<T>* res2 = line_fft<-1, T, BIG>(oth, res, n1, 2 * H, L.ay, L.dc);
-  cx<T>* spec = (cx<T>*)rv.spec;
+  FFTG_GLOBAL cx<T>* spec = gmem((cx<T>*)rv.spec);
   for (int t = threadIdx.x; t < 2 * n1 * H; t += blockDim.x) {
     const int cy = fH.div(t);
     const int k = t - cy * H;
     const int c2 = fn1.div(cy), y = cy - c2 * n1;
-    spec[(2 * pr + c2) * nspec + ((long long)x * n1 + y) * H + k] = res2[(c2 * H + k) * n1 + y];
+    gstore(spec + (2 * pr + c2) * nspec + ((long long)x * n1 + y) * H + k, res2[(c2 * H + k) * n1 + y]);
   }
   if (want_norm || update_p) {
     const double s = block_sum(nrm, L.red);
@@ -998,26 +1032,69 @@ __global__ void __launch_bounds__(512) k_slab_inv(const RveDev* __restrict__ rvs
   const int ri = find_rve(rvs, nrve, P_ZI, tile);
   if (ri < 0) return;
   const RveDev& rv = rvs[ri];
-  const int dn = done_peek(check_done, rv.cg);
-  const int n1 = rv.n1, n2 = rv.n2, H = rv.H;
-  const long long nvox = rv.nvox, nspec = rv.nspec;
-  const int x = tile / 3, pr = tile - 3 * (tile / 3);
+  // descriptor fields, all loaded in one batch (the empty asm keeps the
+  // compiler from deferring any of them past the first use of another)
+  int n1 = rv.n1, n2 = rv.n2, H = rv.H, fold = rv.fold, ntz = rv.tiles[P_ZF];
+  long long nspec = rv.nspec;
+  const long long nvox = rv.nvox;
+  const cx<T>* specp = (const cx<T>*)rv.spec;
+  CgState* cg = rv.cg;
+  const double* part = rv.partial;
   SlabLds<T> L(smem, n1max, n2max, rv.ax[2], rv.ax[1]);
-  if (check_done && done_publish(dn)) return;
+  __asm__ volatile(""
+                   : "+s"(n1), "+s"(n2), "+s"(H), "+s"(fold), "+s"(ntz), "+s"(nspec), "+s"(specp), "+s"(cg),
+                     "+s"(part), "+s"(L.az.M), "+s"(L.az.g_tw), "+s"(L.ay.M), "+s"(L.ay.g_tw)
+                   :
+                   : "memory");
+  const FFTG_GLOBAL cx<T>* const spec = gmem(specp);
+  const int x = tile / 3, pr = tile - 3 * (tile / 3);
+  const long long v0 = (long long)x * n1 * n2;
+  const int npl = n1 * n2;
+  const int c0 = 2 * pr, c1 = 2 * pr + 1;
   const bool cg_out = out_mode == OUT_CG || out_mode == OUT_CG_TIMING;
-  // this thread's share of the p.(C:p) partials, loaded with the spectrum
-  const double pa = (cg_out && rv.fold) ? thread_partials(rv.partial, rv.tiles[P_ZF]) : 0.0;
-  const cx<T>* spec = (const cx<T>*)rv.spec;
+  // Stop flag as in the z pass: the CG form over one RVE decides at the
+  // alpha barrier, otherwise it is tested before any load.
+  const bool late = cg_out && launch_single(nrve);
+  if (check_done && !late && *gmem(&cg->done)) return;
+  // Loads in program order before anything that waits: tables, the
+  // spectrum, the CG scalars, the partials, this thread's first voxel.
+  const AxisFetch<T> tfz = axis_lds_fetch<T>(L.az);
+  const AxisFetch<T> tfy = axis_lds_fetch<T>(L.ay);
   const FastDiv fH(H), fn1(n1), fn2(n2);
-  for (int t = threadIdx.x; t < 2 * n1 * H; t += blockDim.x) {
-    const int cy = fH.div(t);
-    const int k = t - cy * H;
-    const int c2 = fn1.div(cy), y = cy - c2 * n1;
-    L.b0[(c2 * H + k) * n1 + y] = spec[(2 * pr + c2) * nspec + ((long long)x * n1 + y) * H + k];
+  lds_gather<4>(
+      L.b0, spec, 2 * n1 * H,
+      [=](int t) {
+        const int cy = fH.div(t);
+        const int k = t - cy * H;
+        const int c2 = fn1.div(cy), y = cy - c2 * n1;
+        return (2 * pr + c2) * nspec + ((long long)x * n1 + y) * H + k;
+      },
+      [=](int t) {
+        const int cy = fH.div(t);
+        const int k = t - cy * H;
+        const int c2 = fn1.div(cy), y = cy - c2 * n1;
+        return (c2 * H + k) * n1 + y;
+      });
+  const CgPeek pk = cg_peek(cg);
+  const double pa = (cg_out && fold) ? thread_partials(part, ntz) : 0.0;
+  double xv0[2], rv0[2], pv0[2];
+  if (cg_out) {
+    const long long v = v0 + min((int)threadIdx.x, npl - 1);
+    const FFTG_GLOBAL double* gx = gmem((const double*)rv.buf[R_X]);
+    const FFTG_GLOBAL double* gr = gmem((const double*)rv.buf[R_R]);
+    const FFTG_GLOBAL double* gp = gmem((const double*)rv.buf[p_role]);
+    xv0[0] = gx[c0 * nvox + v];
+    xv0[1] = gx[c1 * nvox + v];
+    rv0[0] = gr[c0 * nvox + v];
+    rv0[1] = gr[c1 * nvox + v];
+    pv0[0] = gp[c0 * nvox + v];
+    pv0[1] = gp[c1 * nvox + v];
   }
+  axis_lds_store<T>(L.az, tfz);
+  axis_lds_store<T>(L.ay, tfy);
   double alpha = 0.0;
   if (cg_out) {
-    if (!cg_alpha(rv, tile, cg_peek(rv.cg), false, pa, out_mode == OUT_CG_TIMING, L.red, alpha)) return;
+    if (!cg_alpha(rv, tile, pk, check_done && late, pa, out_mode == OUT_CG_TIMING, L.red, alpha)) return;
   } else {
     __syncthreads();
   }
@@ -1040,32 +1117,37 @@ __global__ void __launch_bounds__(512) k_slab_inv(const RveDev* __restrict__ rvs
   }
   __syncthreads();
   cx<T>* res2 = line_fft<1, T, BIG>(oth, res, n2, n1, L.az, L.dc);
-  const long long v0 = (long long)x * n1 * n2;
-  const int c0 = 2 * pr, c1 = 2 * pr + 1;
   double dot = 0.0;
   if (cg_out) {
     // x += alpha p, r -= alpha G:(C:p) on the tile's two components, partials of r.r
-    double* __restrict__ xx = (double*)rv.buf[R_X];
-    double* __restrict__ rr = (double*)rv.buf[R_R];
-    const double* __restrict__ p = (const double*)rv.buf[p_role];
-    for (int t = threadIdx.x; t < n1 * n2; t += blockDim.x) {
+    FFTG_GLOBAL double* __restrict__ xx = gmem((double*)rv.buf[R_X]);
+    FFTG_GLOBAL double* __restrict__ rr = gmem((double*)rv.buf[R_R]);
+    const FFTG_GLOBAL double* __restrict__ p = gmem((const double*)rv.buf[p_role]);
+    auto update = [&](int t, const double* xv, const double* rv2, const double* pv) {
       const long long v = v0 + t;
       const cx<T> w = res2[t];
-      const long long i0 = c0 * nvox + v, i1 = c1 * nvox + v;
-      const double r0 = rr[i0] - alpha * double(w.re), r1 = rr[i1] - alpha * double(w.im);
-      xx[i0] += alpha * p[i0];
-      xx[i1] += alpha * p[i1];
-      rr[i0] = r0;
-      rr[i1] = r1;
+      const double r0 = rv2[0] - alpha * double(w.re), r1 = rv2[1] - alpha * double(w.im);
+      xx[c0 * nvox + v] = xv[0] + alpha * pv[0];
+      xx[c1 * nvox + v] = xv[1] + alpha * pv[1];
+      rr[c0 * nvox + v] = r0;
+      rr[c1 * nvox + v] = r1;
       dot += r0 * r0 + r1 * r1;
+    };
+    if ((int)threadIdx.x < npl) update(threadIdx.x, xv0, rv0, pv0);
+    for (int t = threadIdx.x + blockDim.x; t < npl; t += blockDim.x) {
+      const long long v = v0 + t;
+      const double xv[2] = {xx[c0 * nvox + v], xx[c1 * nvox + v]};
+      const double rv2[2] = {rr[c0 * nvox + v], rr[c1 * nvox + v]};
+      const double pv[2] = {p[c0 * nvox + v], p[c1 * nvox + v]};
+      update(t, xv, rv2, pv);
     }
     const double s = block_sum(dot, L.red);
     put_partials(&s, 1, rv.partial_rr, rv.tiles[P_ZI], tile);
     return;
   } else if (out_mode == OUT_RESIDUAL) {
-    double* rr = (double*)rv.buf[R_R];
-    double* pp = (double*)rv.buf[R_P];
-    double* xx = (double*)rv.buf[R_X];
+    FFTG_GLOBAL double* rr = gmem((double*)rv.buf[R_R]);
+    FFTG_GLOBAL double* pp = gmem((double*)rv.buf[R_P]);
+    FFTG_GLOBAL double* xx = gmem((double*)rv.buf[R_X]);
     for (int t = threadIdx.x; t < n1 * n2; t += blockDim.x) {
       const long long v = v0 + t;
       const cx<T> w = res2[t];
@@ -1079,7 +1161,7 @@ __global__ void __launch_bounds__(512) k_slab_inv(const RveDev* __restrict__ rvs
       dot += a0 * a0 + a1 * a1;
     }
   } else {
-    T* out = (T*)rv.buf[out_role];
+    FFTG_GLOBAL T* out = gmem((T*)rv.buf[out_role]);
     for (int t = threadIdx.x; t < n1 * n2; t += blockDim.x) {
       const long long v = v0 + t;
       const cx<T> w = res2[t];

@@ -13,6 +13,8 @@
 // (DFT_forward_inverse); normalisation is left to the caller.
 #pragma once
 
+#include <type_traits>
+
 #include "fftg_internal.h"
 
 namespace fftg {
@@ -382,17 +384,34 @@ __device__ cx<T>* line_fft(cx<T>* line, cx<T>* scratch, int ld, int nl, const Ax
       const cx<T>* x = line + l * ld;
       const cx<T> x0 = x[0];
       T ar = x0.re, ai = x0.im, cr = T(0), ci = T(0);  // A and C = -B = sum_j d_j (-sin theta)
-      int idx = 0;
+      if (std::is_same<T, double>::value) {
+        // FP64: the roots w^(jk) by recurrence in registers from w^k (one
+        // table read; the error after (N-1)/2 steps stays near 1e-15), so
+        // that the loop waits only for the inputs
+        const cx<T> wk = P.tw[k];
+        cx<T> w = wk;
 #pragma unroll 4
-      for (int j = 1; j < Hn; ++j) {
-        idx += k;
-        idx -= (idx >= N) ? N : 0;
-        const cx<T> w = P.tw[idx];
-        const cx<T> a = x[j], b = x[N - j];
-        ar += (a.re + b.re) * w.re;
-        ai += (a.im + b.im) * w.re;
-        cr += (a.re - b.re) * w.im;
-        ci += (a.im - b.im) * w.im;
+        for (int j = 1; j < Hn; ++j) {
+          const cx<T> a = x[j], b = x[N - j];
+          ar += (a.re + b.re) * w.re;
+          ai += (a.im + b.im) * w.re;
+          cr += (a.re - b.re) * w.im;
+          ci += (a.im - b.im) * w.im;
+          w = cmul(w, wk);
+        }
+      } else {
+        int idx = 0;
+#pragma unroll 4
+        for (int j = 1; j < Hn; ++j) {
+          idx += k;
+          idx -= (idx >= N) ? N : 0;
+          const cx<T> w = P.tw[idx];
+          const cx<T> a = x[j], b = x[N - j];
+          ar += (a.re + b.re) * w.re;
+          ai += (a.im + b.im) * w.re;
+          cr += (a.re - b.re) * w.im;
+          ci += (a.im - b.im) * w.im;
+        }
       }
       // i B = -i C = (C.im, -C.re)
       const T pr = DIR > 0 ? ar + ci : ar - ci;

@@ -94,9 +94,11 @@ def test_laminate_matches_closed_form_and_oracle():
 
 
 @pytest.mark.parametrize("slab", ["0", "2"])
-@pytest.mark.parametrize("shape,seed", [((9, 7, 5), 21), ((15, 15, 15), 3), ((11, 13, 7), 5)])
+@pytest.mark.parametrize("shape,seed", [((9, 7, 5), 21), ((15, 15, 15), 3), ((11, 13, 7), 5), ((3, 255, 3), 9)])
 def test_lockstep_parity_with_oracle(shape, seed, slab, monkeypatch):
-    """FFTG_SLAB=0 runs the five-pass product, 2 the fused z-y slab passes."""
+    """FFTG_SLAB=0 runs the five-pass product, 2 the fused z-y slab passes.
+    The thin 3 x 255 x 3 grid has many z tiles and few y tiles (the y pass's
+    group sums of the CG partials then take several rounds per tile)."""
     print("solve lockstep", shape, "slab", slab, flush=True)
     monkeypatch.setenv("FFTG_SLAB", slab)
     w = synth.small_random(shape, 0.35, seed, E_eq=0.01, n_inc=4)

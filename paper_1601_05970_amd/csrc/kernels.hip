@@ -87,6 +87,41 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
   return r;
 }
 
+// The same total, formed identically by every thread after a single barrier
+// (per-wave shuffle sums in sh[w], added in the same order as block_sum).
+// Thread 0's flag travels in sh[8] and is returned to every thread: the
+// one value that another tile of the launch may change while this one runs.
+// The caller must not write sh[0..8] again before another barrier.
+__device__ __forceinline__ double block_total(double v, int flag0, double* sh, int& flag) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (lane == 0) sh[w] = v;
+  if (threadIdx.x == 0) sh[8] = flag0 ? 1.0 : 0.0;
+  __syncthreads();
+  const int nw = (blockDim.x + 63) >> 6;
+  double r = 0.0;
+  for (int i = 0; i < nw; ++i) r += sh[i];
+  flag = sh[8] != 0.0;
+  return r;
+}
+
+// block_sum for the last reduction of a kernel: valid in thread 0, one
+// barrier (no later use of sh to protect).
+__device__ __forceinline__ double block_sum_last(double v, double* sh) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (lane == 0) sh[w] = v;
+  __syncthreads();
+  double r = 0.0;
+  if (threadIdx.x == 0) {
+    const int nw = (blockDim.x + 63) >> 6;
+    for (int i = 0; i < nw; ++i) r += sh[i];
+  }
+  return r;
+}
+
 // Stores a tile's partial sums (nv values held by thread 0) at
 // partial[i * ntiles + tile].  The per-RVE totals are formed by k_finalize,
 // launched after the producer on the same stream: the kernel boundary makes
@@ -199,23 +234,9 @@ struct TileLds {
   }
 };
 
-// Start of a CG iteration in the kernel that forms p <- r + beta p (dn: the
-// stop flag as peeked by thread 0 at kernel start; the decision reaches every
-// thread through LDS).  With
-// the scalar steps folded (rv.fold), every tile totals the r.r partials of
-// the last vector update (same order in each tile, so the same value),
-// applies the stopping test and forms beta; tile 0 publishes the state.
-// Other tiles of the launch read only rr_prev, iters and status: tile 0
-// writes no rr_prev or iters, and it writes CG_BREAKDOWN, the one status
-// value tested, only where status already holds it (a breakdown is found by
-// the vector update, which must not write the stop flag that its own tiles
-// read; the solve stops here).  Returns
-// false when the solve has stopped (the tile exits).  red needs 10 doubles;
-// called by the whole workgroup.  PU_TIMING does the same loads and sums
-// with beta = 0 and no state.
 // CG scalars read at the start of an iteration, loaded by every thread with
-// the kernel's other loads and used by thread 0 only (no thread waits for
-// them on its own).  The address passes through a vector register (an empty
+// the kernel's other loads and used after the step's barrier, when the loads
+// have landed.  The address passes through a vector register (an empty
 // asm): values loaded from a uniform address are otherwise moved to scalar
 // registers, and so waited for, right where they are loaded.
 struct CgPeekB {
@@ -231,6 +252,21 @@ __device__ __forceinline__ CgPeekB cg_peek_b(CgState* cg) {
   return CgPeekB{g->done, g->iters, g->status, g->force, g->max_iter, g->rr_prev, g->target2, g->beta};
 }
 
+
+// Start of a CG iteration in the kernel that forms p <- r + beta p.  With
+// the scalar steps folded (rv.fold), every tile totals the r.r partials of
+// the last vector update (same order in each tile, so the same value),
+// applies the stopping test and forms beta; tile 0 publishes the state.
+// Other tiles of the launch read only rr_prev, iters and status: tile 0
+// writes no rr_prev or iters, and it writes CG_BREAKDOWN, the one status
+// value tested, only where status already holds it (a breakdown is found by
+// the vector update, which must not write the stop flag that its own tiles
+// read; the solve stops here).  The stop flag itself may change under the
+// launch, so only thread 0's copy counts (shared with the total through
+// LDS); every thread then takes the same decision.  Returns false when the
+// solve has stopped (the tile exits).  red needs 9 doubles; called by the
+// whole workgroup.  PU_TIMING does the same loads and sums with beta = 0 and
+// no state.
 // (dn: the stop flag of this launch's test, as thread 0 holds it; pk: the
 // scalars above; pa: this thread's share of the r.r partials, loaded by the
 // caller with its data when folded.)
@@ -238,52 +274,43 @@ __device__ bool cg_begin_iter(const RveDev& rv, int tile, int dn, const CgPeekB&
                               double* red, double& beta) {
   CgState* cg = rv.cg;
   const bool timing = mode == PU_TIMING;
-  // Every decision that depends on the CG scalars is thread 0's, shared
-  // through LDS: a branch of all threads on them would make each thread wait
-  // for their loads as soon as they are issued.
-  const double rr = rv.fold ? block_sum(pa, red) : 0.0;
-  if (threadIdx.x == 0) {
-    if (dn) {
-      red[8] = 1.0;  // stopped before this launch: no state change
-    } else if (timing) {
-      red[8] = 0.0;
-      red[9] = 0.0 * rr;
-    } else if (pk.iters == 0) {
-      red[8] = 0.0;  // iteration 0: the residual pass has set p = r
-      red[9] = 0.0;
-    } else if (!rv.fold) {
-      red[8] = 0.0;  // k_finalize took the step
-      red[9] = pk.beta;
+  // One barrier: every thread forms the same r.r total and takes the same
+  // decision from it and from the CG scalars (none of which this launch
+  // changes in a way the tests below can see), except the stop flag, which
+  // is thread 0's copy.  The branches come after the loads have landed.
+  int stopped;
+  const double rr = block_total(rv.fold ? pa : 0.0, dn, red, stopped);
+  beta = 0.0;
+  if (stopped) return false;  // stopped before this launch: no state change
+  if (timing || pk.iters == 0) return true;  // iteration 0: the residual pass has set p = r
+  if (!rv.fold) {
+    beta = pk.beta;  // k_finalize took the step
+    return true;
+  }
+  const int it = pk.iters;
+  int st = CG_RUNNING;
+  if (pk.status == CG_BREAKDOWN) {
+    st = CG_BREAKDOWN;
+  } else if (pk.force >= 0) {
+    if (it >= pk.force) st = CG_FORCED;
+  } else if (rr <= pk.target2) {
+    st = CG_CONVERGED;
+  } else if (it >= pk.max_iter) {
+    st = CG_MAXITER;
+  }
+  const double b = rr / pk.rr_prev;
+  if (tile == 0 && threadIdx.x == 0) {
+    cg->rr = rr;
+    cg->rr_new = rr;
+    cg->status = st;
+    if (st != CG_RUNNING) {
+      __hip_atomic_store(&cg->done, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     } else {
-      const int it = pk.iters;
-      int st = CG_RUNNING;
-      if (pk.status == CG_BREAKDOWN) {
-        st = CG_BREAKDOWN;
-      } else if (pk.force >= 0) {
-        if (it >= pk.force) st = CG_FORCED;
-      } else if (rr <= pk.target2) {
-        st = CG_CONVERGED;
-      } else if (it >= pk.max_iter) {
-        st = CG_MAXITER;
-      }
-      const double b = rr / pk.rr_prev;
-      red[8] = st != CG_RUNNING ? 1.0 : 0.0;
-      red[9] = b;
-      if (tile == 0) {
-        cg->rr = rr;
-        cg->rr_new = rr;
-        cg->status = st;
-        if (st != CG_RUNNING) {
-          __hip_atomic_store(&cg->done, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        } else {
-          cg->beta = b;
-        }
-      }
+      cg->beta = b;
     }
   }
-  __syncthreads();
-  if (red[8] != 0.0) return false;
-  beta = red[9];
+  if (st != CG_RUNNING) return false;
+  beta = b;
   return true;
 }
 
@@ -501,7 +528,7 @@ __global__ void __launch_bounds__(256) k_zfwd(const RveDev* __restrict__ rvs, in
     gstore(spec + (2 * pr + 1) * nspec + o, B);
   }
   if (want_norm || update_p) {
-    const double s = block_sum(nrm, L.red);
+    const double s = block_sum_last(nrm, L.red);
     put_partials(&s, 1, rv.partial, rv.tiles[P_ZF], tile);
   }
 }
@@ -645,6 +672,19 @@ __global__ void __launch_bounds__(256) k_xpass(const RveDev* __restrict__ rvs, i
   }
 }
 
+// CG scalars read by the vector update, loaded by every thread with the
+// kernel's other loads (none is written during the launch but the stop
+// flag, of which thread 0's copy counts) and used after the step's barrier,
+// when the loads have landed.
+struct CgPeek {
+  int done;
+  double rr, alpha;
+};
+__device__ __forceinline__ CgPeek cg_peek(CgState* cg) {
+  const FFTG_GLOBAL CgState* g = cg_vaddr(cg);
+  return CgPeek{g->done, g->rr, g->alpha};
+}
+
 // alpha = r.r / p.(C:p) for the CG vector update of the inverse z pass.  p is
 // compatible (a combination of outputs of G) and G is an orthogonal
 // projection, so p.(C:p) = (G p).(C:p) = p.G:(C:p) = p.Ap: the forward pass
@@ -655,67 +695,40 @@ __global__ void __launch_bounds__(256) k_xpass(const RveDev* __restrict__ rvs, i
 // the other tiles read only rr, which no tile of this launch writes.  A
 // breakdown (p.(C:p) <= 0 or not finite) makes every tile exit unchanged and
 // is recorded in status only, for the next forward pass to stop the solve:
-// the stop flag is read by all threads of these tiles without a barrier.
+// the stop flag is read by these tiles without a barrier between tiles.
 // Not folded: k_finalize formed alpha (and the stop flag, before this
-// launch).  dn is the stop flag as thread 0 loaded it at kernel start (0 when
-// the caller has tested it already); the decision reaches every thread
-// through LDS.  Returns false when the tile must exit.  Called by the whole
-// workgroup (its barriers also publish the caller's LDS writes).  With
-// timing, the same loads and sums give alpha = 0 and touch no state.
-// CG scalars read by the vector update, loaded by every thread with the
-// kernel's other loads (none is written during the launch) and used by
-// thread 0 only, so that no thread waits for them on its own.
-struct CgPeek {
-  int done;
-  double rr, alpha;
-};
-__device__ __forceinline__ CgPeek cg_peek(CgState* cg) {
-  const FFTG_GLOBAL CgState* g = cg_vaddr(cg);
-  return CgPeek{g->done, g->rr, g->alpha};
-}
-
+// launch).  With check_done the stop flag counts, as thread 0 loaded it.
+// Returns false when the tile must exit (the same answer in every thread).
+// Called by the whole workgroup (its barrier also publishes the caller's
+// LDS writes).  With timing, the same loads and sums give alpha = 0 and
+// touch no state.
 __device__ bool cg_alpha(const RveDev& rv, int tile, const CgPeek& pk, bool check_done, double pa, bool timing,
                          double* red, double& alpha) {
   CgState* cg = rv.cg;
-  const int dn = check_done ? pk.done : 0;
+  // one barrier, every thread takes the same decision (as cg_begin_iter)
+  int stopped;
+  const double pap = block_total(rv.fold ? pa : 0.0, check_done ? pk.done : 0, red, stopped);
   alpha = 0.0;
+  if (stopped) return false;  // stopped before this launch: no state change
   if (!rv.fold) {
-    if (threadIdx.x == 0) {
-      red[8] = dn ? 1.0 : 0.0;
-      red[9] = timing ? 0.0 : pk.alpha;
-    }
-    __syncthreads();
-    if (red[8] != 0.0) return false;
-    alpha = red[9];
+    if (!timing) alpha = pk.alpha;
     return true;
   }
-  const double pap = block_sum(pa, red);
-  if (threadIdx.x == 0) {
-    if (dn) {
-      red[8] = 1.0;  // stopped before this launch: no state change
-    } else if (timing) {
-      red[8] = 0.0;
-      red[9] = 0.0 * pap;
+  if (timing) return true;
+  const double rr = pk.rr;
+  const bool brk = !(pap > 0.0) || !(pap < INFINITY);
+  if (tile == 0 && threadIdx.x == 0) {
+    cg->pAp = pap;
+    if (brk) {
+      cg->status = CG_BREAKDOWN;
     } else {
-      const double rr = pk.rr;
-      const bool brk = !(pap > 0.0) || !(pap < INFINITY);
-      red[8] = brk ? 1.0 : 0.0;
-      red[9] = rr / pap;
-      if (tile == 0) {
-        cg->pAp = pap;
-        if (brk) {
-          cg->status = CG_BREAKDOWN;
-        } else {
-          cg->alpha = rr / pap;
-          cg->rr_prev = rr;
-          cg->iters += 1;
-        }
-      }
+      cg->alpha = rr / pap;
+      cg->rr_prev = rr;
+      cg->iters += 1;
     }
   }
-  __syncthreads();
-  if (red[8] != 0.0) return false;
-  alpha = red[9];
+  if (brk) return false;
+  alpha = rr / pap;
   return true;
 }
 
@@ -852,7 +865,7 @@ __global__ void __launch_bounds__(256) k_zinv(const RveDev* __restrict__ rvs, in
       }
       update(t, xv, rv6, pv);
     }
-    const double s = block_sum(dot, L.red);
+    const double s = block_sum_last(dot, L.red);
     put_partials(&s, 1, rv.partial_rr, rv.tiles[P_ZI], tile);
     return;
   } else if (out_mode == OUT_RESIDUAL) {
@@ -891,7 +904,7 @@ __global__ void __launch_bounds__(256) k_zinv(const RveDev* __restrict__ rvs, in
     }
     return;
   }
-  const double s = block_sum(dot, L.red);
+  const double s = block_sum_last(dot, L.red);
   put_partials(&s, 1, rv.partial, rv.tiles[P_ZI], tile);
 }
 
@@ -1019,7 +1032,7 @@ __global__ void __launch_bounds__(512) k_slab_fwd(const RveDev* __restrict__ rvs
     gstore(spec + (2 * pr + c2) * nspec + ((long long)x * n1 + y) * H + k, res2[(c2 * H + k) * n1 + y]);
   }
   if (want_norm || update_p) {
-    const double s = block_sum(nrm, L.red);
+    const double s = block_sum_last(nrm, L.red);
     put_partials(&s, 1, rv.partial, rv.tiles[P_ZF], tile);
   }
 }
@@ -1141,7 +1154,7 @@ __global__ void __launch_bounds__(512) k_slab_inv(const RveDev* __restrict__ rvs
       const double pv[2] = {p[c0 * nvox + v], p[c1 * nvox + v]};
       update(t, xv, rv2, pv);
     }
-    const double s = block_sum(dot, L.red);
+    const double s = block_sum_last(dot, L.red);
     put_partials(&s, 1, rv.partial_rr, rv.tiles[P_ZI], tile);
     return;
   } else if (out_mode == OUT_RESIDUAL) {
@@ -1170,7 +1183,7 @@ __global__ void __launch_bounds__(512) k_slab_inv(const RveDev* __restrict__ rvs
     }
     return;
   }
-  const double s = block_sum(dot, L.red);
+  const double s = block_sum_last(dot, L.red);
   put_partials(&s, 1, rv.partial, rv.tiles[P_ZI], tile);
 }
 

@@ -318,13 +318,6 @@ __device__ __forceinline__ void axis_lds_store(const AxisLds<T>& A, const AxisFe
   }
 }
 
-// Setup and whole copy at once.
-template <class T>
-__device__ __forceinline__ void load_axis_lds(const AxisDev& P, char* base, AxisLds<T>& A) {
-  axis_lds_setup<T>(P, base, A);
-  axis_lds_store<T>(A, axis_lds_fetch<T>(A));
-}
-
 // Runs the Stockham chain of P on a (result ends in a; buffers are swapped).
 // BIG = 0 compiles only the radix 2, 3, 4, 5, 7, 9 codelets (lower register
 // use); BIG = 1 adds 11, 13, 17.

@@ -160,17 +160,10 @@ __device__ double sum_partials(const double* __restrict__ p, int n, double* sh) 
   return block_sum(thread_partials(p, n), sh);
 }
 
-// The CG stop flag, read once per workgroup and shared through LDS: in the
-// kernels that apply a folded scalar step, tile 0 may set it while other
-// tiles of the same launch start, and all threads of a tile must agree.
-// In two halves, so that the flag's load (issued by thread 0 at kernel
-// start) overlaps the loads of the axis tables and partial sums that follow
-// it: peek returns the raw flag in thread 0, publish shares it through LDS
-// (and its barrier also publishes the tables).
-__device__ __forceinline__ int done_peek(int check_done, CgState* cg) {
-  return (check_done && threadIdx.x == 0) ? __hip_atomic_load(&cg->done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
-                                          : 0;
-}
+// Thread 0's copy of the CG stop flag, shared through LDS with the whole
+// workgroup (its barrier also publishes the caller's LDS writes): in the
+// kernels that apply a folded scalar step, tile 0 may set the flag while
+// other tiles of the same launch start, and all threads of a tile must agree.
 __device__ __forceinline__ int done_publish(int v) {
   __shared__ int s_done2;
   if (threadIdx.x == 0) s_done2 = v;
@@ -222,11 +215,10 @@ struct TileLds {
   cx<T>* scratch;
   cx<T>* dc;
   double* red;
-  // With defer, the tables are only carved out: the kernel copies them with
+  // The tables are only carved out: the kernel copies them with
   // axis_lds_fetch / axis_lds_store around its own loads.
-  __device__ TileLds(char* base, int nl, int ld, const AxisDev& P, int ldmax, bool defer = false) {
-    if (defer) axis_lds_setup<T>(P, base, ax);
-    else load_axis_lds<T>(P, base, ax);
+  __device__ TileLds(char* base, int nl, int ld, const AxisDev& P, int ldmax) {
+    axis_lds_setup<T>(P, base, ax);
     line = reinterpret_cast<cx<T>*>(base + axis_lds_bytes<T>(ldmax));
     scratch = line + (size_t)nl * ld;
     dc = scratch + (size_t)nl * ld;
@@ -400,18 +392,6 @@ __device__ __forceinline__ double voxel_compute(const VoxIn<T>& vi, long long v,
   return d;
 }
 
-// Both at once (kernels with nothing to overlap).
-template <class T>
-__device__ __forceinline__ double voxel_tau(const RveDev& rv, long long v, int in_mode, const double* __restrict__ in,
-                                          int update_p, double beta, const double* __restrict__ rres,
-                                          const double* p_old, double* p_new, int own_lo, int own_hi,
-                                          int tan_mode, const MatDev* __restrict__ mats, T tau[6]) {
-  VoxIn<T> vi;
-  voxel_load<T>(v, rv.nvox, in_mode, in, update_p, rres, p_old, tan_mode, rv.tang, rv.phase, vi);
-  return voxel_compute<T>(vi, v, rv.nvox, in_mode, rv.dE, update_p, beta, p_new, own_lo, own_hi, tan_mode, mats,
-                          tau);
-}
-
 // Material table of a launch member into LDS, in two halves like the axis
 // tables (threads past n fetch and store entry n - 1 again, so that no load
 // sits behind a branch).
@@ -448,7 +428,7 @@ __global__ void __launch_bounds__(256) k_zfwd(const RveDev* __restrict__ rvs, in
   const uint8_t* phase = rv.phase;
   const double* prr = rv.partial_rr;
   const MatDev* mats = rv.mats;
-  TileLds<T> L(smem, 3 * rows_per_tile, n2, rv.ax[2], ldmax, true);
+  TileLds<T> L(smem, 3 * rows_per_tile, n2, rv.ax[2], ldmax);
   __asm__ volatile(""
                    : "+s"(n0), "+s"(n1), "+s"(n2), "+s"(H), "+s"(nph), "+s"(fold), "+s"(nti), "+s"(nvox), "+s"(cg),
                      "+s"(in), "+s"(rres), "+s"(pw), "+s"(tang), "+s"(phase), "+s"(prr), "+s"(L.ax.M),
@@ -548,7 +528,7 @@ __global__ void __launch_bounds__(256) k_ypass(const RveDev* __restrict__ rvs, i
   const long long nspec = rv.nspec;
   cx<T>* const spec = (cx<T>*)rv.spec;
   CgState* const cg = rv.cg;
-  TileLds<T> L(smem, lines_per_tile, n1, rv.ax[1], ldmax, true);
+  TileLds<T> L(smem, lines_per_tile, n1, rv.ax[1], ldmax);
   __asm__ volatile("" : "+s"(n0), "+s"(n1), "+s"(H) : : "memory");
   const int ld = n1;
   const int nhb = (H + lines_per_tile - 1) / lines_per_tile;
@@ -604,7 +584,7 @@ __global__ void __launch_bounds__(256) k_xpass(const RveDev* __restrict__ rvs, i
   const long long nspec = rv.nspec, nvox = rv.nvox;
   FFTG_GLOBAL cx<T>* const spec = gmem((cx<T>*)rv.spec);
   CgState* const cg = rv.cg;
-  TileLds<T> L(smem, 6 * lines_per_tile, n0, rv.ax[0], ldmax, true);
+  TileLds<T> L(smem, 6 * lines_per_tile, n0, rv.ax[0], ldmax);
   __asm__ volatile("" : "+s"(n0), "+s"(n1), "+s"(n2), "+s"(H) : : "memory");
   const int nhb = (H + lines_per_tile - 1) / lines_per_tile;
   const int i1 = tile / nhb;
@@ -750,7 +730,7 @@ __global__ void __launch_bounds__(256) k_zinv(const RveDev* __restrict__ rvs, in
   CgState* cg = rv.cg;
   int fold = rv.fold, ntz = rv.tiles[P_ZF];
   const double* part = rv.partial;
-  TileLds<T> L(smem, 3 * rows_per_tile, n2, rv.ax[2], ldmax, true);
+  TileLds<T> L(smem, 3 * rows_per_tile, n2, rv.ax[2], ldmax);
   __asm__ volatile(""
                    : "+s"(n0), "+s"(n1), "+s"(n2), "+s"(H), "+s"(nspec), "+s"(specp), "+s"(cg), "+s"(fold),
                      "+s"(ntz), "+s"(part), "+s"(L.ax.M), "+s"(L.ax.g_tw)

@@ -1199,10 +1199,36 @@ static double time_ms(hipStream_t s, int reps, F&& launch) {
   return ms;
 }
 
+// FFTG_TILES="rows:threads_z:lines_y:threads_y:lines_x:threads_x" pins the
+// tiles of the five passes instead of timing candidates (reproducible runs,
+// tile studies); values outside the autotuner's candidate sets, or tiles
+// whose LDS exceeds the budget, are ignored.
+static bool pinned_tiles(LaunchCfg& c, int n0, int n1, int n2) {
+  const char* s = getenv("FFTG_TILES");
+  if (!s || !*s) return false;
+  int v[6];
+  if (sscanf(s, "%d:%d:%d:%d:%d:%d", &v[0], &v[1], &v[2], &v[3], &v[4], &v[5]) != 6) return false;
+  auto thr_ok = [](int t) { return t == 64 || t == 128 || t == 256; };
+  auto rows_ok = [](int r) { return r == 1 || r == 2 || r == 3 || r == 4 || r == 6 || r == 8; };
+  auto ly_ok = [](int l) { return l == 1 || l == 2 || l == 4 || l == 8 || l == 12 || l == 16; };
+  if (!rows_ok(v[0]) || !thr_ok(v[1]) || !ly_ok(v[2]) || !thr_ok(v[3]) || !rows_ok(v[4]) || !thr_ok(v[5]))
+    return false;
+  const size_t budget = (size_t)env_long("FFTG_LDS_KB", 128, 1) * 1024;
+  if (lds_z(0, v[0], n2) > budget || lds_y(0, v[2], n1) > budget || lds_x(0, v[4], n0) > budget) return false;
+  c.rows_per_tile = v[0];
+  c.threads_z = v[1];
+  c.lines_y = v[2];
+  c.threads_y = v[3];
+  c.lines_x = v[4];
+  c.threads_x = v[5];
+  c.slab = 0;
+  return true;
+}
+
 static fftg_status group_autotune(Group& g) {
   const GridSum gs = group_gridsum(g);
   LaunchCfg best = choose_cfg(gs);
-  if (env_long("FFTG_AUTOTUNE", 1) != 1) {
+  if (pinned_tiles(best, gs.n0, gs.n1, gs.n2) || env_long("FFTG_AUTOTUNE", 1) != 1) {
     group_set_cfg(g, best);
     return FFTG_OK;
   }

@@ -44,6 +44,10 @@ def test_host_only_calls(lib):
     assert 0 < f32 < f64 < 2 ** 31
     assert fftg.fftg_footprint_bytes(0, 1, 1, 0) == 0
     assert lib.fftg_last_error() is not None
+    # sampled kernel timing: bad kernel ids and strides are rejected
+    for kid, every in ((fftg.FFTG_KERNEL_ZFWD, 0), (-1, 1), (8, 1)):
+        with pytest.raises(fftg.FFTGError):
+            fftg.fftg_profiler_start_every(kid, every)
 
 
 def test_struct_layouts_match_header():

@@ -42,6 +42,24 @@ def test_projection_matches_oracle(shape):
     assert rel_err(got, ref) < 1e-12
 
 
+def test_sampled_kernel_timing_counts_every_launch():
+    """fftg_profiler_start_every brackets launches 0, every, 2 every, ... of
+    one kind; fftg_profiler_seen counts all of them."""
+    from paper_1601_05970_amd import fftg
+    shape = (15, 15, 15)
+    print("profiler sampling", shape, flush=True)
+    pl = _plan(shape)
+    d_in = to_dev(t2m(synth.random_sym_tensor_field(shape, 4)))
+    d_out = pl.field()
+    pl.apply_GK(d_in, d_out, fftg.FFTG_TANGENT_IDENTITY)  # autotunes before the profiled window
+    fftg.fftg_profiler_start_every(fftg.FFTG_KERNEL_X_PROJ, 3)
+    for _ in range(8):
+        pl.apply_GK(d_in, d_out, fftg.FFTG_TANGENT_IDENTITY)
+    ms, launches, vox = fftg.fftg_profiler_stop()
+    assert fftg.fftg_profiler_seen() == 8
+    assert launches == 3 and ms > 0.0 and vox == 3 * 15 ** 3
+
+
 @pytest.mark.parametrize("slab", ["0", "2"])
 @pytest.mark.parametrize("shape", [(3, 5, 7), (1, 5, 7), (7, 5, 1), (15, 15, 15), (31, 31, 31), (61, 9, 53),
                                    (5, 63, 63), (13, 17, 11)])

@@ -347,11 +347,100 @@ __device__ void run_chain(cx<T>*& a, cx<T>*& b, int ld, int nl, const AxisLds<T>
   }
 }
 
+// Direct DFT of nl odd-length lines from line into scratch (same stride ld):
+// X_k = sum_j x_j w^(jk), w = exp(-+ 2 pi i / N).  With s_j = x_j + x_(N-j)
+// and d_j = x_j - x_(N-j) (j = 1 .. (N-1)/2) and theta = 2 pi j k / N,
+//   X_k = A + DIR i B,  X_(N-k) = A - DIR i B,
+//   A = x_0 + sum_j s_j cos theta,  B = sum_j d_j sin theta,
+// so one thread forms the pair X_k, X_(N-k) (k = 1 .. (N-1)/2; slot 0 forms
+// X_0) with four multiply-adds per j.  The root table holds
+// exp(-i theta) = (cos theta, -sin theta).  FP64 forms the roots w^(jk) by
+// recurrence in registers from w^k (one table read; the error after (N-1)/2
+// steps stays near 1e-15), FP32 reads them from the table.  NF > 0 fixes N at
+// compile time (all steps unrolled); NF == 0 takes N from the plan.  No
+// barrier.
+template <int DIR, class T, int NF>
+__device__ __forceinline__ void direct_dft(const cx<T>* line, cx<T>* scratch, int ld, int nl, const AxisLds<T>& P) {
+  const int N = NF > 0 ? NF : P.M;
+  const int Hn = (N + 1) / 2;
+  const FastDiv fh(Hn);
+  for (int t = threadIdx.x; t < nl * Hn; t += blockDim.x) {
+    const int l = NF > 0 ? t / Hn : fh.div(t);
+    const int k = t - l * Hn;
+    const cx<T>* x = line + l * ld;
+    const cx<T> x0 = x[0];
+    T ar = x0.re, ai = x0.im, cr = T(0), ci = T(0);  // A and C = -B = sum_j d_j (-sin theta)
+    auto step = [&](cx<T> a, cx<T> b, cx<T> w) {
+      ar += (a.re + b.re) * w.re;
+      ai += (a.im + b.im) * w.re;
+      cr += (a.re - b.re) * w.im;
+      ci += (a.im - b.im) * w.im;
+    };
+    if constexpr (NF > 0) {
+      // every LDS read of the line (and, in FP32, of the roots) is issued
+      // before the first multiply-add, so the thread waits once
+      constexpr int H = (NF - 1) / 2;
+      [[maybe_unused]] const cx<T> wk = P.tw[k];  // FP64 only (root recurrence)
+      cx<T> va[H], vb[H];
+#pragma unroll
+      for (int j = 0; j < H; ++j) {
+        va[j] = x[j + 1];
+        vb[j] = x[NF - 1 - j];
+      }
+      if constexpr (std::is_same<T, double>::value) {
+        __builtin_amdgcn_sched_barrier(0);
+        cx<T> w = wk;
+#pragma unroll
+        for (int j = 0; j < H; ++j) {
+          step(va[j], vb[j], w);
+          w = cmul(w, wk);
+        }
+      } else {
+        cx<T> wt[H];
+        int idx = 0;
+#pragma unroll
+        for (int j = 0; j < H; ++j) {
+          idx += k;
+          idx -= (idx >= N) ? N : 0;
+          wt[j] = P.tw[idx];
+        }
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int j = 0; j < H; ++j) step(va[j], vb[j], wt[j]);
+      }
+    } else if (std::is_same<T, double>::value) {
+      const cx<T> wk = P.tw[k];
+      cx<T> w = wk;
+#pragma unroll 4
+      for (int j = 1; j < Hn; ++j) {
+        step(x[j], x[N - j], w);
+        w = cmul(w, wk);
+      }
+    } else {
+      int idx = 0;
+#pragma unroll 4
+      for (int j = 1; j < Hn; ++j) {
+        idx += k;
+        idx -= (idx >= N) ? N : 0;
+        step(x[j], x[N - j], P.tw[idx]);
+      }
+    }
+    // i B = -i C = (C.im, -C.re)
+    const T pr = DIR > 0 ? ar + ci : ar - ci;
+    const T pi = DIR > 0 ? ai - cr : ai + cr;
+    const T mr = DIR > 0 ? ar - ci : ar + ci;
+    const T mi = DIR > 0 ? ai + cr : ai - cr;
+    cx<T>* o = scratch + l * ld;
+    o[k] = cx<T>{pr, pi};
+    if (k > 0) o[N - k] = cx<T>{mr, mi};
+  }
+}
+
 // In-LDS FFT of nl lines of length P.N, DIR = -1 forward, +1 inverse
-// (unnormalised).  line and scratch each hold nl lines of stride ld >= N;
+// (unnormalised); NF > 0 unrolls the direct DFT for lines of NF points.  line and scratch each hold nl lines of stride ld >= N;
 // dc holds nl scratch slots (Rader only).  Returns the buffer holding the
 // result (line or scratch).  Must be called by the whole workgroup.
-template <int DIR, class T, int BIG>
+template <int DIR, class T, int BIG, int NF = 0>
 __device__ cx<T>* line_fft(cx<T>* line, cx<T>* scratch, int ld, int nl, const AxisLds<T>& P, cx<T>* dc) {
   if (P.rader == AX_CHAIN) {
     cx<T>* a = line;
@@ -360,61 +449,17 @@ __device__ cx<T>* line_fft(cx<T>* line, cx<T>* scratch, int ld, int nl, const Ax
     return a;
   }
   if (P.rader == AX_DIRECT) {
-    // X_k = sum_j x_j w^(jk), w = exp(-+ 2 pi i / N), N odd.  With
-    // s_j = x_j + x_(N-j) and d_j = x_j - x_(N-j) (j = 1 .. (N-1)/2) and
-    // theta = 2 pi j k / N,
-    //   X_k = A + DIR i B,  X_(N-k) = A - DIR i B,
-    //   A = x_0 + sum_j s_j cos theta,  B = sum_j d_j sin theta,
-    // so one thread forms the pair X_k, X_(N-k) (k = 1 .. (N-1)/2; slot 0
-    // forms X_0) with four multiply-adds per j.  The root table holds
-    // exp(-i theta) = (cos theta, -sin theta).
-    const int N = P.M;
-    const int Hn = (N + 1) / 2;
-    const FastDiv fh(Hn);
-    for (int t = threadIdx.x; t < nl * Hn; t += blockDim.x) {
-      const int l = fh.div(t);
-      const int k = t - l * Hn;
-      const cx<T>* x = line + l * ld;
-      const cx<T> x0 = x[0];
-      T ar = x0.re, ai = x0.im, cr = T(0), ci = T(0);  // A and C = -B = sum_j d_j (-sin theta)
-      if (std::is_same<T, double>::value) {
-        // FP64: the roots w^(jk) by recurrence in registers from w^k (one
-        // table read; the error after (N-1)/2 steps stays near 1e-15), so
-        // that the loop waits only for the inputs
-        const cx<T> wk = P.tw[k];
-        cx<T> w = wk;
-#pragma unroll 4
-        for (int j = 1; j < Hn; ++j) {
-          const cx<T> a = x[j], b = x[N - j];
-          ar += (a.re + b.re) * w.re;
-          ai += (a.im + b.im) * w.re;
-          cr += (a.re - b.re) * w.im;
-          ci += (a.im - b.im) * w.im;
-          w = cmul(w, wk);
-        }
-      } else {
-        int idx = 0;
-#pragma unroll 4
-        for (int j = 1; j < Hn; ++j) {
-          idx += k;
-          idx -= (idx >= N) ? N : 0;
-          const cx<T> w = P.tw[idx];
-          const cx<T> a = x[j], b = x[N - j];
-          ar += (a.re + b.re) * w.re;
-          ai += (a.im + b.im) * w.re;
-          cr += (a.re - b.re) * w.im;
-          ci += (a.im - b.im) * w.im;
-        }
+    // NF > 0 (kernels built for one line length): that length with every
+    // step unrolled, so that each thread issues all its LDS reads before its
+    // first wait (more registers, hence a separate build)
+    bool done = false;
+    if constexpr (NF > 0) {
+      if (P.M == NF) {
+        direct_dft<DIR, T, NF>(line, scratch, ld, nl, P);
+        done = true;
       }
-      // i B = -i C = (C.im, -C.re)
-      const T pr = DIR > 0 ? ar + ci : ar - ci;
-      const T pi = DIR > 0 ? ai - cr : ai + cr;
-      const T mr = DIR > 0 ? ar - ci : ar + ci;
-      const T mi = DIR > 0 ? ai + cr : ai - cr;
-      cx<T>* o = scratch + l * ld;
-      o[k] = cx<T>{pr, pi};
-      if (k > 0) o[N - k] = cx<T>{mr, mi};
     }
+    if (!done) direct_dft<DIR, T, 0>(line, scratch, ld, nl, P);
     __syncthreads();
     return scratch;
   }

@@ -126,6 +126,7 @@ struct LaunchCfg {
   int slab;            // 1: z and y transforms fused per y-z plane (k_slab_fwd / k_slab_inv)
   int threads_s;       // slab passes
   int big_radix;       // 1 when some axis needs the radix-11/13/17 codelets
+  int direct31;        // bit a (0 x, 1 y, 2 z): every member takes axis a by the 31-point direct DFT
   int xcd_remap;       // 1: blocks mapped to tiles XCD-contiguously
   int n0max, n1max, n2max;  // largest extents of the launch (LDS table sizing)
 };

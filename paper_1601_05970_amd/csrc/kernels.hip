@@ -406,7 +406,7 @@ __device__ __forceinline__ void mats_store(const MatDev& m, int n, MatDev* s_mat
 
 // ------------------------------------------------------------- z forward
 // tau = C(x):p(x) (or p, or Ce:p, or C(x):dE) for a tile of rows, R2C along z.
-template <class T, int BIG>
+template <class T, int BIG, int NF>
 __global__ void __launch_bounds__(256) k_zfwd(const RveDev* __restrict__ rvs, int nrve, int rows_per_tile, int ldmax,
                                               int in_mode, int in_role, int tan_mode, int want_norm,
                                               int check_done, int update_p) {
@@ -492,7 +492,7 @@ __global__ void __launch_bounds__(256) k_zfwd(const RveDev* __restrict__ rvs, in
     process(vi, t);
   }
   __syncthreads();
-  cx<T>* res = line_fft<-1, T, BIG>(L.line, L.scratch, ld, 3 * nrows, L.ax, L.dc);
+  cx<T>* res = line_fft<-1, T, BIG, NF>(L.line, L.scratch, ld, 3 * nrows, L.ax, L.dc);
   // untangle two real transforms: A_k = (Z_k + conj Z_-k)/2, B_k = (Z_k - conj Z_-k)/(2i)
   FFTG_GLOBAL cx<T>* spec = gmem((cx<T>*)rv.spec);
   for (int t = threadIdx.x; t < nrows * 3 * H; t += blockDim.x) {
@@ -514,7 +514,7 @@ __global__ void __launch_bounds__(256) k_zfwd(const RveDev* __restrict__ rvs, in
 }
 
 // --------------------------------------------------------------- y pass
-template <class T, int DIR, int BIG>
+template <class T, int DIR, int BIG, int NF>
 __global__ void __launch_bounds__(256) k_ypass(const RveDev* __restrict__ rvs, int nrve, int lines_per_tile,
                                                int ldmax, int check_done) {
   extern __shared__ __align__(16) char smem[];
@@ -561,7 +561,7 @@ __global__ void __launch_bounds__(256) k_ypass(const RveDev* __restrict__ rvs, i
   axis_lds_store<T>(L.ax, tf);
   if (check_done && single && dn1) return;
   __syncthreads();
-  cx<T>* res = line_fft<DIR, T, BIG>(L.line, L.scratch, ld, nh, L.ax, L.dc);
+  cx<T>* res = line_fft<DIR, T, BIG, NF>(L.line, L.scratch, ld, nh, L.ax, L.dc);
   for (int t = threadIdx.x; t < n1 * nh; t += blockDim.x) {
     const int y = fnh.div(t);
     const int hh = t - y * nh;
@@ -570,7 +570,7 @@ __global__ void __launch_bounds__(256) k_ypass(const RveDev* __restrict__ rvs, i
 }
 
 // --------------------------------------------------- x pass with G^(k)
-template <class T, int BIG>
+template <class T, int BIG, int NF>
 __global__ void __launch_bounds__(256) k_xpass(const RveDev* __restrict__ rvs, int nrve, int lines_per_tile,
                                                int ldmax, double scale_in, int check_done) {
   extern __shared__ __align__(16) char smem[];
@@ -617,7 +617,7 @@ __global__ void __launch_bounds__(256) k_xpass(const RveDev* __restrict__ rvs, i
   axis_lds_store<T>(L.ax, tf);
   if (check_done && single && dn1) return;
   __syncthreads();
-  cx<T>* res = line_fft<-1, T, BIG>(L.line, L.scratch, ld, nl, L.ax, L.dc);
+  cx<T>* res = line_fft<-1, T, BIG, NF>(L.line, L.scratch, ld, nl, L.ax, L.dc);
   cx<T>* oth = (res == L.line) ? L.scratch : L.line;
   // projection on every frequency (k0, k1, k2) of the tile; xi_i = k_i / L_i, L_i = n_i
   const T scale = T(scale_in / double(nvox));   // inverse DFT normalisation 1/|N|
@@ -642,7 +642,7 @@ __global__ void __launch_bounds__(256) k_xpass(const RveDev* __restrict__ rvs, i
     for (int c = 0; c < 6; ++c) res[(c * nh + hh) * ld + x] = v[c];
   }
   __syncthreads();
-  cx<T>* res2 = line_fft<1, T, BIG>(res, oth, ld, nl, L.ax, L.dc);
+  cx<T>* res2 = line_fft<1, T, BIG, NF>(res, oth, ld, nl, L.ax, L.dc);
   for (int t = threadIdx.x; t < 6 * n0 * nh; t += blockDim.x) {
     const int cx_ = fxn.div(t);
     const int r = t - cx_ * n0 * nh;
@@ -713,7 +713,7 @@ __device__ bool cg_alpha(const RveDev& rv, int tile, const CgPeek& pk, bool chec
 }
 
 // ------------------------------------------------------------- z inverse
-template <class T, int BIG>
+template <class T, int BIG, int NF>
 __global__ void __launch_bounds__(256) k_zinv(const RveDev* __restrict__ rvs, int nrve, int rows_per_tile, int ldmax,
                                               int out_mode, int out_role, int check_done, int p_role) {
   extern __shared__ __align__(16) char smem[];
@@ -810,7 +810,7 @@ __global__ void __launch_bounds__(256) k_zinv(const RveDev* __restrict__ rvs, in
   } else {
     __syncthreads();
   }
-  cx<T>* res = line_fft<1, T, BIG>(L.line, L.scratch, ld, 3 * nrows, L.ax, L.dc);
+  cx<T>* res = line_fft<1, T, BIG, NF>(L.line, L.scratch, ld, 3 * nrows, L.ax, L.dc);
   double dot = 0.0;
   if (cg_out) {
     // x += alpha p, r -= alpha G:(C:p), partials of the new r.r
@@ -1428,26 +1428,29 @@ size_t lds_x(int mixed, int lines, int n0) {
                : tile_lds<double>(6 * lines, n0) + axis_lds_bytes<double>(n0);
 }
 
-template <class T, int BIG>
+template <class T, int BIG, int NF>
 static void zfwd_go(dim3 G, dim3 B, size_t lds, hipStream_t s, const RveDev* rv, int nrve, int rows, int ldmax,
                     int in_mode, int in_role, int tan_mode, int want_norm, int check_done, int update_p) {
-  hipLaunchKernelGGL((k_zfwd<T, BIG>), G, B, lds, s, rv, nrve, rows, ldmax, in_mode, in_role, tan_mode, want_norm,
+  hipLaunchKernelGGL((k_zfwd<T, BIG, NF>), G, B, lds, s, rv, nrve, rows, ldmax, in_mode, in_role, tan_mode, want_norm,
                      check_done, update_p);
 }
-template <class T, int DIR, int BIG>
-static void ypass_go(dim3 G, dim3 B, size_t lds, hipStream_t s, const RveDev* rv, int nrve, int lines, int ldmax,
-                     int check_done) {
-  hipLaunchKernelGGL((k_ypass<T, DIR, BIG>), G, B, lds, s, rv, nrve, lines, ldmax, check_done);
-}
-template <class T, int BIG>
+template <int DIR>
+struct ypass_go {
+  template <class T, int BIG, int NF>
+  static void go(dim3 G, dim3 B, size_t lds, hipStream_t s, const RveDev* rv, int nrve, int lines, int ldmax,
+                 int check_done) {
+    hipLaunchKernelGGL((k_ypass<T, DIR, BIG, NF>), G, B, lds, s, rv, nrve, lines, ldmax, check_done);
+  }
+};
+template <class T, int BIG, int NF>
 static void xpass_go(dim3 G, dim3 B, size_t lds, hipStream_t s, const RveDev* rv, int nrve, int lines, int ldmax,
                      double scale, int check_done) {
-  hipLaunchKernelGGL((k_xpass<T, BIG>), G, B, lds, s, rv, nrve, lines, ldmax, scale, check_done);
+  hipLaunchKernelGGL((k_xpass<T, BIG, NF>), G, B, lds, s, rv, nrve, lines, ldmax, scale, check_done);
 }
-template <class T, int BIG>
+template <class T, int BIG, int NF>
 static void zinv_go(dim3 G, dim3 B, size_t lds, hipStream_t s, const RveDev* rv, int nrve, int rows, int ldmax,
                     int out_mode, int out_role, int check_done, int p_role) {
-  hipLaunchKernelGGL((k_zinv<T, BIG>), G, B, lds, s, rv, nrve, rows, ldmax, out_mode, out_role, check_done, p_role);
+  hipLaunchKernelGGL((k_zinv<T, BIG, NF>), G, B, lds, s, rv, nrve, rows, ldmax, out_mode, out_role, check_done, p_role);
 }
 template <class T, int BIG>
 static void slab_fwd_go(dim3 G, dim3 B, size_t lds, hipStream_t s, const RveDev* rv, int nrve, int n1max, int n2max,
@@ -1477,12 +1480,29 @@ static int nrve_arg(int nrve, const LaunchCfg& cfg) { return nrve | (cfg.xcd_rem
     }                                                 \
   } while (0)
 
+// As DISPATCH_TB for the five-pass kernels, with the kernels built for
+// 31-point lines when every member's transformed axis (bit ax of
+// cfg.direct31) takes the 31-point direct DFT.
+#define DISPATCH_TBF(fn, ax, ...)                                   \
+  do {                                                              \
+    const bool f31 = !cfg.big_radix && ((cfg.direct31 >> (ax)) & 1); \
+    if (mixed) {                                                    \
+      if (cfg.big_radix) fn<float, 1, 0>(__VA_ARGS__);              \
+      else if (f31) fn<float, 0, 31>(__VA_ARGS__);                  \
+      else fn<float, 0, 0>(__VA_ARGS__);                            \
+    } else {                                                        \
+      if (cfg.big_radix) fn<double, 1, 0>(__VA_ARGS__);             \
+      else if (f31) fn<double, 0, 31>(__VA_ARGS__);                 \
+      else fn<double, 0, 0>(__VA_ARGS__);                           \
+    }                                                               \
+  } while (0)
+
 hipError_t launch_zfwd(int mixed, const RveDev* rv, int nrve, int tiles, const LaunchCfg& cfg, size_t lds,
                        int in_mode, int in_role, int tan_mode, int want_norm, int check_done, int update_p,
                        hipStream_t s) {
   if (tiles <= 0) return hipSuccess;
   const int nr = nrve_arg(nrve, cfg);
-  DISPATCH_TB(zfwd_go, dim3(tiles), dim3(cfg.threads_z), lds, s, rv, nr, cfg.rows_per_tile, cfg.n2max, in_mode,
+  DISPATCH_TBF(zfwd_go, 2, dim3(tiles), dim3(cfg.threads_z), lds, s, rv, nr, cfg.rows_per_tile, cfg.n2max, in_mode,
               in_role, tan_mode, want_norm, check_done, update_p);
   return hipGetLastError();
 }
@@ -1492,23 +1512,10 @@ hipError_t launch_ypass(int mixed, int dir, const RveDev* rv, int nrve, int tile
   if (tiles <= 0) return hipSuccess;
   const int nr = nrve_arg(nrve, cfg);
   const dim3 G(tiles), B(cfg.threads_y);
-  if (mixed) {
-    if (cfg.big_radix) {
-      if (dir < 0) ypass_go<float, -1, 1>(G, B, lds, s, rv, nr, cfg.lines_y, cfg.n1max, check_done);
-      else ypass_go<float, 1, 1>(G, B, lds, s, rv, nr, cfg.lines_y, cfg.n1max, check_done);
-    } else {
-      if (dir < 0) ypass_go<float, -1, 0>(G, B, lds, s, rv, nr, cfg.lines_y, cfg.n1max, check_done);
-      else ypass_go<float, 1, 0>(G, B, lds, s, rv, nr, cfg.lines_y, cfg.n1max, check_done);
-    }
-  } else {
-    if (cfg.big_radix) {
-      if (dir < 0) ypass_go<double, -1, 1>(G, B, lds, s, rv, nr, cfg.lines_y, cfg.n1max, check_done);
-      else ypass_go<double, 1, 1>(G, B, lds, s, rv, nr, cfg.lines_y, cfg.n1max, check_done);
-    } else {
-      if (dir < 0) ypass_go<double, -1, 0>(G, B, lds, s, rv, nr, cfg.lines_y, cfg.n1max, check_done);
-      else ypass_go<double, 1, 0>(G, B, lds, s, rv, nr, cfg.lines_y, cfg.n1max, check_done);
-    }
-  }
+  if (dir < 0)
+    DISPATCH_TBF(ypass_go<-1>::go, 1, G, B, lds, s, rv, nr, cfg.lines_y, cfg.n1max, check_done);
+  else
+    DISPATCH_TBF(ypass_go<1>::go, 1, G, B, lds, s, rv, nr, cfg.lines_y, cfg.n1max, check_done);
   return hipGetLastError();
 }
 
@@ -1516,7 +1523,7 @@ hipError_t launch_xpass(int mixed, const RveDev* rv, int nrve, int tiles, const 
                         double scale, int check_done, hipStream_t s) {
   if (tiles <= 0) return hipSuccess;
   const int nr = nrve_arg(nrve, cfg);
-  DISPATCH_TB(xpass_go, dim3(tiles), dim3(cfg.threads_x), lds, s, rv, nr, cfg.lines_x, cfg.n0max, scale,
+  DISPATCH_TBF(xpass_go, 0, dim3(tiles), dim3(cfg.threads_x), lds, s, rv, nr, cfg.lines_x, cfg.n0max, scale,
               check_done);
   return hipGetLastError();
 }
@@ -1525,7 +1532,7 @@ hipError_t launch_zinv(int mixed, const RveDev* rv, int nrve, int tiles, const L
                        int out_mode, int out_role, int check_done, int p_role, hipStream_t s) {
   if (tiles <= 0) return hipSuccess;
   const int nr = nrve_arg(nrve, cfg);
-  DISPATCH_TB(zinv_go, dim3(tiles), dim3(cfg.threads_z), lds, s, rv, nr, cfg.rows_per_tile, cfg.n2max, out_mode,
+  DISPATCH_TBF(zinv_go, 2, dim3(tiles), dim3(cfg.threads_z), lds, s, rv, nr, cfg.rows_per_tile, cfg.n2max, out_mode,
               out_role, check_done, p_role);
   return hipGetLastError();
 }

@@ -360,6 +360,7 @@ struct GridSum {
   long long hmax = 1;
   long long vox = 0;
   int big = 0;
+  int direct31 = 7;                 // bit a: every member's axis a is the 31-point direct DFT
 };
 
 static LaunchCfg choose_cfg(const GridSum& gs) {
@@ -390,6 +391,7 @@ static LaunchCfg choose_cfg(const GridSum& gs) {
   c.slab = (slab_mode() == 2 && slab_fits(gs.n1, gs.n2)) ? 1 : 0;
   c.threads_s = 256;
   c.big_radix = gs.big;
+  c.direct31 = gs.direct31;
   c.xcd_remap = env_long("FFTG_XCD_REMAP", 1) == 1 ? 1 : 0;
   c.n0max = gs.n0;
   c.n1max = gs.n1;
@@ -756,6 +758,8 @@ static GridSum group_gridsum(const Group& g) {
     gs.hmax = std::max<long long>(gs.hmax, pl->H);
     gs.vox += pl->nvox;
     gs.big = gs.big || pl->big_radix;
+    for (int a = 0; a < 3; ++a)
+      if (!(pl->ax_dev[a].rader == AX_DIRECT && pl->ax_dev[a].M == 31)) gs.direct31 &= ~(1 << a);
   }
   return gs;
 }

@@ -15,7 +15,7 @@ pytestmark = pytest.mark.gpu
 
 SHAPES = [(3, 3, 3), (1, 5, 7), (7, 5, 1), (3, 5, 7), (5, 7, 9), (11, 11, 11), (13, 17, 11),
           (15, 15, 15), (21, 25, 27), (31, 31, 31), (63, 31, 15), (19, 23, 29), (61, 9, 5),
-          (47, 5, 59), (3, 53, 43), (127, 3, 5), (3, 255, 3), (5, 3, 127)]
+          (47, 5, 59), (3, 53, 43), (127, 3, 5), (3, 255, 3), (5, 3, 127), (31, 9, 5), (9, 5, 31)]
 
 
 def _plan(shape, phase=None, mats=None, precision=0):

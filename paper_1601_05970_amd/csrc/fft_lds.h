@@ -442,6 +442,16 @@ __device__ __forceinline__ void direct_dft(const cx<T>* line, cx<T>* scratch, in
 // result (line or scratch).  Must be called by the whole workgroup.
 template <int DIR, class T, int BIG, int NF = 0>
 __device__ cx<T>* line_fft(cx<T>* line, cx<T>* scratch, int ld, int nl, const AxisLds<T>& P, cx<T>* dc) {
+  if constexpr (NF > 0) {
+    // kernels built for one line length run only where every line of the
+    // launch takes the NF-point direct DFT (the host checks the plan's
+    // axes): that length with every step unrolled, so that each thread
+    // issues all its LDS reads before its first wait (more registers, hence
+    // a separate build), and no other transform compiled in
+    direct_dft<DIR, T, NF>(line, scratch, ld, nl, P);
+    __syncthreads();
+    return scratch;
+  }
   if (P.rader == AX_CHAIN) {
     cx<T>* a = line;
     cx<T>* b = scratch;
@@ -449,17 +459,7 @@ __device__ cx<T>* line_fft(cx<T>* line, cx<T>* scratch, int ld, int nl, const Ax
     return a;
   }
   if (P.rader == AX_DIRECT) {
-    // NF > 0 (kernels built for one line length): that length with every
-    // step unrolled, so that each thread issues all its LDS reads before its
-    // first wait (more registers, hence a separate build)
-    bool done = false;
-    if constexpr (NF > 0) {
-      if (P.M == NF) {
-        direct_dft<DIR, T, NF>(line, scratch, ld, nl, P);
-        done = true;
-      }
-    }
-    if (!done) direct_dft<DIR, T, 0>(line, scratch, ld, nl, P);
+    direct_dft<DIR, T, 0>(line, scratch, ld, nl, P);
     __syncthreads();
     return scratch;
   }

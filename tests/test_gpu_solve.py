@@ -204,6 +204,36 @@ def test_batch_equals_alone():
             assert rel_err(f[k], alone[i][0][k]) < 1e-12, k
 
 
+def test_batch_with_31_point_axes_equals_alone():
+    """A batch whose members share 31-point x and z axes but not y: the z and
+    x passes run the kernels built for 31-point lines with two members, the y
+    pass the general ones; alone, the 31^3 member takes the 31-point y pass
+    too.  Both agree with the members solved alone."""
+    print("batch vs alone, 31-point axes", flush=True)
+    from paper_1601_05970_amd import fftg
+    # 0.002 equivalent strain per increment (the FP64 oracle converges in
+    # 2, 5 and 4-5 Newton iterations on these three increments)
+    ws = [synth.small_random(sh, 0.35, i + 7, E_eq=0.01, n_inc=5)
+          for i, sh in enumerate([(31, 31, 31), (31, 9, 31)])]
+    alone = []
+    for w in ws:
+        _, h, st = _run_gpu(w, _opts(w), n_inc=3)
+        alone.append((_fields(h), st))
+    plans = [fftg.Plan(w.phase, w.materials, _opts(w)) for w in ws]
+    hists = [fftg.History(p) for p in plans]
+    b = fftg.Batch(plans, hists)
+    for n in range(1, 4):
+        dE = np.array([tensor6(w.dE(n)) for w in ws])
+        st = b.solve_increment(dE)
+        for i in range(2):
+            assert st[i]["cg_iters"] == alone[i][1][n - 1]["cg_iters"]
+    # the two y-pass builds differ only in the rounding of a few root products
+    for i, h in enumerate(hists):
+        f = _fields(h)
+        for k in f:
+            assert rel_err(f[k], alone[i][0][k]) < 1e-10, k
+
+
 def test_error_paths():
     print("errors", flush=True)
     from paper_1601_05970_amd import fftg

@@ -23,6 +23,9 @@ ARCH = os.environ.get("FFTG_ARCH", "gfx950")
 COMMON = [
     "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-mcode-object-version=5",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # kernel arguments preloaded into SGPRs by the dispatcher (gfx950): the
+    # first descriptor load need not wait for a load of the arguments
+    "-mllvm", "-amdgpu-kernarg-preload-count=16",
     "-Wall", "-Wno-unused-function", "-Wno-unknown-pragmas", "-Wno-unused-result", "-Wno-unused-value",
     f"-I{os.path.join(ROOT, 'include')}", f"-I{CSRC}",
 ]

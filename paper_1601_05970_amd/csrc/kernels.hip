@@ -918,7 +918,7 @@ struct SlabLds {
   }
 };
 
-template <class T, int BIG>
+template <class T, int BIG, int NF>
 __global__ void __launch_bounds__(512) k_slab_fwd(const RveDev* __restrict__ rvs, int nrve, int n1max, int n2max,
                                                   int in_mode, int in_role, int tan_mode, int want_norm,
                                                   int check_done, int update_p, int p_in, int p_out) {
@@ -990,7 +990,7 @@ __global__ void __launch_bounds__(512) k_slab_fwd(const RveDev* __restrict__ rvs
     process(vi, t);
   }
   __syncthreads();
-  cx<T>* res = line_fft<-1, T, BIG>(L.b0, L.b1, n2, n1, L.az, L.dc);
+  cx<T>* res = line_fft<-1, T, BIG, NF>(L.b0, L.b1, n2, n1, L.az, L.dc);
   cx<T>* oth = (res == L.b0) ? L.b1 : L.b0;
   // untangle into y-lines: component 2pr + c2, frequency k -> line c2 * H + k
   const FastDiv fH(H), fn1(n1);
@@ -1003,7 +1003,7 @@ __global__ void __launch_bounds__(512) k_slab_fwd(const RveDev* __restrict__ rvs
     oth[(H + k) * n1 + y] = cx<T>{T(0.5) * (zk.im + zm.im), T(-0.5) * (zk.re - zm.re)};
   }
   __syncthreads();
-  cx<T>* res2 = line_fft<-1, T, BIG>(oth, res, n1, 2 * H, L.ay, L.dc);
+  cx<T>* res2 = line_fft<-1, T, BIG, NF>(oth, res, n1, 2 * H, L.ay, L.dc);
   FFTG_GLOBAL cx<T>* spec = gmem((cx<T>*)rv.spec);
   for (int t = threadIdx.x; t < 2 * n1 * H; t += blockDim.x) {
     const int cy = fH.div(t);
@@ -1017,7 +1017,7 @@ __global__ void __launch_bounds__(512) k_slab_fwd(const RveDev* __restrict__ rvs
   }
 }
 
-template <class T, int BIG>
+template <class T, int BIG, int NF>
 __global__ void __launch_bounds__(512) k_slab_inv(const RveDev* __restrict__ rvs, int nrve, int n1max, int n2max,
                                                   int out_mode, int out_role, int check_done, int p_role) {
   extern __shared__ __align__(16) char smem[];
@@ -1091,7 +1091,7 @@ __global__ void __launch_bounds__(512) k_slab_inv(const RveDev* __restrict__ rvs
   } else {
     __syncthreads();
   }
-  cx<T>* res = line_fft<1, T, BIG>(L.b0, L.b1, n1, 2 * H, L.ay, L.dc);
+  cx<T>* res = line_fft<1, T, BIG, NF>(L.b0, L.b1, n1, 2 * H, L.ay, L.dc);
   cx<T>* oth = (res == L.b0) ? L.b1 : L.b0;
   // z-line y: Z_z = A_z + i B_z, Z_{n2-k} = conj(A_k) + i conj(B_k)
   for (int t = threadIdx.x; t < n1 * n2; t += blockDim.x) {
@@ -1109,7 +1109,7 @@ __global__ void __launch_bounds__(512) k_slab_inv(const RveDev* __restrict__ rvs
     oth[t] = Zv;
   }
   __syncthreads();
-  cx<T>* res2 = line_fft<1, T, BIG>(oth, res, n2, n1, L.az, L.dc);
+  cx<T>* res2 = line_fft<1, T, BIG, NF>(oth, res, n2, n1, L.az, L.dc);
   double dot = 0.0;
   if (cg_out) {
     // x += alpha p, r -= alpha G:(C:p) on the tile's two components, partials of r.r
@@ -1452,40 +1452,30 @@ static void zinv_go(dim3 G, dim3 B, size_t lds, hipStream_t s, const RveDev* rv,
                     int out_mode, int out_role, int check_done, int p_role) {
   hipLaunchKernelGGL((k_zinv<T, BIG, NF>), G, B, lds, s, rv, nrve, rows, ldmax, out_mode, out_role, check_done, p_role);
 }
-template <class T, int BIG>
+template <class T, int BIG, int NF>
 static void slab_fwd_go(dim3 G, dim3 B, size_t lds, hipStream_t s, const RveDev* rv, int nrve, int n1max, int n2max,
                         int in_mode, int in_role, int tan_mode, int want_norm, int check_done, int update_p, int p_in,
                         int p_out) {
-  hipLaunchKernelGGL((k_slab_fwd<T, BIG>), G, B, lds, s, rv, nrve, n1max, n2max, in_mode, in_role, tan_mode,
+  hipLaunchKernelGGL((k_slab_fwd<T, BIG, NF>), G, B, lds, s, rv, nrve, n1max, n2max, in_mode, in_role, tan_mode,
                      want_norm, check_done, update_p, p_in, p_out);
 }
-template <class T, int BIG>
+template <class T, int BIG, int NF>
 static void slab_inv_go(dim3 G, dim3 B, size_t lds, hipStream_t s, const RveDev* rv, int nrve, int n1max, int n2max,
                         int out_mode, int out_role, int check_done, int p_role) {
-  hipLaunchKernelGGL((k_slab_inv<T, BIG>), G, B, lds, s, rv, nrve, n1max, n2max, out_mode, out_role, check_done,
+  hipLaunchKernelGGL((k_slab_inv<T, BIG, NF>), G, B, lds, s, rv, nrve, n1max, n2max, out_mode, out_role, check_done,
                      p_role);
 }
 
 // Member count with the tile-mapping flag for the tiled kernels.
 static int nrve_arg(int nrve, const LaunchCfg& cfg) { return nrve | (cfg.xcd_remap ? kLaunchRemap : 0); }
 
-#define DISPATCH_TB(fn, ...)                          \
-  do {                                                \
-    if (mixed) {                                      \
-      if (cfg.big_radix) fn<float, 1>(__VA_ARGS__);   \
-      else fn<float, 0>(__VA_ARGS__);                 \
-    } else {                                          \
-      if (cfg.big_radix) fn<double, 1>(__VA_ARGS__);  \
-      else fn<double, 0>(__VA_ARGS__);                \
-    }                                                 \
-  } while (0)
-
-// As DISPATCH_TB for the five-pass kernels, with the kernels built for
-// 31-point lines when every member's transformed axis (bit ax of
-// cfg.direct31) takes the 31-point direct DFT.
-#define DISPATCH_TBF(fn, ax, ...)                                   \
-  do {                                                              \
-    const bool f31 = !cfg.big_radix && ((cfg.direct31 >> (ax)) & 1); \
+// Launches fn<T, BIG, NF> for the launch's precision and codelet set, with
+// the kernels built for 31-point lines (NF = 31) when every member takes
+// each axis the kernel transforms (the bits of axes in cfg.direct31) by the
+// 31-point direct DFT.
+#define DISPATCH_TBF(fn, axes, ...)                                    \
+  do {                                                                 \
+    const bool f31 = !cfg.big_radix && (cfg.direct31 & (axes)) == (axes); \
     if (mixed) {                                                    \
       if (cfg.big_radix) fn<float, 1, 0>(__VA_ARGS__);              \
       else if (f31) fn<float, 0, 31>(__VA_ARGS__);                  \
@@ -1502,7 +1492,7 @@ hipError_t launch_zfwd(int mixed, const RveDev* rv, int nrve, int tiles, const L
                        hipStream_t s) {
   if (tiles <= 0) return hipSuccess;
   const int nr = nrve_arg(nrve, cfg);
-  DISPATCH_TBF(zfwd_go, 2, dim3(tiles), dim3(cfg.threads_z), lds, s, rv, nr, cfg.rows_per_tile, cfg.n2max, in_mode,
+  DISPATCH_TBF(zfwd_go, 4, dim3(tiles), dim3(cfg.threads_z), lds, s, rv, nr, cfg.rows_per_tile, cfg.n2max, in_mode,
               in_role, tan_mode, want_norm, check_done, update_p);
   return hipGetLastError();
 }
@@ -1513,9 +1503,9 @@ hipError_t launch_ypass(int mixed, int dir, const RveDev* rv, int nrve, int tile
   const int nr = nrve_arg(nrve, cfg);
   const dim3 G(tiles), B(cfg.threads_y);
   if (dir < 0)
-    DISPATCH_TBF(ypass_go<-1>::go, 1, G, B, lds, s, rv, nr, cfg.lines_y, cfg.n1max, check_done);
+    DISPATCH_TBF(ypass_go<-1>::go, 2, G, B, lds, s, rv, nr, cfg.lines_y, cfg.n1max, check_done);
   else
-    DISPATCH_TBF(ypass_go<1>::go, 1, G, B, lds, s, rv, nr, cfg.lines_y, cfg.n1max, check_done);
+    DISPATCH_TBF(ypass_go<1>::go, 2, G, B, lds, s, rv, nr, cfg.lines_y, cfg.n1max, check_done);
   return hipGetLastError();
 }
 
@@ -1523,7 +1513,7 @@ hipError_t launch_xpass(int mixed, const RveDev* rv, int nrve, int tiles, const 
                         double scale, int check_done, hipStream_t s) {
   if (tiles <= 0) return hipSuccess;
   const int nr = nrve_arg(nrve, cfg);
-  DISPATCH_TBF(xpass_go, 0, dim3(tiles), dim3(cfg.threads_x), lds, s, rv, nr, cfg.lines_x, cfg.n0max, scale,
+  DISPATCH_TBF(xpass_go, 1, dim3(tiles), dim3(cfg.threads_x), lds, s, rv, nr, cfg.lines_x, cfg.n0max, scale,
               check_done);
   return hipGetLastError();
 }
@@ -1532,7 +1522,7 @@ hipError_t launch_zinv(int mixed, const RveDev* rv, int nrve, int tiles, const L
                        int out_mode, int out_role, int check_done, int p_role, hipStream_t s) {
   if (tiles <= 0) return hipSuccess;
   const int nr = nrve_arg(nrve, cfg);
-  DISPATCH_TBF(zinv_go, 2, dim3(tiles), dim3(cfg.threads_z), lds, s, rv, nr, cfg.rows_per_tile, cfg.n2max, out_mode,
+  DISPATCH_TBF(zinv_go, 4, dim3(tiles), dim3(cfg.threads_z), lds, s, rv, nr, cfg.rows_per_tile, cfg.n2max, out_mode,
               out_role, check_done, p_role);
   return hipGetLastError();
 }
@@ -1542,7 +1532,7 @@ hipError_t launch_slab_fwd(int mixed, const RveDev* rv, int nrve, int tiles, con
                            int p_in, int p_out, hipStream_t s) {
   if (tiles <= 0) return hipSuccess;
   const int nr = nrve_arg(nrve, cfg);
-  DISPATCH_TB(slab_fwd_go, dim3(tiles), dim3(cfg.threads_s), lds, s, rv, nr, cfg.n1max, cfg.n2max, in_mode,
+  DISPATCH_TBF(slab_fwd_go, 6, dim3(tiles), dim3(cfg.threads_s), lds, s, rv, nr, cfg.n1max, cfg.n2max, in_mode,
               in_role, tan_mode, want_norm, check_done, update_p, p_in, p_out);
   return hipGetLastError();
 }
@@ -1551,7 +1541,7 @@ hipError_t launch_slab_inv(int mixed, const RveDev* rv, int nrve, int tiles, con
                            int out_mode, int out_role, int check_done, int p_role, hipStream_t s) {
   if (tiles <= 0) return hipSuccess;
   const int nr = nrve_arg(nrve, cfg);
-  DISPATCH_TB(slab_inv_go, dim3(tiles), dim3(cfg.threads_s), lds, s, rv, nr, cfg.n1max, cfg.n2max, out_mode,
+  DISPATCH_TBF(slab_inv_go, 6, dim3(tiles), dim3(cfg.threads_s), lds, s, rv, nr, cfg.n1max, cfg.n2max, out_mode,
               out_role, check_done, p_role);
   return hipGetLastError();
 }

@@ -952,12 +952,15 @@ __global__ void __launch_bounds__(512) k_slab_fwd(const RveDev* __restrict__ rvs
   const int npl = n1 * n2;
   __shared__ MatDev s_mats[kMaxPhases];  // per-voxel material lookups from LDS
   // Loads in program order before anything that waits (as in the z pass):
-  // tables, this thread's first voxel, materials, CG scalars, partials.
+  // tables, this thread's first two voxels (a plane has up to twice as many
+  // voxels as a tile has threads at 31^2), materials, CG scalars, partials.
   const AxisFetch<T> tfz = axis_lds_fetch<T>(L.az);
   const AxisFetch<T> tfy = axis_lds_fetch<T>(L.ay);
-  VoxIn<T> vi0;
+  const int t1 = (int)threadIdx.x + (int)blockDim.x;
+  VoxIn<T> vi0, vi1;
   voxel_load<T>(v0 + min((int)threadIdx.x, npl - 1), nvox, in_mode, in, update_p, rres, pin, tan_mode, tang, phase,
                 vi0);
+  voxel_load<T>(v0 + min(t1, npl - 1), nvox, in_mode, in, update_p, rres, pin, tan_mode, tang, phase, vi1);
   const MatDev mt = mats_fetch(mats, nph);
   const CgPeekB pk = cg_peek_b(cg);
   const double pa = (update_p && fold) ? thread_partials(prr, nti) : 0.0;
@@ -984,7 +987,8 @@ __global__ void __launch_bounds__(512) k_slab_fwd(const RveDev* __restrict__ rvs
     L.b0[t] = cx<T>{a, b};  // z-line y at y * n2
   };
   if ((int)threadIdx.x < npl) process(vi0, threadIdx.x);
-  for (int t = threadIdx.x + blockDim.x; t < npl; t += blockDim.x) {
+  if (t1 < npl) process(vi1, t1);
+  for (int t = t1 + blockDim.x; t < npl; t += blockDim.x) {
     VoxIn<T> vi;
     voxel_load<T>(v0 + t, nvox, in_mode, in, update_p, rres, pin, tan_mode, tang, phase, vi);
     process(vi, t);
@@ -1050,7 +1054,7 @@ __global__ void __launch_bounds__(512) k_slab_inv(const RveDev* __restrict__ rvs
   const bool late = cg_out && launch_single(nrve);
   if (check_done && !late && *gmem(&cg->done)) return;
   // Loads in program order before anything that waits: tables, the
-  // spectrum, the CG scalars, the partials, this thread's first voxel.
+  // spectrum, the CG scalars, the partials, this thread's first two voxels.
   const AxisFetch<T> tfz = axis_lds_fetch<T>(L.az);
   const AxisFetch<T> tfy = axis_lds_fetch<T>(L.ay);
   const FastDiv fH(H), fn1(n1), fn2(n2);
@@ -1070,9 +1074,11 @@ __global__ void __launch_bounds__(512) k_slab_inv(const RveDev* __restrict__ rvs
       });
   const CgPeek pk = cg_peek(cg);
   const double pa = (cg_out && fold) ? thread_partials(part, ntz) : 0.0;
-  double xv0[2], rv0[2], pv0[2];
+  const int t1 = (int)threadIdx.x + (int)blockDim.x;
+  double xv0[2], rv0[2], pv0[2], xv1[2], rv1[2], pv1[2];
   if (cg_out) {
     const long long v = v0 + min((int)threadIdx.x, npl - 1);
+    const long long w = v0 + min(t1, npl - 1);
     const FFTG_GLOBAL double* gx = gmem((const double*)rv.buf[R_X]);
     const FFTG_GLOBAL double* gr = gmem((const double*)rv.buf[R_R]);
     const FFTG_GLOBAL double* gp = gmem((const double*)rv.buf[p_role]);
@@ -1082,6 +1088,12 @@ __global__ void __launch_bounds__(512) k_slab_inv(const RveDev* __restrict__ rvs
     rv0[1] = gr[c1 * nvox + v];
     pv0[0] = gp[c0 * nvox + v];
     pv0[1] = gp[c1 * nvox + v];
+    xv1[0] = gx[c0 * nvox + w];
+    xv1[1] = gx[c1 * nvox + w];
+    rv1[0] = gr[c0 * nvox + w];
+    rv1[1] = gr[c1 * nvox + w];
+    pv1[0] = gp[c0 * nvox + w];
+    pv1[1] = gp[c1 * nvox + w];
   }
   axis_lds_store<T>(L.az, tfz);
   axis_lds_store<T>(L.ay, tfy);
@@ -1127,7 +1139,8 @@ __global__ void __launch_bounds__(512) k_slab_inv(const RveDev* __restrict__ rvs
       dot += r0 * r0 + r1 * r1;
     };
     if ((int)threadIdx.x < npl) update(threadIdx.x, xv0, rv0, pv0);
-    for (int t = threadIdx.x + blockDim.x; t < npl; t += blockDim.x) {
+    if (t1 < npl) update(t1, xv1, rv1, pv1);
+    for (int t = t1 + blockDim.x; t < npl; t += blockDim.x) {
       const long long v = v0 + t;
       const double xv[2] = {xx[c0 * nvox + v], xx[c1 * nvox + v]};
       const double rv2[2] = {rr[c0 * nvox + v], rr[c1 * nvox + v]};

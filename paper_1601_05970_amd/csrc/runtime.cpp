@@ -336,16 +336,16 @@ static long env_long(const char* name, long dflt, long lo = 0) {
 constexpr size_t kSlabLdsMax = 160 * 1024 - 1024;
 static bool slab_fits(int n1, int n2) { return lds_slab(0, n1, n2) <= kSlabLdsMax; }
 
-// FFTG_SLAB: 0 (default) never uses the slab passes, 1 lets the autotuner
-// choose them when an isolated product is faster, 2 uses them whenever the
-// plane fits in LDS.  Inside CG they do not pay: each of a plane's three
-// tiles re-reads r, p and the tangent (31^3 solve 150.3 against 149.2 ms,
-// 64-RVE FP32 batch 3.69 against 3.12 s with the five passes).
+// FFTG_SLAB: 0 never uses the slab passes, 1 (default) lets the autotuner
+// choose them where the whole product in its CG form is faster with them
+// (the 31^3 single RVE: two launches fewer per CG iteration; not the mixed
+// batches, whose 63^3 members' planes give few, long tiles), 2 uses them
+// whenever the plane fits in LDS.
 static int slab_mode() {
   const char* s = getenv("FFTG_SLAB");
-  if (!s || !*s) return 0;
+  if (!s || !*s) return 1;
   const long v = strtol(s, nullptr, 10);
-  return (v >= 0 && v <= 2) ? (int)v : 0;
+  return (v >= 0 && v <= 2) ? (int)v : 1;
 }
 
 static int threads_for(long long points) {
@@ -1251,7 +1251,6 @@ static fftg_status group_autotune(Group& g) {
   const int thr[3] = {64, 128, 256};
   const int reps = gs.vox > 4000000 ? 2 : (gs.vox > 500000 ? 4 : 10);
   fftg_status st;
-  double t_zpair = 1e30, t_y = 1e30;
   // z passes: rows per tile and threads (zfwd + zinv timed together, in the
   // form they take inside CG: the p update, the vector update and their
   // folded sums, in the timing variant that uses no CG state.  Before a
@@ -1283,7 +1282,6 @@ static fftg_status group_autotune(Group& g) {
     }
     best.rows_per_tile = cb.rows_per_tile;
     best.threads_z = cb.threads_z;
-    t_zpair = tbest;
   }
   // y pass
   {
@@ -1309,7 +1307,6 @@ static fftg_status group_autotune(Group& g) {
     }
     best.lines_y = cb.lines_y;
     best.threads_y = cb.threads_y;
-    t_y = tbest;
   }
   // x pass
   {
@@ -1336,32 +1333,59 @@ static fftg_status group_autotune(Group& g) {
     best.lines_x = cb.lines_x;
     best.threads_x = cb.threads_x;
   }
-  // slab passes (z and y fused) against the z + y + y + z passes they replace
+  // slab passes (z and y fused) against the passes they replace, each timed
+  // as the whole product in its CG form (x pass included), so that launch
+  // costs and cold caches count as they do inside CG; the two schedules are
+  // timed in turn, three rounds, and each keeps its fastest round (clock
+  // ramps and other work on the device only ever add time)
   if (slab_mode() != 0 && slab_fits(gs.n1, gs.n2)) {
-    double tbest = 1e30;
-    LaunchCfg cb = best;
-    for (int t : {256, 512}) {
-      LaunchCfg c = best;
-      c.slab = 1;
-      c.threads_s = t;
-      group_set_cfg(g, c);
-      if ((st = group_upload(g)) != FFTG_OK) return st;
+    const size_t lz = mixed ? g.lds_zf32 : g.lds_zf, ly = mixed ? g.lds_y32 : g.lds_y;
+    const size_t lx = mixed ? g.lds_x32 : g.lds_x;
+    auto time_five = [&]() {
+      return time_ms(g.stream, reps, [&]() {
+        hipError_t e = launch_zfwd(mixed, g.d, nr, g.total[P_ZF], g.cfg, lz, IN_ROLE, R_P, TAN_ELASTIC, 0, 0,
+                                   PU_TIMING, g.stream);
+        if (e == hipSuccess) e = launch_ypass(mixed, -1, g.d, nr, g.total[P_Y], g.cfg, ly, 0, g.stream);
+        if (e == hipSuccess) e = launch_xpass(mixed, g.d, nr, g.total[P_X], g.cfg, lx, 1.0, 0, g.stream);
+        if (e == hipSuccess) e = launch_ypass(mixed, 1, g.d, nr, g.total[P_Y], g.cfg, ly, 0, g.stream);
+        if (e != hipSuccess) return e;
+        return launch_zinv(mixed, g.d, nr, g.total[P_ZI], g.cfg, lz, OUT_CG_TIMING, R_X, 0, R_P, g.stream);
+      });
+    };
+    auto time_slab = [&]() {
       const size_t ls = mixed ? g.lds_s32 : g.lds_s;
-      const double ms = time_ms(g.stream, reps, [&]() {
+      return time_ms(g.stream, reps, [&]() {
         hipError_t e = launch_slab_fwd(mixed, g.d, nr, g.total[P_ZF], g.cfg, ls, IN_ROLE, R_P, TAN_ELASTIC, 0, 0,
                                        PU_TIMING, R_P, R_P2, g.stream);
+        if (e == hipSuccess) e = launch_xpass(mixed, g.d, nr, g.total[P_X], g.cfg, lx, 1.0, 0, g.stream);
         if (e != hipSuccess) return e;
         return launch_slab_inv(mixed, g.d, nr, g.total[P_ZI], g.cfg, ls, OUT_CG_TIMING, R_X, 0, R_P2, g.stream);
       });
-      if (ms < 0.97 * tbest) {  // a later candidate must win clearly (stable choices)
-        tbest = ms;
-        cb = c;
+    };
+    const int slab_thr[2] = {256, 512};
+    double t_five = 1e30, t_slab[2] = {1e30, 1e30};
+    for (int round = 0; round < 3; ++round) {
+      group_set_cfg(g, best);
+      if ((st = group_upload(g)) != FFTG_OK) return st;
+      t_five = std::min(t_five, time_five());
+      for (int i = 0; i < 2; ++i) {
+        LaunchCfg c = best;
+        c.slab = 1;
+        c.threads_s = slab_thr[i];
+        group_set_cfg(g, c);
+        if ((st = group_upload(g)) != FFTG_OK) return st;
+        t_slab[i] = std::min(t_slab[i], time_slab());
       }
     }
-    if (slab_mode() == 2 || tbest < t_zpair + 2.0 * t_y) {
+    // a later candidate must win clearly (stable choices)
+    const int ib = t_slab[1] < 0.97 * t_slab[0] ? 1 : 0;
+    if (slab_mode() == 2 || t_slab[ib] < 0.99 * t_five) {
       best.slab = 1;
-      best.threads_s = cb.threads_s;
+      best.threads_s = slab_thr[ib];
     }
+    if (env_long("FFTG_VERBOSE", 0) == 1)
+      fprintf(stderr, "fftg autotune %s: product %.2f us five passes, %.2f us slab\n", key.c_str(), 1e3 * t_five,
+              1e3 * t_slab[ib]);
   }
   HIP_TRY(hipStreamSynchronize(g.stream));
   if (env_long("FFTG_VERBOSE", 0) == 1)

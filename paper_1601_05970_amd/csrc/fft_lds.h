@@ -347,9 +347,9 @@ __device__ void run_chain(cx<T>*& a, cx<T>*& b, int ld, int nl, const AxisLds<T>
   }
 }
 
-// Direct DFT of nl odd-length lines from line into scratch (same stride ld):
-// X_k = sum_j x_j w^(jk), w = exp(-+ 2 pi i / N).  With s_j = x_j + x_(N-j)
-// and d_j = x_j - x_(N-j) (j = 1 .. (N-1)/2) and theta = 2 pi j k / N,
+// Direct DFT of nl odd-length lines: X_k = sum_j x_j w^(jk),
+// w = exp(-+ 2 pi i / N).  With s_j = x_j + x_(N-j) and d_j = x_j - x_(N-j)
+// (j = 1 .. (N-1)/2) and theta = 2 pi j k / N,
 //   X_k = A + DIR i B,  X_(N-k) = A - DIR i B,
 //   A = x_0 + sum_j s_j cos theta,  B = sum_j d_j sin theta,
 // so one thread forms the pair X_k, X_(N-k) (k = 1 .. (N-1)/2; slot 0 forms
@@ -357,18 +357,20 @@ __device__ void run_chain(cx<T>*& a, cx<T>*& b, int ld, int nl, const AxisLds<T>
 // exp(-i theta) = (cos theta, -sin theta).  FP64 forms the roots w^(jk) by
 // recurrence in registers from w^k (one table read; the error after (N-1)/2
 // steps stays near 1e-15), FP32 reads them from the table.  NF > 0 fixes N at
-// compile time (all steps unrolled); NF == 0 takes N from the plan.  No
+// compile time (all steps unrolled); NF == 0 takes N from the plan.
+// The input comes from in0(l) -> x_0 and in(l, j, x_j&, x_(N-j)&), the
+// output goes to out(l, k, X_k, X_(N-k)) (k = 0: X_0 twice), so that a
+// caller can fold a pre- or post-processing step into the transform.  No
 // barrier.
-template <int DIR, class T, int NF>
-__device__ __forceinline__ void direct_dft(const cx<T>* line, cx<T>* scratch, int ld, int nl, const AxisLds<T>& P) {
+template <int DIR, class T, int NF, class In0, class In, class Out>
+__device__ __forceinline__ void direct_dft_io(int nl, const AxisLds<T>& P, In0&& in0, In&& in, Out&& out) {
   const int N = NF > 0 ? NF : P.M;
   const int Hn = (N + 1) / 2;
   const FastDiv fh(Hn);
   for (int t = threadIdx.x; t < nl * Hn; t += blockDim.x) {
     const int l = NF > 0 ? t / Hn : fh.div(t);
     const int k = t - l * Hn;
-    const cx<T>* x = line + l * ld;
-    const cx<T> x0 = x[0];
+    const cx<T> x0 = in0(l);
     T ar = x0.re, ai = x0.im, cr = T(0), ci = T(0);  // A and C = -B = sum_j d_j (-sin theta)
     auto step = [&](cx<T> a, cx<T> b, cx<T> w) {
       ar += (a.re + b.re) * w.re;
@@ -383,10 +385,7 @@ __device__ __forceinline__ void direct_dft(const cx<T>* line, cx<T>* scratch, in
       [[maybe_unused]] const cx<T> wk = P.tw[k];  // FP64 only (root recurrence)
       cx<T> va[H], vb[H];
 #pragma unroll
-      for (int j = 0; j < H; ++j) {
-        va[j] = x[j + 1];
-        vb[j] = x[NF - 1 - j];
-      }
+      for (int j = 0; j < H; ++j) in(l, j + 1, va[j], vb[j]);
       if constexpr (std::is_same<T, double>::value) {
         __builtin_amdgcn_sched_barrier(0);
         cx<T> w = wk;
@@ -413,7 +412,9 @@ __device__ __forceinline__ void direct_dft(const cx<T>* line, cx<T>* scratch, in
       cx<T> w = wk;
 #pragma unroll 4
       for (int j = 1; j < Hn; ++j) {
-        step(x[j], x[N - j], w);
+        cx<T> a, b;
+        in(l, j, a, b);
+        step(a, b, w);
         w = cmul(w, wk);
       }
     } else {
@@ -422,7 +423,9 @@ __device__ __forceinline__ void direct_dft(const cx<T>* line, cx<T>* scratch, in
       for (int j = 1; j < Hn; ++j) {
         idx += k;
         idx -= (idx >= N) ? N : 0;
-        step(x[j], x[N - j], P.tw[idx]);
+        cx<T> a, b;
+        in(l, j, a, b);
+        step(a, b, P.tw[idx]);
       }
     }
     // i B = -i C = (C.im, -C.re)
@@ -430,10 +433,25 @@ __device__ __forceinline__ void direct_dft(const cx<T>* line, cx<T>* scratch, in
     const T pi = DIR > 0 ? ai - cr : ai + cr;
     const T mr = DIR > 0 ? ar - ci : ar + ci;
     const T mi = DIR > 0 ? ai + cr : ai - cr;
-    cx<T>* o = scratch + l * ld;
-    o[k] = cx<T>{pr, pi};
-    if (k > 0) o[N - k] = cx<T>{mr, mi};
+    out(l, k, cx<T>{pr, pi}, cx<T>{mr, mi});
   }
+}
+
+// The direct DFT of nl lines from line into scratch (same stride ld).
+template <int DIR, class T, int NF>
+__device__ __forceinline__ void direct_dft(const cx<T>* line, cx<T>* scratch, int ld, int nl, const AxisLds<T>& P) {
+  const int N = NF > 0 ? NF : P.M;
+  direct_dft_io<DIR, T, NF>(
+      nl, P, [&](int l) { return line[l * ld]; },
+      [&](int l, int j, cx<T>& a, cx<T>& b) {
+        a = line[l * ld + j];
+        b = line[l * ld + N - j];
+      },
+      [&](int l, int k, cx<T> xk, cx<T> xm) {
+        cx<T>* o = scratch + l * ld;
+        o[k] = xk;
+        if (k > 0) o[N - k] = xm;
+      });
 }
 
 // In-LDS FFT of nl lines of length P.N, DIR = -1 forward, +1 inverse

@@ -994,20 +994,39 @@ __global__ void __launch_bounds__(512) k_slab_fwd(const RveDev* __restrict__ rvs
     process(vi, t);
   }
   __syncthreads();
-  cx<T>* res = line_fft<-1, T, BIG, NF>(L.b0, L.b1, n2, n1, L.az, L.dc);
-  cx<T>* oth = (res == L.b0) ? L.b1 : L.b0;
-  // untangle into y-lines: component 2pr + c2, frequency k -> line c2 * H + k
+  // z transform of the packed lines, untangled into y-lines: component
+  // 2pr + c2, frequency k -> line c2 * H + k
   const FastDiv fH(H), fn1(n1);
-  for (int t = threadIdx.x; t < n1 * H; t += blockDim.x) {
-    const int y = fH.div(t);
-    const int k = t - y * H;
-    const cx<T> zk = res[y * n2 + k];
-    const cx<T> zm = res[y * n2 + (k == 0 ? 0 : n2 - k)];
-    oth[k * n1 + y] = cx<T>{T(0.5) * (zk.re + zm.re), T(0.5) * (zk.im - zm.im)};
-    oth[(H + k) * n1 + y] = cx<T>{T(0.5) * (zk.im + zm.im), T(-0.5) * (zk.re - zm.re)};
+  cx<T>* yl;
+  if constexpr (NF > 0) {
+    // the thread that forms X_k and X_(n2-k) of packed line y holds both
+    // components' frequency k: untangled as they are stored (no pass of
+    // its own)
+    direct_dft_io<-1, T, NF>(
+        n1, L.az, [&](int y) { return L.b0[y * n2]; },
+        [&](int y, int j, cx<T>& a, cx<T>& b) {
+          a = L.b0[y * n2 + j];
+          b = L.b0[y * n2 + NF - j];
+        },
+        [&](int y, int k, cx<T> zk, cx<T> zm) {
+          L.b1[k * n1 + y] = cx<T>{T(0.5) * (zk.re + zm.re), T(0.5) * (zk.im - zm.im)};
+          L.b1[(H + k) * n1 + y] = cx<T>{T(0.5) * (zk.im + zm.im), T(-0.5) * (zk.re - zm.re)};
+        });
+    yl = L.b1;
+  } else {
+    cx<T>* res = line_fft<-1, T, BIG, NF>(L.b0, L.b1, n2, n1, L.az, L.dc);
+    yl = (res == L.b0) ? L.b1 : L.b0;
+    for (int t = threadIdx.x; t < n1 * H; t += blockDim.x) {
+      const int y = fH.div(t);
+      const int k = t - y * H;
+      const cx<T> zk = res[y * n2 + k];
+      const cx<T> zm = res[y * n2 + (k == 0 ? 0 : n2 - k)];
+      yl[k * n1 + y] = cx<T>{T(0.5) * (zk.re + zm.re), T(0.5) * (zk.im - zm.im)};
+      yl[(H + k) * n1 + y] = cx<T>{T(0.5) * (zk.im + zm.im), T(-0.5) * (zk.re - zm.re)};
+    }
   }
   __syncthreads();
-  cx<T>* res2 = line_fft<-1, T, BIG, NF>(oth, res, n1, 2 * H, L.ay, L.dc);
+  cx<T>* res2 = line_fft<-1, T, BIG, NF>(yl, yl == L.b0 ? L.b1 : L.b0, n1, 2 * H, L.ay, L.dc);
   FFTG_GLOBAL cx<T>* spec = gmem((cx<T>*)rv.spec);
   for (int t = threadIdx.x; t < 2 * n1 * H; t += blockDim.x) {
     const int cy = fH.div(t);
@@ -1105,23 +1124,47 @@ __global__ void __launch_bounds__(512) k_slab_inv(const RveDev* __restrict__ rvs
   }
   cx<T>* res = line_fft<1, T, BIG, NF>(L.b0, L.b1, n1, 2 * H, L.ay, L.dc);
   cx<T>* oth = (res == L.b0) ? L.b1 : L.b0;
-  // z-line y: Z_z = A_z + i B_z, Z_{n2-k} = conj(A_k) + i conj(B_k)
-  for (int t = threadIdx.x; t < n1 * n2; t += blockDim.x) {
-    const int y = fn2.div(t);
-    const int z = t - y * n2;
-    cx<T> Zv;
-    if (z < H) {
-      const cx<T> A = res[z * n1 + y], B = res[(H + z) * n1 + y];
-      Zv = cx<T>{A.re - B.im, A.im + B.re};
-    } else {
-      const int k = n2 - z;
-      const cx<T> A = res[k * n1 + y], B = res[(H + k) * n1 + y];
-      Zv = cx<T>{A.re + B.im, -A.im + B.re};
+  // z-line y (at y * n2): Z_z = A_z + i B_z, Z_{n2-k} = conj(A_k) + i conj(B_k)
+  cx<T>* res2;
+  if constexpr (NF > 0) {
+    // the pair Z_j, Z_(n2-j) that the z transform takes together needs only
+    // A_j and B_j: the packing is folded into the transform's loads (no
+    // pass of its own)
+    direct_dft_io<1, T, NF>(
+        n1, L.az,
+        [&](int y) {
+          const cx<T> A = res[y], B = res[H * n1 + y];
+          return cx<T>{A.re - B.im, A.im + B.re};
+        },
+        [&](int y, int j, cx<T>& a, cx<T>& b) {
+          const cx<T> A = res[j * n1 + y], B = res[(H + j) * n1 + y];
+          a = cx<T>{A.re - B.im, A.im + B.re};
+          b = cx<T>{A.re + B.im, -A.im + B.re};
+        },
+        [&](int y, int k, cx<T> xk, cx<T> xm) {
+          oth[y * n2 + k] = xk;
+          if (k > 0) oth[y * n2 + NF - k] = xm;
+        });
+    __syncthreads();
+    res2 = oth;
+  } else {
+    for (int t = threadIdx.x; t < n1 * n2; t += blockDim.x) {
+      const int y = fn2.div(t);
+      const int z = t - y * n2;
+      cx<T> Zv;
+      if (z < H) {
+        const cx<T> A = res[z * n1 + y], B = res[(H + z) * n1 + y];
+        Zv = cx<T>{A.re - B.im, A.im + B.re};
+      } else {
+        const int k = n2 - z;
+        const cx<T> A = res[k * n1 + y], B = res[(H + k) * n1 + y];
+        Zv = cx<T>{A.re + B.im, -A.im + B.re};
+      }
+      oth[t] = Zv;
     }
-    oth[t] = Zv;
+    __syncthreads();
+    res2 = line_fft<1, T, BIG, NF>(oth, res, n2, n1, L.az, L.dc);
   }
-  __syncthreads();
-  cx<T>* res2 = line_fft<1, T, BIG, NF>(oth, res, n2, n1, L.az, L.dc);
   double dot = 0.0;
   if (cg_out) {
     // x += alpha p, r -= alpha G:(C:p) on the tile's two components, partials of r.r

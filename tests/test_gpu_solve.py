@@ -8,6 +8,7 @@ import pytest
 import synth
 from oracle import j2, solver as S
 from tests.gpu_util import m2t, rel_err, t2m, tensor6, to_dev, to_host
+from tests.fixtures import load_golden
 
 pytestmark = pytest.mark.gpu
 
@@ -129,11 +130,13 @@ def test_natural_stopping_agrees_with_oracle():
 
 def test_literal_algorithm_without_predictor():
     print("solve predictor NONE", flush=True)
+    lam = load_golden("laminate_sec5_1.txt")  # the paper's laminate setting (Sec. 5.1)
     ph = synth.laminate(11, 4)
-    elastic = (0.833, 0.386, 1e30, 0.0, 1.0)
-    plastic = (0.833, 0.386, 0.01 * 0.386, 0.05 * 0.386, 1.0)
-    w = synth.Workload("lam_lit", ph, [elastic, plastic], synth.shear_xy(0.05), 1, 1e-6, 1e-12)
-    s = S.Solver(ph, w.materials, 1e-6, 1e-12, predictor="none")
+    G = 0.386
+    elastic = (0.833, G, 1e30, 0.0, 1.0)
+    plastic = (0.833, G, lam["sigma0_over_G"] * G, lam["H_over_G"] * G, 1.0)
+    w = synth.Workload("lam_lit", ph, [elastic, plastic], synth.shear_xy(lam["E12"]), 1, lam["eta_newton"], 1e-12)
+    s = S.Solver(ph, w.materials, lam["eta_newton"], 1e-12, predictor="none")
     st_ref = s.solve_increment(w.E_at(1))
     from paper_1601_05970_amd import fftg
     pl, h, stats = _run_gpu(w, _opts(w, predictor=fftg.FFTG_PREDICTOR_NONE))

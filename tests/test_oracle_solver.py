@@ -10,6 +10,7 @@ import synth
 from oracle import j2, solver as S
 from oracle.dense import newton_step_exact
 from oracle.projection import apply_G
+from tests.fixtures import load_golden
 
 
 def test_homogeneous_material_returns_applied_strain():
@@ -76,11 +77,13 @@ def test_laminate_matches_closed_form():
 def test_literal_algorithm_on_laminate_with_elastic_phase():
     """The paper's laminate setting (phase 2 linear elastic, Sec. 5.1) with
     Algorithm 1 as printed: one increment reaches the closed-form solution."""
+    lam = load_golden("laminate_sec5_1.txt")
     ph = synth.laminate(11, 4)
-    elastic = (0.833, 0.386, 1e30, 0.0, 1.0)        # never yields
-    plastic = (0.833, 0.386, 0.01 * 0.386, 0.05 * 0.386, 1.0)
-    s = S.Solver(ph, [elastic, plastic], 1e-6, 1e-12, predictor="none")
-    E12 = 0.05
+    G = 0.386
+    elastic = (0.833, G, 1e30, 0.0, 1.0)        # never yields
+    plastic = (0.833, G, lam["sigma0_over_G"] * G, lam["H_over_G"] * G, 1.0)
+    s = S.Solver(ph, [elastic, plastic], lam["eta_newton"], 1e-12, predictor="none")
+    E12 = lam["E12"]
     st = s.solve_increment(synth.shear_xy(E12))
     assert st.converged
 

@@ -1093,11 +1093,25 @@ __global__ void __launch_bounds__(512) k_slab_inv(const RveDev* __restrict__ rvs
       });
   const CgPeek pk = cg_peek(cg);
   const double pa = (cg_out && fold) ? thread_partials(part, ntz) : 0.0;
+  // the two voxels whose CG update this thread takes first: in the 31-point
+  // builds those of its first z-transform task (z-line y, pair k and n2 - k),
+  // else voxels t and t + blockDim of the plane
   const int t1 = (int)threadIdx.x + (int)blockDim.x;
+  constexpr int Hq = (NF + 1) / 2;  // z-transform tasks per line (31-point builds)
+  long long va, vb;
+  if constexpr (NF > 0) {
+    const int tq = min((int)threadIdx.x, n1 * Hq - 1);
+    const int yq = tq / Hq, kq = tq - yq * Hq;
+    va = v0 + (long long)yq * n2 + kq;
+    vb = v0 + (long long)yq * n2 + (kq == 0 ? 0 : n2 - kq);
+  } else {
+    va = v0 + min((int)threadIdx.x, npl - 1);
+    vb = v0 + min(t1, npl - 1);
+  }
   double xv0[2], rv0[2], pv0[2], xv1[2], rv1[2], pv1[2];
   if (cg_out) {
-    const long long v = v0 + min((int)threadIdx.x, npl - 1);
-    const long long w = v0 + min(t1, npl - 1);
+    const long long v = va;
+    const long long w = vb;
     const FFTG_GLOBAL double* gx = gmem((const double*)rv.buf[R_X]);
     const FFTG_GLOBAL double* gr = gmem((const double*)rv.buf[R_R]);
     const FFTG_GLOBAL double* gp = gmem((const double*)rv.buf[p_role]);
@@ -1124,12 +1138,34 @@ __global__ void __launch_bounds__(512) k_slab_inv(const RveDev* __restrict__ rvs
   }
   cx<T>* res = line_fft<1, T, BIG, NF>(L.b0, L.b1, n1, 2 * H, L.ay, L.dc);
   cx<T>* oth = (res == L.b0) ? L.b1 : L.b0;
+  // x += alpha p, r -= alpha G:(C:p) at voxel v on the tile's two
+  // components, and the r.r partial (CG form)
+  double dot = 0.0;
+  FFTG_GLOBAL double* __restrict__ xx = gmem((double*)rv.buf[R_X]);
+  FFTG_GLOBAL double* __restrict__ rr = gmem((double*)rv.buf[R_R]);
+  const FFTG_GLOBAL double* __restrict__ pg = gmem((const double*)rv.buf[p_role]);
+  auto update = [&](long long v, cx<T> w, const double* xv, const double* rv2, const double* pv) {
+    const double r0 = rv2[0] - alpha * double(w.re), r1 = rv2[1] - alpha * double(w.im);
+    xx[c0 * nvox + v] = xv[0] + alpha * pv[0];
+    xx[c1 * nvox + v] = xv[1] + alpha * pv[1];
+    rr[c0 * nvox + v] = r0;
+    rr[c1 * nvox + v] = r1;
+    dot += r0 * r0 + r1 * r1;
+  };
+  auto update_load = [&](long long v, cx<T> w) {
+    const double xv[2] = {xx[c0 * nvox + v], xx[c1 * nvox + v]};
+    const double rv2[2] = {rr[c0 * nvox + v], rr[c1 * nvox + v]};
+    const double pv[2] = {pg[c0 * nvox + v], pg[c1 * nvox + v]};
+    update(v, w, xv, rv2, pv);
+  };
   // z-line y (at y * n2): Z_z = A_z + i B_z, Z_{n2-k} = conj(A_k) + i conj(B_k)
-  cx<T>* res2;
+  cx<T>* res2 = oth;
+  bool updated = false;  // the CG update already done inside the z transform
   if constexpr (NF > 0) {
     // the pair Z_j, Z_(n2-j) that the z transform takes together needs only
-    // A_j and B_j: the packing is folded into the transform's loads (no
-    // pass of its own)
+    // A_j and B_j: the packing is folded into the transform's loads; and the
+    // thread that forms the outputs z = k and n2 - k of line y applies the
+    // CG update to those two voxels at once (no pass of its own for either)
     direct_dft_io<1, T, NF>(
         n1, L.az,
         [&](int y) {
@@ -1142,11 +1178,22 @@ __global__ void __launch_bounds__(512) k_slab_inv(const RveDev* __restrict__ rvs
           b = cx<T>{A.re + B.im, -A.im + B.re};
         },
         [&](int y, int k, cx<T> xk, cx<T> xm) {
-          oth[y * n2 + k] = xk;
-          if (k > 0) oth[y * n2 + NF - k] = xm;
+          if (cg_out) {
+            const long long v_a = v0 + (long long)y * n2 + k, v_b = v0 + (long long)y * n2 + (NF - k);
+            if (y * Hq + k == (int)threadIdx.x) {  // this thread's first task: inputs prefetched
+              update(v_a, xk, xv0, rv0, pv0);
+              if (k > 0) update(v_b, xm, xv1, rv1, pv1);
+            } else {
+              update_load(v_a, xk);
+              if (k > 0) update_load(v_b, xm);
+            }
+          } else {
+            oth[y * n2 + k] = xk;
+            if (k > 0) oth[y * n2 + NF - k] = xm;
+          }
         });
-    __syncthreads();
-    res2 = oth;
+    updated = cg_out;
+    if (!cg_out) __syncthreads();
   } else {
     for (int t = threadIdx.x; t < n1 * n2; t += blockDim.x) {
       const int y = fn2.div(t);
@@ -1165,30 +1212,11 @@ __global__ void __launch_bounds__(512) k_slab_inv(const RveDev* __restrict__ rvs
     __syncthreads();
     res2 = line_fft<1, T, BIG, NF>(oth, res, n2, n1, L.az, L.dc);
   }
-  double dot = 0.0;
   if (cg_out) {
-    // x += alpha p, r -= alpha G:(C:p) on the tile's two components, partials of r.r
-    FFTG_GLOBAL double* __restrict__ xx = gmem((double*)rv.buf[R_X]);
-    FFTG_GLOBAL double* __restrict__ rr = gmem((double*)rv.buf[R_R]);
-    const FFTG_GLOBAL double* __restrict__ p = gmem((const double*)rv.buf[p_role]);
-    auto update = [&](int t, const double* xv, const double* rv2, const double* pv) {
-      const long long v = v0 + t;
-      const cx<T> w = res2[t];
-      const double r0 = rv2[0] - alpha * double(w.re), r1 = rv2[1] - alpha * double(w.im);
-      xx[c0 * nvox + v] = xv[0] + alpha * pv[0];
-      xx[c1 * nvox + v] = xv[1] + alpha * pv[1];
-      rr[c0 * nvox + v] = r0;
-      rr[c1 * nvox + v] = r1;
-      dot += r0 * r0 + r1 * r1;
-    };
-    if ((int)threadIdx.x < npl) update(threadIdx.x, xv0, rv0, pv0);
-    if (t1 < npl) update(t1, xv1, rv1, pv1);
-    for (int t = t1 + blockDim.x; t < npl; t += blockDim.x) {
-      const long long v = v0 + t;
-      const double xv[2] = {xx[c0 * nvox + v], xx[c1 * nvox + v]};
-      const double rv2[2] = {rr[c0 * nvox + v], rr[c1 * nvox + v]};
-      const double pv[2] = {p[c0 * nvox + v], p[c1 * nvox + v]};
-      update(t, xv, rv2, pv);
+    if (!updated) {
+      if ((int)threadIdx.x < npl) update(va, res2[threadIdx.x], xv0, rv0, pv0);
+      if (t1 < npl) update(vb, res2[t1], xv1, rv1, pv1);
+      for (int t = t1 + blockDim.x; t < npl; t += blockDim.x) update_load(v0 + t, res2[t]);
     }
     const double s = block_sum_last(dot, L.red);
     put_partials(&s, 1, rv.partial_rr, rv.tiles[P_ZI], tile);

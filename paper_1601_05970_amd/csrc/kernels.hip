@@ -1026,13 +1026,31 @@ __global__ void __launch_bounds__(512) k_slab_fwd(const RveDev* __restrict__ rvs
     }
   }
   __syncthreads();
-  cx<T>* res2 = line_fft<-1, T, BIG, NF>(yl, yl == L.b0 ? L.b1 : L.b0, n1, 2 * H, L.ay, L.dc);
   FFTG_GLOBAL cx<T>* spec = gmem((cx<T>*)rv.spec);
-  for (int t = threadIdx.x; t < 2 * n1 * H; t += blockDim.x) {
-    const int cy = fH.div(t);
-    const int k = t - cy * H;
-    const int c2 = fn1.div(cy), y = cy - c2 * n1;
-    gstore(spec + (2 * pr + c2) * nspec + ((long long)x * n1 + y) * H + k, res2[(c2 * H + k) * n1 + y]);
+  if constexpr (NF > 0) {
+    // y transform of y-line c2 * H + kz; the thread that forms outputs
+    // ky = k and n1 - k stores them to the spectrum at once (no pass of its
+    // own: lanes of a wave cover four kz at sixteen ky, runs of 64 bytes)
+    direct_dft_io<-1, T, NF>(
+        2 * H, L.ay, [&](int l) { return yl[l * n1]; },
+        [&](int l, int j, cx<T>& a, cx<T>& b) {
+          a = yl[l * n1 + j];
+          b = yl[l * n1 + NF - j];
+        },
+        [&](int l, int k, cx<T> xk, cx<T> xm) {
+          const int c2 = l >= H ? 1 : 0, kz = l - c2 * H;
+          FFTG_GLOBAL cx<T>* o = spec + (2 * pr + c2) * nspec + (long long)x * n1 * H + kz;
+          gstore(o + (long long)k * H, xk);
+          if (k > 0) gstore(o + (long long)(NF - k) * H, xm);
+        });
+  } else {
+    cx<T>* res2 = line_fft<-1, T, BIG, NF>(yl, yl == L.b0 ? L.b1 : L.b0, n1, 2 * H, L.ay, L.dc);
+    for (int t = threadIdx.x; t < 2 * n1 * H; t += blockDim.x) {
+      const int cy = fH.div(t);
+      const int k = t - cy * H;
+      const int c2 = fn1.div(cy), y = cy - c2 * n1;
+      gstore(spec + (2 * pr + c2) * nspec + ((long long)x * n1 + y) * H + k, res2[(c2 * H + k) * n1 + y]);
+    }
   }
   if (want_norm || update_p) {
     const double s = block_sum_last(nrm, L.red);

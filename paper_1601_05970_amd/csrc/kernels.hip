@@ -642,13 +642,31 @@ __global__ void __launch_bounds__(256) k_xpass(const RveDev* __restrict__ rvs, i
     for (int c = 0; c < 6; ++c) res[(c * nh + hh) * ld + x] = v[c];
   }
   __syncthreads();
-  cx<T>* res2 = line_fft<1, T, BIG, NF>(res, oth, ld, nl, L.ax, L.dc);
-  for (int t = threadIdx.x; t < 6 * n0 * nh; t += blockDim.x) {
-    const int cx_ = fxn.div(t);
-    const int r = t - cx_ * n0 * nh;
-    const int x = fnh.div(r);
-    const int hh = r - x * nh;
-    gstore(spec + cx_ * nspec + x * rs + off + hh, res2[(cx_ * nh + hh) * ld + x]);
+  if constexpr (NF > 0) {
+    // inverse x transform of line c * nh + hh; the thread that forms outputs
+    // x = k and n0 - k stores them to the spectrum at once (no pass of its
+    // own; the runs are nh frequencies long, as in the general store)
+    direct_dft_io<1, T, NF>(
+        nl, L.ax, [&](int l) { return res[l * ld]; },
+        [&](int l, int j, cx<T>& a, cx<T>& b) {
+          a = res[l * ld + j];
+          b = res[l * ld + NF - j];
+        },
+        [&](int l, int k, cx<T> xk, cx<T> xm) {
+          const int c = fnh.div(l), hh = l - c * nh;
+          FFTG_GLOBAL cx<T>* o = spec + c * nspec + off + hh;
+          gstore(o + k * rs, xk);
+          if (k > 0) gstore(o + (NF - k) * rs, xm);
+        });
+  } else {
+    cx<T>* res2 = line_fft<1, T, BIG, NF>(res, oth, ld, nl, L.ax, L.dc);
+    for (int t = threadIdx.x; t < 6 * n0 * nh; t += blockDim.x) {
+      const int cx_ = fxn.div(t);
+      const int r = t - cx_ * n0 * nh;
+      const int x = fnh.div(r);
+      const int hh = r - x * nh;
+      gstore(spec + cx_ * nspec + x * rs + off + hh, res2[(cx_ * nh + hh) * ld + x]);
+    }
   }
 }
 

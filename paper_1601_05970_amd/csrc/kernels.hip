@@ -1011,6 +1011,16 @@ __global__ void __launch_bounds__(512) k_slab_fwd(const RveDev* __restrict__ rvs
     voxel_load<T>(v0 + t, nvox, in_mode, in, update_p, rres, pin, tan_mode, tang, phase, vi);
     process(vi, t);
   }
+  // the tile's partial (p.tau or ||tau||^2) is complete here: its per-wave
+  // sums go to LDS ahead of the barrier the transforms need anyway (slots 16
+  // on, clear of the CG step's, which other waves may still be reading), and
+  // thread 0 adds them at the end
+  const bool part_out = want_norm || update_p;
+  if (part_out) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) nrm += __shfl_xor(nrm, o, 64);
+    if ((threadIdx.x & 63) == 0) L.red[16 + (threadIdx.x >> 6)] = nrm;
+  }
   __syncthreads();
   // z transform of the packed lines, untangled into y-lines: component
   // 2pr + c2, frequency k -> line c2 * H + k
@@ -1070,9 +1080,11 @@ __global__ void __launch_bounds__(512) k_slab_fwd(const RveDev* __restrict__ rvs
       gstore(spec + (2 * pr + c2) * nspec + ((long long)x * n1 + y) * H + k, res2[(c2 * H + k) * n1 + y]);
     }
   }
-  if (want_norm || update_p) {
-    const double s = block_sum_last(nrm, L.red);
-    put_partials(&s, 1, rv.partial, rv.tiles[P_ZF], tile);
+  if (part_out && threadIdx.x == 0) {
+    const int nw = (blockDim.x + 63) >> 6;
+    double sp = 0.0;
+    for (int i = 0; i < nw; ++i) sp += L.red[16 + i];
+    put_partials(&sp, 1, rv.partial, rv.tiles[P_ZF], tile);
   }
 }
 
@@ -1540,7 +1552,7 @@ template <class T>
 static size_t slab_lds(int n1, int n2) {
   const int nd = n1 > n2 + 1 ? n1 : n2 + 1;
   return axis_lds_bytes<T>(n2) + axis_lds_bytes<T>(n1) + (size_t)2 * n1 * (n2 + 1) * sizeof(cx<T>) +
-         (size_t)(nd + 2) * sizeof(cx<T>) + 16 * sizeof(double) + 64;
+         (size_t)(nd + 2) * sizeof(cx<T>) + 32 * sizeof(double) + 64;
 }
 size_t lds_slab(int mixed, int n1, int n2) { return mixed ? slab_lds<float>(n1, n2) : slab_lds<double>(n1, n2); }
 size_t lds_x(int mixed, int lines, int n0) {

@@ -71,10 +71,37 @@ __device__ __forceinline__ int find_rve(const RveDev* __restrict__ rv, int nrve_
   return lo;
 }
 
+// One DPP move of a double (two 32-bit halves); lanes whose source is out of
+// the row, or whose row is masked off, read 0.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ double dpp_f64(double v) {
+  const long long b = __builtin_bit_cast(long long, v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, ROWS, 0xf, true);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, ROWS, 0xf, true);
+  return __builtin_bit_cast(double, ((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
+// Sum over the 64 lanes of a full wave, returned to every lane: an inclusive
+// scan within each row of 16 lanes (row shifts by 1, 2, 4, 8), then row 0's
+// and row 2's totals into rows 1 and 3, and rows 0-1's total into rows 2 and
+// 3 (row broadcasts of lanes 15 and 31), so that lane 63 holds the total; in
+// registers, with no trip through the LDS crossbar.  Fixed order, so every
+// wave of every tile adds the same values the same way.
+__device__ __forceinline__ double wave_sum(double v) {
+  v += dpp_f64<0x111, 0xf>(v);  // row_shr:1
+  v += dpp_f64<0x112, 0xf>(v);  // row_shr:2
+  v += dpp_f64<0x114, 0xf>(v);  // row_shr:4
+  v += dpp_f64<0x118, 0xf>(v);  // row_shr:8
+  v += dpp_f64<0x142, 0xa>(v);  // row_bcast:15 into rows 1 and 3
+  v += dpp_f64<0x143, 0xc>(v);  // row_bcast:31 into rows 2 and 3
+  const long long b = __builtin_bit_cast(long long, v);
+  const int lo = __builtin_amdgcn_readlane((int)b, 63), hi = __builtin_amdgcn_readlane((int)(b >> 32), 63);
+  return __builtin_bit_cast(double, ((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
 // Sum over the workgroup; result valid in thread 0.
 __device__ __forceinline__ double block_sum(double v, double* sh) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  v = wave_sum(v);
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   if (lane == 0) sh[w] = v;
   __syncthreads();
@@ -88,13 +115,12 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
 }
 
 // The same total, formed identically by every thread after a single barrier
-// (per-wave shuffle sums in sh[w], added in the same order as block_sum).
+// (per-wave sums in sh[w], added in the same order as block_sum).
 // Thread 0's flag travels in sh[8] and is returned to every thread: the
 // one value that another tile of the launch may change while this one runs.
 // The caller must not write sh[0..8] again before another barrier.
 __device__ __forceinline__ double block_total(double v, int flag0, double* sh, int& flag) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  v = wave_sum(v);
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   if (lane == 0) sh[w] = v;
   if (threadIdx.x == 0) sh[8] = flag0 ? 1.0 : 0.0;
@@ -109,8 +135,7 @@ __device__ __forceinline__ double block_total(double v, int flag0, double* sh, i
 // block_sum for the last reduction of a kernel: valid in thread 0, one
 // barrier (no later use of sh to protect).
 __device__ __forceinline__ double block_sum_last(double v, double* sh) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  v = wave_sum(v);
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   if (lane == 0) sh[w] = v;
   __syncthreads();
@@ -1017,8 +1042,7 @@ __global__ void __launch_bounds__(512) k_slab_fwd(const RveDev* __restrict__ rvs
   // thread 0 adds them at the end
   const bool part_out = want_norm || update_p;
   if (part_out) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) nrm += __shfl_xor(nrm, o, 64);
+    nrm = wave_sum(nrm);
     if ((threadIdx.x & 63) == 0) L.red[16 + (threadIdx.x >> 6)] = nrm;
   }
   __syncthreads();

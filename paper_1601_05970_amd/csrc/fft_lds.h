@@ -455,9 +455,10 @@ __device__ __forceinline__ void direct_dft(const cx<T>* line, cx<T>* scratch, in
 }
 
 // In-LDS FFT of nl lines of length P.N, DIR = -1 forward, +1 inverse
-// (unnormalised); NF > 0 unrolls the direct DFT for lines of NF points.  line and scratch each hold nl lines of stride ld >= N;
-// dc holds nl scratch slots (Rader only).  Returns the buffer holding the
-// result (line or scratch).  Must be called by the whole workgroup.
+// (unnormalised); NF > 0 compiles only the unrolled direct DFT of NF-point
+// lines.  line and scratch each hold nl lines of stride ld >= N; dc holds
+// nl scratch slots (Rader only).  Returns the buffer holding the result
+// (line or scratch).  Must be called by the whole workgroup.
 template <int DIR, class T, int BIG, int NF = 0>
 __device__ cx<T>* line_fft(cx<T>* line, cx<T>* scratch, int ld, int nl, const AxisLds<T>& P, cx<T>* dc) {
   if constexpr (NF > 0) {

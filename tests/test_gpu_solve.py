@@ -1,5 +1,6 @@
 """GPU parity of the full Newton--CG increment (Algorithm 1) against the FP64
 oracle, closed forms and invariants; checkpoint, batch and error paths."""
+import functools
 import math
 
 import numpy as np
@@ -148,6 +149,30 @@ def test_literal_algorithm_without_predictor():
 def test_mixed_precision_agrees_with_fp64_oracle(slab, monkeypatch):
     monkeypatch.setenv("FFTG_SLAB", slab)
     _mixed_vs_oracle()
+
+
+@functools.lru_cache(maxsize=None)
+def _oracle_random31_mixed_case():
+    w = synth.small_random((31, 31, 31), 0.35, 11, E_eq=0.01, n_inc=5)
+    s = S.Solver(w.phase, w.materials, 1e-10, 1e-10)
+    st_ref = [s.solve_increment(w.E_at(n)) for n in range(1, 3)]
+    return w, s, st_ref
+
+
+@pytest.mark.parametrize("slab", ["0", "2"])
+def test_mixed_precision_31_point_builds_agree_with_fp64_oracle(slab, monkeypatch):
+    """Mixed precision at 31^3, where the CG product runs in the FP32 kernels
+    built for 31-point lines (five passes, or the slab passes with their
+    folded untangle, packing and CG update): two increments agree with the
+    FP64 oracle at the FP32 product's level."""
+    monkeypatch.setenv("FFTG_SLAB", slab)
+    print("solve mixed 31^3, slab", slab, flush=True)
+    from paper_1601_05970_amd import fftg
+    w, s, st_ref = _oracle_random31_mixed_case()
+    pl, h, stats = _run_gpu(w, _opts(w, precision=fftg.FFTG_MIXED, tol_newton=1e-10, tol_cg=1e-10), n_inc=2)
+    f = _fields(h)
+    assert rel_err(np.array(stats[-1]["Sigma"]), np.array(tensor6(st_ref[-1].Sigma))) < 1e-6
+    assert rel_err(f["strain"], t2m(s.strain())) < 1e-6
 
 
 def _mixed_vs_oracle():

@@ -51,7 +51,9 @@ typedef enum {
   FFTG_E_HIP = -3,            /* a HIP runtime call failed */
   FFTG_E_NOT_CONVERGED = -4,  /* Newton or CG iteration cap reached; stats filled */
   FFTG_E_BREAKDOWN = -5,      /* CG met p.Ap <= 0 or not finite (indefinite tangent); stats filled */
-  FFTG_E_UNSUPPORTED = -6     /* grid extent or material law not implemented */
+  FFTG_E_UNSUPPORTED = -6,    /* grid extent or material law not implemented */
+  FFTG_E_NONFINITE = -7       /* the stress or the Newton update became NaN or infinite
+                                 (e.g. a non-finite strain handed in); stats filled */
 } fftg_status;
 
 typedef enum { FFTG_FP64 = 0, FFTG_MIXED = 1 } fftg_precision;
@@ -100,6 +102,9 @@ typedef struct {
   int converged;                      /* 1 when the Newton test was met (or lockstep done) */
   int total_cg;                       /* sum of cg_iters */
   double seconds;                     /* wall time of the call */
+  double rel_equilibrium;             /* ||G sigma|| / ||sigma|| at the committed state: how far
+                                         the result is from nodal equilibrium (Eq.
+                                         nodal_equilibrium_equations); 0 when sigma = 0 */
 } fftg_stats;
 
 typedef struct fftg_plan_s* fftg_plan;

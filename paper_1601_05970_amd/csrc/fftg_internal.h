@@ -131,4 +131,48 @@ struct LaunchCfg {
   int n0max, n1max, n2max;  // largest extents of the launch (LDS table sizing)
 };
 
+// Sizes of the RVEs a launch covers, from which the launch configuration is
+// chosen (host).
+struct GridSum {
+  int n0 = 1, n1 = 1, n2 = 1;      // maxima over members
+  long long rows = 0;               // sum of n0*n1
+  long long yl = 0;                 // sum of 6*n0 (y-line groups per h)
+  long long xl = 0;                 // sum of n1
+  long long hmax = 1;
+  long long vox = 0;
+  int big = 0;
+  int direct31 = 7;                 // bit a: every member's axis a is the 31-point direct DFT
+};
+
+// Host side (runtime.cpp): the heuristic launch configuration and the tile
+// counts of every pass of one RVE under it.
+LaunchCfg choose_cfg(const GridSum& gs);
+void compute_tiles(const LaunchCfg& c, int n0, int n1, int n2, long long nvox, int tiles[P_NPASS]);
+
+// Host side (kernels.hip): LDS bytes of the pass kernels and their launchers.
+size_t lds_z(int mixed, int rows, int n2);
+size_t lds_y(int mixed, int lines, int n1);
+size_t lds_x(int mixed, int lines, int n0);
+size_t lds_slab(int mixed, int n1, int n2);
+hipError_t launch_zfwd(int mixed, const RveDev* rv, int nrve, int tiles, const LaunchCfg& cfg, size_t lds,
+                       int in_mode, int in_role, int tan_mode, int want_norm, int check_done, int update_p,
+                       hipStream_t s);
+hipError_t launch_ypass(int mixed, int dir, const RveDev* rv, int nrve, int tiles, const LaunchCfg& cfg,
+                        size_t lds, int check_done, hipStream_t s);
+hipError_t launch_xpass(int mixed, const RveDev* rv, int nrve, int tiles, const LaunchCfg& cfg, size_t lds,
+                        double scale, int check_done, hipStream_t s);
+hipError_t launch_zinv(int mixed, const RveDev* rv, int nrve, int tiles, const LaunchCfg& cfg, size_t lds,
+                       int out_mode, int out_role, int check_done, int p_role, hipStream_t s);
+hipError_t launch_slab_fwd(int mixed, const RveDev* rv, int nrve, int tiles, const LaunchCfg& cfg, size_t lds,
+                           int in_mode, int in_role, int tan_mode, int want_norm, int check_done, int update_p,
+                           int p_in, int p_out, hipStream_t s);
+hipError_t launch_slab_inv(int mixed, const RveDev* rv, int nrve, int tiles, const LaunchCfg& cfg, size_t lds,
+                           int out_mode, int out_role, int check_done, int p_role, hipStream_t s);
+hipError_t launch_newton_update(const RveDev* rv, int nrve, int tiles, const LaunchCfg& cfg, hipStream_t s);
+hipError_t launch_finalize(const RveDev* rv, int nrve, int step, hipStream_t s);
+hipError_t launch_constitutive(int mixed, const RveDev* rv, int nrve, int tiles, const LaunchCfg& cfg,
+                               int eps_role, int commit, hipStream_t s);
+hipError_t launch_cg_setup(const RveDev* rv, int nrve, double eta2, double floor2, int max_iter, int force,
+                           hipStream_t s);
+
 }  // namespace fftg

@@ -19,32 +19,6 @@
 
 using namespace fftg;
 
-namespace fftg {
-size_t lds_z(int mixed, int rows, int n2);
-size_t lds_y(int mixed, int lines, int n1);
-size_t lds_x(int mixed, int lines, int n0);
-hipError_t launch_zfwd(int mixed, const RveDev* rv, int nrve, int tiles, const LaunchCfg& cfg, size_t lds,
-                       int in_mode, int in_role, int tan_mode, int want_norm, int check_done, int update_p,
-                       hipStream_t s);
-hipError_t launch_ypass(int mixed, int dir, const RveDev* rv, int nrve, int tiles, const LaunchCfg& cfg,
-                        size_t lds, int check_done, hipStream_t s);
-hipError_t launch_xpass(int mixed, const RveDev* rv, int nrve, int tiles, const LaunchCfg& cfg, size_t lds,
-                        double scale, int check_done, hipStream_t s);
-hipError_t launch_zinv(int mixed, const RveDev* rv, int nrve, int tiles, const LaunchCfg& cfg, size_t lds,
-                       int out_mode, int out_role, int check_done, int p_role, hipStream_t s);
-size_t lds_slab(int mixed, int n1, int n2);
-hipError_t launch_slab_fwd(int mixed, const RveDev* rv, int nrve, int tiles, const LaunchCfg& cfg, size_t lds,
-                           int in_mode, int in_role, int tan_mode, int want_norm, int check_done, int update_p,
-                           int p_in, int p_out, hipStream_t s);
-hipError_t launch_slab_inv(int mixed, const RveDev* rv, int nrve, int tiles, const LaunchCfg& cfg, size_t lds,
-                           int out_mode, int out_role, int check_done, int p_role, hipStream_t s);
-hipError_t launch_newton_update(const RveDev* rv, int nrve, int tiles, const LaunchCfg& cfg, hipStream_t s);
-hipError_t launch_finalize(const RveDev* rv, int nrve, int step, hipStream_t s);
-hipError_t launch_constitutive(int mixed, const RveDev* rv, int nrve, int tiles, const LaunchCfg& cfg,
-                               int eps_role, int commit, hipStream_t s);
-hipError_t launch_cg_setup(const RveDev* rv, int nrve, double eta2, double floor2, int max_iter, int force,
-                           hipStream_t s);
-}  // namespace fftg
 
 // ------------------------------------------------------------------ errors
 static thread_local std::string g_err;
@@ -53,6 +27,8 @@ static fftg_status fail(fftg_status st, const std::string& msg) {
   g_err = msg;
   return st;
 }
+
+void fftg_set_last_error(const char* msg) { g_err = msg; }
 
 #define HIP_TRY(expr)                                                                       \
   do {                                                                                      \
@@ -352,18 +328,7 @@ static int threads_for(long long points) {
   return points <= 192 ? 64 : (points <= 640 ? 128 : 256);
 }
 
-struct GridSum {
-  int n0 = 1, n1 = 1, n2 = 1;      // maxima over members
-  long long rows = 0;               // sum of n0*n1
-  long long yl = 0;                 // sum of 6*n0 (y-line groups per h)
-  long long xl = 0;                 // sum of n1
-  long long hmax = 1;
-  long long vox = 0;
-  int big = 0;
-  int direct31 = 7;                 // bit a: every member's axis a is the 31-point direct DFT
-};
-
-static LaunchCfg choose_cfg(const GridSum& gs) {
+LaunchCfg fftg::choose_cfg(const GridSum& gs) {
   LaunchCfg c;
   const size_t budget = (size_t)env_long("FFTG_LDS_KB", 128, 1) * 1024;
   const long long kMinTiles = env_long("FFTG_MIN_TILES", 2048, 1);
@@ -399,7 +364,7 @@ static LaunchCfg choose_cfg(const GridSum& gs) {
   return c;
 }
 
-static void compute_tiles(const LaunchCfg& c, int n0, int n1, int n2, long long nvox, int tiles[P_NPASS]) {
+void fftg::compute_tiles(const LaunchCfg& c, int n0, int n1, int n2, long long nvox, int tiles[P_NPASS]) {
   const int H = (n2 + 1) / 2;
   const int rows = n0 * n1;
   if (c.slab) {
@@ -807,9 +772,12 @@ static void group_totals(Group& g) {
 // r.r) run inside the consumer kernels when every one of their tiles can
 // total the producer's partials cheaply: the L2 reads of that redundant sum
 // grow as (forward-pass tiles) x (inverse-pass tiles).  Larger RVEs use
-// k_finalize.
+// k_finalize.  FFTG_FOLD_MAX overrides the bound (0 sends every RVE through
+// k_finalize; read when descriptors are uploaded).
 constexpr long long kFoldMax = 1LL << 23;
-static bool fold_ok(const RveDev& rv) { return (long long)rv.tiles[P_ZF] * rv.tiles[P_ZI] <= kFoldMax; }
+static bool fold_ok(const RveDev& rv, long long fold_max) {
+  return (long long)rv.tiles[P_ZF] * rv.tiles[P_ZI] <= fold_max;
+}
 
 // Uploads the host descriptors (stream-ordered, through a pinned slot).
 static fftg_status group_upload(Group& g) {
@@ -819,9 +787,10 @@ static fftg_status group_upload(Group& g) {
   HIP_TRY(hipEventSynchronize(g.ev[slot]));
   char* st = reinterpret_cast<char*>(g.h_pinned) + slot * desc_bytes(n);
   g.need_fin = false;
+  const long long fold_max = env_long("FFTG_FOLD_MAX", kFoldMax, 0);
   for (size_t i = 0; i < n; ++i) {
     RveDev& rv = g.h[i];
-    rv.fold = fold_ok(rv) ? 1 : 0;
+    rv.fold = fold_ok(rv, fold_max) ? 1 : 0;
     if (!rv.skip && !rv.fold) g.need_fin = true;
   }
   memcpy(st, g.h.data(), n * sizeof(RveDev));
@@ -897,7 +866,6 @@ static fftg_status enqueue_apply(Group& g, int mixed, int in_mode, int in_role, 
 }
 
 static fftg_status enqueue_cg_iters(Group& g, int iters) {
-  const int nr = (int)g.h.size();
   for (int i = 0; i < iters; ++i) {
     // p <- r + beta p is fused into the first pass of the product.  The slab
     // passes own two components of a voxel per tile, so p alternates between
@@ -1093,7 +1061,13 @@ static fftg_status group_increment(Group& g, const double* dE_tensor, const int*
         mr[i].stats->total_cg += c.iters;
       }
       mr[i].newton += 1;
-      if (c.status == CG_BREAKDOWN) {
+      // a non-finite stress (seen in ||sigma||^2 of the residual product) or
+      // Newton update ends the member's solve: no later iteration recovers
+      const bool nonfinite = !std::isfinite(c.dnorm2) || (!pred_step && !std::isfinite(c.snorm2));
+      if (nonfinite) {
+        mr[i].err = FFTG_E_NONFINITE;
+        mr[i].active = false;
+      } else if (c.status == CG_BREAKDOWN) {
         mr[i].err = FFTG_E_BREAKDOWN;
         mr[i].active = false;
       } else if (!lockstep && !pred_step && res <= o.tol_newton) {
@@ -1120,17 +1094,27 @@ static fftg_status group_increment(Group& g, const double* dE_tensor, const int*
   PROF_LAUNCH(FFTG_KERNEL_CONSTITUTIVE,
               launch_constitutive(g.mixed, g.d, nr, g.total[P_VEC], g.cfg, R_EPS_FL, 1, g.stream));
   PROF_LAUNCH(FFTG_KERNEL_FINALIZE, launch_finalize(g.d, nr, FIN_SIGMA, g.stream));
+  // equilibrium of the committed state: ||G sigma|| and ||sigma|| from one
+  // FP64 identity product in residual form (it overwrites x, r and p, which
+  // the next Newton iteration sets up again)
+  st = enqueue_apply(g, 0, IN_ROLE, R_SIG, TAN_IDENTITY, 1, OUT_RESIDUAL, R_R, -1.0, 0);
+  if (st != FFTG_OK) return st;
   st = read_states(g);
   if (st != FFTG_OK) return st;
   const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   fftg_status ret = FFTG_OK;
   for (size_t i = 0; i < n; ++i) {
     g.hists[i]->inc += 1;
+    const CgState& c = g.h_cg[i];
+    bool finite = std::isfinite(c.snorm2) && std::isfinite(c.bnorm2);
+    for (int k = 0; k < 6; ++k) finite = finite && std::isfinite(c.Sigma[k]);
+    if (!finite && mr[i].err == FFTG_OK) mr[i].err = FFTG_E_NONFINITE;
     if (mr[i].stats) {
       mr[i].stats->newton_iters = mr[i].newton;
-      mandel_to_tensor(g.h_cg[i].Sigma, mr[i].stats->Sigma);
+      mandel_to_tensor(c.Sigma, mr[i].stats->Sigma);
       mr[i].stats->converged = mr[i].converged ? 1 : 0;
       mr[i].stats->seconds = secs;
+      mr[i].stats->rel_equilibrium = c.snorm2 > 0.0 ? std::sqrt(c.bnorm2 / c.snorm2) : 0.0;
     }
     if (ret == FFTG_OK) {
       if (mr[i].err != FFTG_OK)
@@ -1140,6 +1124,7 @@ static fftg_status group_increment(Group& g, const double* dE_tensor, const int*
     }
   }
   if (ret == FFTG_E_BREAKDOWN) g_err = "CG breakdown (p.Ap <= 0 or not finite)";
+  if (ret == FFTG_E_NONFINITE) g_err = "non-finite stress or Newton update";
   if (ret == FFTG_E_NOT_CONVERGED) g_err = "Newton iteration cap reached";
   return ret;
 }

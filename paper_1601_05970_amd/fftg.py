@@ -22,6 +22,7 @@ FFTG_E_HIP = -3
 FFTG_E_NOT_CONVERGED = -4
 FFTG_E_BREAKDOWN = -5
 FFTG_E_UNSUPPORTED = -6
+FFTG_E_NONFINITE = -7
 
 FFTG_FP64 = 0
 FFTG_MIXED = 1
@@ -60,13 +61,15 @@ class fftg_options(C.Structure):
 class fftg_stats(C.Structure):
     _fields_ = [("newton_iters", C.c_int), ("cg_iters", C.c_int * FFTG_MAX_NEWTON),
                 ("newton_res", C.c_double * FFTG_MAX_NEWTON), ("Sigma", C.c_double * 6),
-                ("converged", C.c_int), ("total_cg", C.c_int), ("seconds", C.c_double)]
+                ("converged", C.c_int), ("total_cg", C.c_int), ("seconds", C.c_double),
+                ("rel_equilibrium", C.c_double)]
 
     def to_dict(self):
         n = min(self.newton_iters, FFTG_MAX_NEWTON)
         return {"newton_iters": self.newton_iters, "cg_iters": list(self.cg_iters[:n]),
                 "newton_res": list(self.newton_res[:n]), "Sigma": list(self.Sigma),
-                "converged": bool(self.converged), "total_cg": self.total_cg, "seconds": self.seconds}
+                "converged": bool(self.converged), "total_cg": self.total_cg, "seconds": self.seconds,
+                "rel_equilibrium": self.rel_equilibrium}
 
 
 _lib = None

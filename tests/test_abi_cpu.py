@@ -54,4 +54,4 @@ def test_struct_layouts_match_header():
     import ctypes as C
     from paper_1601_05970_amd import fftg
     assert C.sizeof(fftg.fftg_material) == 40
-    assert C.sizeof(fftg.fftg_stats) == 4 + 4 * 64 + 4 + 8 * 64 + 8 * 6 + 4 + 4 + 8
+    assert C.sizeof(fftg.fftg_stats) == 4 + 4 * 64 + 4 + 8 * 64 + 8 * 6 + 4 + 4 + 8 + 8

@@ -3,6 +3,8 @@
 The library is called through its C ABI (ctypes binding); the oracle applies
 G with numpy FFTs and the explicit four-index G^ of Appendix A.
 """
+import functools
+
 import numpy as np
 import pytest
 
@@ -175,6 +177,100 @@ def _compatible(shape, seed):
             e = np.fft.ifftn(0.5 * (gi * uh[j] + gj * uh[i])).real
             out[i, j] = out[j, i] = e
     return out
+
+
+@functools.lru_cache(maxsize=1)
+def _oracle_127_products():
+    """The oracle's G and G:(Ce:p) of one random symmetric field at 127^3."""
+    shape = (127, 127, 127)
+    p = synth.random_sym_tensor_field(shape, 127)
+    ph = synth.bernoulli(shape, 0.4, 127)
+    K, G, _, _, _ = j2.material_fields(ph, MATS2)
+    return p, ph, t2m(apply_G(p)), t2m(apply_G(j2.ddot42(j2.elastic_stiffness(K, G), p)))
+
+
+MATS2 = [(0.833, 0.386, 0.003, 0.004, 1.0), (2.0, 1.3, 0.006, 0.008, 1.0)]
+
+
+@pytest.mark.timeout(600)
+def test_full_size_127_products_match_oracle():
+    """127^3 (Rader's algorithm on every axis, the full-size tile and LDS
+    configuration), random incompatible input, element by element against
+    the oracle: the projection and the elastic-tangent product, FP64 and the
+    FP32 product."""
+    import torch
+    from paper_1601_05970_amd import fftg
+    print("apply 127^3 vs oracle", flush=True)
+    p, ph, ref_g, ref_c = _oracle_127_products()
+    d_in = to_dev(t2m(p))
+    for prec, tol, dt in ((fftg.FFTG_FP64, 1e-12, torch.float64), (fftg.FFTG_MIXED, 3e-6, torch.float32)):
+        pl = _plan(p.shape[2:], ph, MATS2, precision=prec)
+        for mode, ref in ((fftg.FFTG_TANGENT_IDENTITY, ref_g), (fftg.FFTG_TANGENT_ELASTIC, ref_c)):
+            d_out = pl.field(dtype=dt)
+            pl.apply_GK(d_in, d_out, mode)
+            err = rel_err(to_host(d_out), ref)
+            print("  precision", prec, "mode", mode, "rel err %.2e" % err, flush=True)
+            assert err < tol
+            del d_out
+        del pl
+        torch.cuda.empty_cache()
+
+
+def _ghat_at(k):
+    """G^(k) for an integer frequency k with |k_i| <= 3, taken from the
+    oracle's four-index G^ on a 7^3 grid: G^ depends on the direction of
+    xi = k / L only (degree-0 homogeneous), so for cubic cells it is the
+    same at that k on any grid."""
+    from oracle.projection import ghat
+    G = ghat((7, 7, 7))
+    return G[(slice(None),) * 4 + tuple(int(c) % 7 for c in k)]
+
+
+# frequency, seed of the complex symmetric amplitude
+MODES = [((0, 0, 0), 1), ((1, 0, 0), 2), ((0, -2, 1), 3), ((3, 1, -2), 4), ((-1, 3, 3), 5), ((2, -3, 1), 6)]
+
+
+@pytest.mark.timeout(600)
+def test_full_size_255_projection_of_fourier_modes():
+    """255^3 (Rader's algorithm over 254-point chains, five passes, the
+    largest plan): the input is a sum of a few Fourier modes
+    Re(T_k exp(2 pi i k.x / 255)), whose projection is Re((G^(k):T_k)
+    exp(2 pi i k.x / 255)) in closed form (Appendix A, Eq. FT_projection;
+    the constant mode is removed, G^(0) = 0).  Checked element by element,
+    FP64 and FP32 product."""
+    import torch
+    from paper_1601_05970_amd import fftg
+    shape = (255, 255, 255)
+    print("apply 255^3 Fourier modes", flush=True)
+    x = [np.arange(n, dtype=np.float64) for n in shape]
+    tau = np.zeros((3, 3) + shape)
+    ref = np.zeros((3, 3) + shape)
+    for k, seed in MODES:
+        rng = np.random.default_rng(seed)
+        A = rng.standard_normal((3, 3)) + 1j * rng.standard_normal((3, 3))
+        T = 0.5 * (A + A.T)
+        GT = np.einsum("ijlm,lm->ij", _ghat_at(k), T)
+        ph = (2.0 * np.pi * k[0] / shape[0] * x[0])[:, None, None] + \
+             (2.0 * np.pi * k[1] / shape[1] * x[1])[None, :, None] + \
+             (2.0 * np.pi * k[2] / shape[2] * x[2])[None, None, :]
+        c, s = np.cos(ph), np.sin(ph)
+        for i in range(3):
+            for j in range(3):
+                tau[i, j] += T[i, j].real * c - T[i, j].imag * s
+                ref[i, j] += GT[i, j].real * c - GT[i, j].imag * s
+        del ph, c, s
+    d_in = to_dev(t2m(tau))
+    del tau
+    ref = t2m(ref)
+    for prec, tol, dt in ((fftg.FFTG_FP64, 1e-11, torch.float64), (fftg.FFTG_MIXED, 3e-6, torch.float32)):
+        pl = _plan(shape, np.zeros(shape, np.uint8), precision=prec)
+        d_out = pl.field(dtype=dt)
+        pl.apply_GK(d_in, d_out, fftg.FFTG_TANGENT_IDENTITY)
+        err = rel_err(to_host(d_out), ref)
+        print("  precision", prec, "rel err %.2e" % err, flush=True)
+        assert err < tol
+        del d_out, pl
+        torch.cuda.empty_cache()
 
 
 @pytest.mark.parametrize("shape", [(127, 127, 127), (255, 255, 255)])

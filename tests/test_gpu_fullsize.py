@@ -27,14 +27,15 @@ def _opts(w):
     return o
 
 
-def test_random31_fp64_lockstep_first_increments():
+@pytest.mark.timeout(900)
+def test_random31_fp64_lockstep_all_increments():
     from paper_1601_05970_amd import fftg
     w = synth.random_31()
     print("full size", w.name, w.shape, flush=True)
     s = S.Solver(w.phase, w.materials, w.tol_newton, w.tol_cg)
     pl = fftg.Plan(w.phase, w.materials, _opts(w))
     h = fftg.History(pl)
-    for n in (1, 2, 3):
+    for n in range(1, w.n_inc + 1):
         ref = s.solve_increment(w.E_at(n))
         st = h.solve_increment(tensor6(w.dE(n)), ref.cg_iters)
         print("increment", n, "cg", st["cg_iters"], flush=True)
@@ -92,3 +93,62 @@ def test_voronoi127_mixed_invariants_and_sampled_return_map():
     assert rel_err(eb[idx], eb_new) < 1e-12
     ep = m2t(to_host(h.get_field(fftg.FFTG_FIELD_EPS_P)))
     assert rel_err(ep[(slice(None), slice(None)) + idx], ep_new) < 1e-12
+
+
+@pytest.mark.timeout(900)
+def test_batch_member_63_lockstep_with_oracle():
+    """A 63^3 member of the 64-RVE batch alone, in lockstep with the oracle
+    over its first three increments: at this size the CG scalar steps run in
+    k_finalize (the product of forward and inverse tiles exceeds the fold
+    bound), which is how every 63^3 member of the batch solves."""
+    from paper_1601_05970_amd import fftg
+    w = synth.batch_rve(0)
+    print("full size", w.name, w.shape, flush=True)
+    s = S.Solver(w.phase, w.materials, w.tol_newton, w.tol_cg)
+    pl = fftg.Plan(w.phase, w.materials, _opts(w))
+    h = fftg.History(pl)
+    for n in (1, 2, 3):
+        ref = s.solve_increment(w.E_at(n))
+        st = h.solve_increment(tensor6(w.dE(n)), ref.cg_iters)
+        print("increment", n, "cg", st["cg_iters"], flush=True)
+        assert st["cg_iters"] == ref.cg_iters
+        assert rel_err(to_host(h.get_field(fftg.FFTG_FIELD_STRAIN)), t2m(s.strain())) < 1e-10
+        assert rel_err(to_host(h.get_field(fftg.FFTG_FIELD_STRESS)), t2m(s.sigma)) < 1e-10
+    assert np.max(s.epbar) > 0
+    assert rel_err(to_host(h.get_field(fftg.FFTG_FIELD_EPBAR))[0], s.epbar) < 1e-10
+
+
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_batch_of_config_sizes_equals_alone(precision):
+    """Members of the 64-RVE batch recipe at its three sizes (63^3, 15^3,
+    31^3) batched and alone over four increments, in FP64 and with the FP32
+    product: batched launches give each member the result it gets alone (FP64
+    to 1e-10 with identical CG counts; mixed to the FP32 product's level)."""
+    from paper_1601_05970_amd import fftg
+    ws = [synth.batch_rve(r, precision=precision) for r in (0, 3, 6)]
+    print("batch vs alone", precision, [w.shape for w in ws], flush=True)
+    n_inc = 4
+    alone = []
+    for w in ws:
+        pl = fftg.Plan(w.phase, w.materials, _opts(w))
+        h = fftg.History(pl)
+        st = [h.solve_increment(tensor6(w.dE(n))) for n in range(1, n_inc + 1)]
+        alone.append(([to_host(h.get_field(k)) for k in (fftg.FFTG_FIELD_STRAIN, fftg.FFTG_FIELD_EPBAR)], st))
+        h.close()
+        pl.close()
+    plans = [fftg.Plan(w.phase, w.materials, _opts(w)) for w in ws]
+    hists = [fftg.History(p) for p in plans]
+    b = fftg.Batch(plans, hists)
+    for n in range(1, n_inc + 1):
+        st = b.solve_increment(np.array([tensor6(w.dE(n)) for w in ws]))
+        print("increment", n, "cg", [s_["cg_iters"] for s_ in st], flush=True)
+        for i in range(len(ws)):
+            if precision == "fp64":
+                assert st[i]["cg_iters"] == alone[i][1][n - 1]["cg_iters"]
+    tol = 1e-10 if precision == "fp64" else 1e-6
+    for i, h in enumerate(hists):
+        got = [to_host(h.get_field(k)) for k in (fftg.FFTG_FIELD_STRAIN, fftg.FFTG_FIELD_EPBAR)]
+        assert rel_err(got[0], alone[i][0][0]) < tol
+        assert rel_err(got[1], alone[i][0][1]) < tol * 10
+    b.close()

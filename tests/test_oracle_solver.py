@@ -100,6 +100,31 @@ def test_literal_algorithm_on_laminate_with_elastic_phase():
     assert np.max(np.abs(eps[0, 1][ph == 1] - e12(tau, plastic))) < 1e-10 * E12
 
 
+def test_literal_algorithm_stalls_where_the_tangent_predictor_converges():
+    """Why the first Newton iteration of an increment is a tangent predictor.
+    On the 11^3 two-phase elasto-plastic laminate (both phases plastic), the
+    second increment of Algorithm 1 as printed starts from the return map at
+    E_new + eps*_old: the whole strain increment lands in every voxel, the
+    hard layers yield spuriously, and the Newton corrections grow instead of
+    shrinking, then cycle without converging.  The predictor, which solves the
+    linearised load step about the last converged state first, converges in
+    two iterations, to the laminate's closed form."""
+    w = synth.laminate_11()
+    lit = S.Solver(w.phase, w.materials, w.tol_newton, w.tol_cg, predictor="none", max_newton=30)
+    prd = S.Solver(w.phase, w.materials, w.tol_newton, w.tol_cg, predictor="tangent", max_newton=30)
+    assert lit.solve_increment(w.E_at(1)).converged
+    assert prd.solve_increment(w.E_at(1)).converged
+    st = lit.solve_increment(w.E_at(2))
+    assert not st.converged and st.newton_iters == 30
+    # the corrections grow at first and never fall below the first one
+    assert st.newton_res[1] > st.newton_res[0] > 1.0
+    assert min(st.newton_res[1:]) > st.newton_res[0]
+    sp = prd.solve_increment(w.E_at(2))
+    assert sp.converged and sp.newton_iters == 2
+    tau, _, _ = laminate_closed_form(w.E_at(2)[0, 1])
+    assert abs(sp.Sigma[0, 1] - tau) <= 1e-10 * tau
+
+
 @pytest.mark.parametrize("predictor", ["tangent", "none"])
 def test_converged_fields_are_compatible_zero_mean_and_equilibrated(predictor):
     w = synth.small_random((9, 7, 5), 0.4, 21, E_eq=0.006, n_inc=3)

@@ -215,6 +215,14 @@ fftg_status fftg_profiler_start(int kernel_id);
  * bracketed launches only; fftg_profiler_seen gives all of them. */
 fftg_status fftg_profiler_start_every(int kernel_id, int every);
 fftg_status fftg_profiler_stop(double* total_ms, long long* launches, double* voxels);
+/* As fftg_profiler_start_every for every kind whose bit (1 << kernel_id) is
+ * set in kernel_mask (nonzero, below 1 << FFTG_KERNEL_COUNT), sampled per
+ * kind; stop and seen then report the sums over those kinds. */
+fftg_status fftg_profiler_start_set(unsigned kernel_mask, int every);
+/* Totals of one kind from the last run, valid after fftg_profiler_stop:
+ * summed time of its bracketed launches (ms), their count, the voxels they
+ * covered, and all its launches (bracketed or not); any output may be NULL. */
+fftg_status fftg_profiler_kind(int kernel_id, double* ms, long long* launches, double* voxels, long long* seen);
 /* Launches of the profiled kind since the last start, bracketed or not
  * (kept after stop until the next start). */
 long long fftg_profiler_seen(void);

@@ -575,24 +575,32 @@ void fftg_history_destroy(fftg_history h) {
 }
 
 // ------------------------------------------------------------- profiler
-// Brackets launches of one kernel kind with HIP events (process-wide).
-struct Profiler {
-  int kid = -1;
-  std::vector<hipEvent_t> pool;   // 2 per recorded launch
-  size_t used = 0;
-  double voxels = 0.0;
+// Brackets launches of a set of kernel kinds with HIP events (process-wide),
+// one launch in `every` of each kind, with the times and counts kept per
+// kind.
+struct ProfKind {
+  double ms = 0.0;         // summed over the bracketed launches (filled at stop)
+  double voxels = 0.0;     // voxels the bracketed launches covered
   long long launches = 0;  // bracketed
   long long seen = 0;      // all launches of the kind
-  int every = 1;           // bracket one launch in every
+};
+struct Profiler {
+  unsigned mask = 0;              // kinds being profiled (bit = fftg_kernel_id)
+  unsigned last_mask = 0;         // kinds of the last run (readable after stop)
+  std::vector<hipEvent_t> pool;   // 2 per recorded launch
+  std::vector<int> kind_of;       // kind of each recorded pair
+  size_t used = 0;
+  int every = 1;                  // bracket one launch in every (per kind)
+  ProfKind k[FFTG_KERNEL_COUNT];
 };
 static Profiler g_prof;
 static std::mutex g_prof_mutex;
 
 static int prof_begin(int kid, hipStream_t s) {
-  if (g_prof.kid != kid) return -1;  // racy read is benign: profiling is off or on for one kind
+  if (!(g_prof.mask & (1u << kid))) return -1;  // racy read is benign: the mask is off or on
   std::lock_guard<std::mutex> lk(g_prof_mutex);
-  if (g_prof.kid != kid) return -1;
-  if (g_prof.seen++ % g_prof.every != 0) return -1;
+  if (!(g_prof.mask & (1u << kid))) return -1;
+  if (g_prof.k[kid].seen++ % g_prof.every != 0) return -1;
   if (g_prof.used + 2 > g_prof.pool.size()) {
     for (int i = 0; i < 64; ++i) {
       // timing-only events: no system-scope fence (cache write-back and
@@ -605,6 +613,8 @@ static int prof_begin(int kid, hipStream_t s) {
   }
   const int idx = (int)g_prof.used;
   g_prof.used += 2;
+  if (g_prof.kind_of.size() < g_prof.used / 2) g_prof.kind_of.resize(g_prof.used / 2);
+  g_prof.kind_of[idx / 2] = kid;
   hipEventRecord(g_prof.pool[idx], s);
   return idx;
 }
@@ -613,44 +623,70 @@ static void prof_end(int idx, hipStream_t s, double voxels) {
   if (idx < 0) return;
   std::lock_guard<std::mutex> lk(g_prof_mutex);
   hipEventRecord(g_prof.pool[idx + 1], s);
-  g_prof.launches += 1;
-  g_prof.voxels += voxels;
+  ProfKind& k = g_prof.k[g_prof.kind_of[idx / 2]];
+  k.launches += 1;
+  k.voxels += voxels;
+}
+
+fftg_status fftg_profiler_start_set(unsigned kernel_mask, int every) {
+  if (kernel_mask == 0 || (kernel_mask >> FFTG_KERNEL_COUNT) != 0) return fail(FFTG_E_INVALID, "bad kernel mask");
+  if (every < 1) return fail(FFTG_E_INVALID, "every must be >= 1");
+  std::lock_guard<std::mutex> lk(g_prof_mutex);
+  g_prof.used = 0;
+  g_prof.every = every;
+  for (auto& k : g_prof.k) k = ProfKind{};
+  g_prof.last_mask = kernel_mask;
+  g_prof.mask = kernel_mask;
+  return FFTG_OK;
 }
 
 fftg_status fftg_profiler_start_every(int kernel_id, int every) {
   if (kernel_id < 0 || kernel_id >= FFTG_KERNEL_COUNT) return fail(FFTG_E_INVALID, "bad kernel id");
-  if (every < 1) return fail(FFTG_E_INVALID, "every must be >= 1");
-  std::lock_guard<std::mutex> lk(g_prof_mutex);
-  g_prof.kid = kernel_id;
-  g_prof.used = 0;
-  g_prof.voxels = 0.0;
-  g_prof.launches = 0;
-  g_prof.seen = 0;
-  g_prof.every = every;
-  return FFTG_OK;
+  return fftg_profiler_start_set(1u << kernel_id, every);
 }
 
 fftg_status fftg_profiler_start(int kernel_id) { return fftg_profiler_start_every(kernel_id, 1); }
 
 long long fftg_profiler_seen(void) {
   std::lock_guard<std::mutex> lk(g_prof_mutex);
-  return g_prof.seen;
+  long long n = 0;
+  for (int i = 0; i < FFTG_KERNEL_COUNT; ++i)
+    if (g_prof.last_mask & (1u << i)) n += g_prof.k[i].seen;
+  return n;
 }
 
 fftg_status fftg_profiler_stop(double* total_ms, long long* launches, double* voxels) {
   std::lock_guard<std::mutex> lk(g_prof_mutex);
-  double tot = 0.0;
+  g_prof.mask = 0;
   for (size_t i = 0; i + 1 < g_prof.used; i += 2) {
     HIP_TRY(hipEventSynchronize(g_prof.pool[i + 1]));
     float ms = 0.f;
     HIP_TRY(hipEventElapsedTime(&ms, g_prof.pool[i], g_prof.pool[i + 1]));
-    tot += ms;
+    g_prof.k[g_prof.kind_of[i / 2]].ms += ms;
   }
-  if (total_ms) *total_ms = tot;
-  if (launches) *launches = g_prof.launches;
-  if (voxels) *voxels = g_prof.voxels;
-  g_prof.kid = -1;
   g_prof.used = 0;
+  double tot = 0.0, vox = 0.0;
+  long long n = 0;
+  for (int i = 0; i < FFTG_KERNEL_COUNT; ++i)
+    if (g_prof.last_mask & (1u << i)) {
+      tot += g_prof.k[i].ms;
+      n += g_prof.k[i].launches;
+      vox += g_prof.k[i].voxels;
+    }
+  if (total_ms) *total_ms = tot;
+  if (launches) *launches = n;
+  if (voxels) *voxels = vox;
+  return FFTG_OK;
+}
+
+fftg_status fftg_profiler_kind(int kernel_id, double* ms, long long* launches, double* voxels, long long* seen) {
+  if (kernel_id < 0 || kernel_id >= FFTG_KERNEL_COUNT) return fail(FFTG_E_INVALID, "bad kernel id");
+  std::lock_guard<std::mutex> lk(g_prof_mutex);
+  const ProfKind& k = g_prof.k[kernel_id];
+  if (ms) *ms = k.ms;
+  if (launches) *launches = k.launches;
+  if (voxels) *voxels = k.voxels;
+  if (seen) *seen = k.seen;
   return FFTG_OK;
 }
 

@@ -41,6 +41,7 @@ EXPORTS = [
     "fftg_get_field", "fftg_set_field", "fftg_history_get_E", "fftg_history_save", "fftg_history_restore",
     "fftg_footprint_bytes", "fftg_batch_create", "fftg_batch_destroy", "fftg_batch_solve_increment",
     "fftg_profiler_start", "fftg_profiler_start_every", "fftg_profiler_stop", "fftg_profiler_seen",
+    "fftg_profiler_start_set", "fftg_profiler_kind",
     "fftg_last_error",
 ]
 FFTG_KERNEL_ZFWD, FFTG_KERNEL_Y_FWD, FFTG_KERNEL_X_PROJ, FFTG_KERNEL_Y_INV, FFTG_KERNEL_ZINV = range(5)
@@ -121,13 +122,16 @@ def lib():
     L.fftg_profiler_seen.argtypes = []
     L.fftg_profiler_seen.restype = C.c_longlong
     L.fftg_profiler_stop.argtypes = [dp, C.POINTER(C.c_longlong), dp]
+    L.fftg_profiler_start_set.argtypes = [C.c_uint, ip]
+    L.fftg_profiler_kind.argtypes = [ip, dp, C.POINTER(C.c_longlong), dp, C.POINTER(C.c_longlong)]
     L.fftg_last_error.argtypes = []
     L.fftg_last_error.restype = C.c_char_p
     for name in ("fftg_plan_create", "fftg_history_create", "fftg_solve_increment", "fftg_apply_GK",
                  "fftg_eval_constitutive", "fftg_get_field", "fftg_set_field", "fftg_history_get_E",
                  "fftg_history_save", "fftg_history_restore", "fftg_batch_create",
                  "fftg_batch_solve_increment", "fftg_profiler_start", "fftg_profiler_start_every",
-                 "fftg_profiler_stop"):
+                 "fftg_profiler_stop", "fftg_profiler_start_set",
+                 "fftg_profiler_kind"):
         getattr(L, name).restype = C.c_int
     _lib = L
     return L
@@ -180,6 +184,20 @@ def fftg_profiler_start_every(kernel_id: int, every: int):
 
 def fftg_profiler_seen() -> int:
     return int(lib().fftg_profiler_seen())
+
+
+def fftg_profiler_start_set(kernel_ids, every: int):
+    mask = 0
+    for k in kernel_ids:
+        mask |= 1 << int(k)
+    check(lib().fftg_profiler_start_set(mask, every))
+
+
+def fftg_profiler_kind(kernel_id: int):
+    """(ms, bracketed launches, voxels, all launches) of one kind after stop."""
+    ms, n, vox, seen = C.c_double(), C.c_longlong(), C.c_double(), C.c_longlong()
+    check(lib().fftg_profiler_kind(kernel_id, C.byref(ms), C.byref(n), C.byref(vox), C.byref(seen)))
+    return ms.value, n.value, vox.value, seen.value
 
 
 def fftg_profiler_stop():

@@ -229,6 +229,30 @@ long long fftg_profiler_seen(void);
 
 const char* fftg_last_error(void);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * product of fftg_apply_GK in its IDENTITY or ELASTIC form, FP64, without a
+ * plan and without any allocation.  d_out = G:(C:d_in) on an n0 x n1 x n2
+ * grid, C = identity or the elastic stiffness Ce of each voxel's phase.
+ * d_in, d_out: device double, 6 planes each (layout as everywhere above),
+ * caller-owned, non-aliasing, on the current device.  ELASTIC: d_phase is
+ * the device phase map (n0*n1*n2 bytes, ids < n_phases: not checked, the map
+ * stays on the device), mats a host array of n_phases <= 16 entries (K, G
+ * used); IDENTITY ignores both (may be NULL).  hip_stream: a stream of the
+ * current device or NULL.  Asynchronous.
+ * Work memory: one static device array of 16 MiB per device (held until the
+ * process ends), holding the descriptor, the FFT root tables and the half
+ * spectrum; grids whose half spectrum (6 n0 n1 (n2+1)/2 complex doubles)
+ * exceeds 16 MiB - 64 KiB (63^3 fits, 75^3 does not) give FFTG_E_INVALID,
+ * extents that need Rader's algorithm (primes above 53 and other extents
+ * above 64 without a 3/5/7/11/13/17 factorisation) FFTG_E_UNSUPPORTED.
+ * Every call on a device shares that device's array: calls that overlap on
+ * one device (several streams or threads) race and must be serialised by
+ * the caller.  Each call rewrites everything it reads from the array. */
+fftg_status fftg_apply_GK_noalloc(int n0, int n1, int n2, const double* d_in, double* d_out, fftg_tangent_mode mode,
+                                  const uint8_t* d_phase, int n_phases, const fftg_material* mats,
+                                  void* hip_stream);
+
 #ifdef __cplusplus
 }
 #endif

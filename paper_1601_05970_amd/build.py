@@ -30,7 +30,7 @@ COMMON = [
     f"-I{os.path.join(ROOT, 'include')}", f"-I{CSRC}",
 ]
 
-SOURCES = ["kernels.hip", "runtime.cpp"]
+SOURCES = ["kernels.hip", "runtime.cpp", "noalloc.hip"]
 
 
 def _run(cmd):

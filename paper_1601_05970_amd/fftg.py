@@ -42,7 +42,7 @@ EXPORTS = [
     "fftg_footprint_bytes", "fftg_batch_create", "fftg_batch_destroy", "fftg_batch_solve_increment",
     "fftg_profiler_start", "fftg_profiler_start_every", "fftg_profiler_stop", "fftg_profiler_seen",
     "fftg_profiler_start_set", "fftg_profiler_kind",
-    "fftg_last_error",
+    "fftg_last_error", "fftg_apply_GK_noalloc",
 ]
 FFTG_KERNEL_ZFWD, FFTG_KERNEL_Y_FWD, FFTG_KERNEL_X_PROJ, FFTG_KERNEL_Y_INV, FFTG_KERNEL_ZINV = range(5)
 FFTG_KERNEL_FINALIZE, FFTG_KERNEL_CONSTITUTIVE, FFTG_KERNEL_NEWTON = range(5, 8)
@@ -124,13 +124,14 @@ def lib():
     L.fftg_profiler_stop.argtypes = [dp, C.POINTER(C.c_longlong), dp]
     L.fftg_profiler_start_set.argtypes = [C.c_uint, ip]
     L.fftg_profiler_kind.argtypes = [ip, dp, C.POINTER(C.c_longlong), dp, C.POINTER(C.c_longlong)]
+    L.fftg_apply_GK_noalloc.argtypes = [ip, ip, ip, vp, vp, ip, vp, ip, C.POINTER(fftg_material), vp]
     L.fftg_last_error.argtypes = []
     L.fftg_last_error.restype = C.c_char_p
     for name in ("fftg_plan_create", "fftg_history_create", "fftg_solve_increment", "fftg_apply_GK",
                  "fftg_eval_constitutive", "fftg_get_field", "fftg_set_field", "fftg_history_get_E",
                  "fftg_history_save", "fftg_history_restore", "fftg_batch_create",
                  "fftg_batch_solve_increment", "fftg_profiler_start", "fftg_profiler_start_every",
-                 "fftg_profiler_stop", "fftg_profiler_start_set",
+                 "fftg_profiler_stop", "fftg_apply_GK_noalloc", "fftg_profiler_start_set",
                  "fftg_profiler_kind"):
         getattr(L, name).restype = C.c_int
     _lib = L
@@ -252,6 +253,27 @@ class Plan:
         _check_field(d_in, self.shape, 6, "float64")
         _check_field(d_out, self.shape, 6, "float32" if self.mixed else "float64")
         check(lib().fftg_apply_GK(self.handle, hist.handle if hist else None, _dptr(d_in), _dptr(d_out), mode))
+
+
+def fftg_apply_GK_noalloc(d_in, d_out, mode=FFTG_TANGENT_IDENTITY, d_phase=None, materials=None, stream=None):
+    """fftg_apply_GK_noalloc: d_out = G:(C:d_in) in FP64 without a plan or a
+    device allocation (IDENTITY or ELASTIC); d_in, d_out (6,)+grid float64."""
+    shape = tuple(d_in.shape[1:])
+    _check_field(d_in, shape, 6, "float64")
+    _check_field(d_out, shape, 6, "float64")
+    if materials:
+        mats = (fftg_material * len(materials))(*[fftg_material(*[float(v) for v in m]) for m in materials])
+        nm = len(materials)
+    else:
+        mats, nm = None, 0
+    ph = None
+    if d_phase is not None:
+        if not (d_phase.is_cuda and d_phase.is_contiguous()) or tuple(d_phase.shape) != shape or \
+                str(d_phase.dtype) != "torch.uint8":
+            raise ValueError("d_phase must be a contiguous uint8 device tensor of the grid's shape")
+        ph = _dptr(d_phase)
+    check(lib().fftg_apply_GK_noalloc(shape[0], shape[1], shape[2], _dptr(d_in), _dptr(d_out), mode, ph, nm,
+                                      mats, _stream_handle(stream)))
 
 
 def _check_field(t, shape, ncomp, dtype):

@@ -13,9 +13,11 @@ on non-linear FFT-based micromechanical simulations" (arXiv:1601.05970):
   Appendix A (Eq. FT_projection); the reference Green operator Gamma^ref of
   Appendix A (Eq. Gamma_explicit); dense DFT and projection matrices of
   Appendix B for brute-force checks on tiny grids.
-* ``j2`` -- the elasto-plastic J2 model of Sec. 4.2: backward-Euler elastic
-  predictor / plastic corrector and the consistent tangent, as full
-  fourth-order tensors.
+* ``j2`` -- the elasto-plastic J2 model of Sec. 4.2 (power-law hardening):
+  backward-Euler elastic predictor / plastic corrector and the consistent
+  tangent, as full fourth-order tensors.
+* ``laws`` -- the non-linear elastic (Sec. 4.1) and visco-plastic (Sec. 4.3)
+  models, and the choice of law per voxel.
 * ``solver`` -- conjugate gradients on the linearised system
   (Eq. linear_system) and the incremental-iterative Newton loop of
   Algorithm 1.

@@ -40,7 +40,7 @@ from typing import List, Optional
 
 import numpy as np
 
-from . import j2
+from . import j2, laws
 from .projection import apply_G
 
 
@@ -110,13 +110,16 @@ class Solver:
 
     def __init__(self, phase, materials, tol_newton=1e-5, tol_cg=1e-8,
                  max_newton=50, max_cg=2000, zero_rhs_rel=1e-14,
-                 predictor: str = "tangent"):
+                 predictor: str = "tangent", dt: float = 1.0):
         self.phase = np.asarray(phase)
         self.shape = tuple(self.phase.shape)
         for n in self.shape:
             if n % 2 == 0 or n < 1:
                 raise ValueError("grid extents must be odd and positive")
-        self.K, self.G, self.sy0, self.H, _n = j2.material_fields(self.phase, materials)
+        self.materials = [tuple(m) for m in materials]
+        self.dt = dt  # real time step of every increment (rate-dependent laws, Sec. 4.3)
+        self.K, self.G, self.sy0, self.H, _n = j2.material_fields(self.phase, self.materials)
+        self.j2_only = bool(np.all(laws.material_rows(self.materials)[:, 5] == laws.LAW_J2))
         self.tol_newton = tol_newton
         self.tol_cg = tol_cg
         self.max_newton = max_newton
@@ -133,7 +136,8 @@ class Solver:
         self.increment = 0
         self.sigma = np.zeros(z)
         # consistent tangent at the last converged state (elastic initially)
-        self.C_last = j2.elastic_stiffness(self.K, self.G)
+        self.C_last = (j2.elastic_stiffness(self.K, self.G) if self.j2_only
+                       else laws.elastic_tangent(self.phase, self.materials))
 
     @property
     def nvox(self) -> int:
@@ -141,7 +145,7 @@ class Solver:
 
     def constitutive(self, eps_fl):
         eps = eps_fl + self.E[:, :, None, None, None]
-        return j2.return_map(eps, self.eps_p, self.epbar, self.K, self.G, self.sy0, self.H)
+        return laws.constitutive(self.phase, self.materials, eps, self.eps_p, self.epbar, self.dt)
 
     def _linear_step(self, C, b, force):
         """CG solve of G C d = b.
@@ -229,9 +233,9 @@ class Solver:
         return self.eps_fl + self.E[:, :, None, None, None]
 
 
-def run_workload(w, lockstep=None, n_inc=None, predictor="tangent"):
+def run_workload(w, lockstep=None, n_inc=None, predictor="tangent", dt=1.0):
     """Run the load path of a synth.Workload; returns (solver, [stats])."""
-    s = Solver(w.phase, w.materials, w.tol_newton, w.tol_cg, predictor=predictor)
+    s = Solver(w.phase, w.materials, w.tol_newton, w.tol_cg, predictor=predictor, dt=dt)
     out = []
     for n in range(1, (n_inc or w.n_inc) + 1):
         ls = None if lockstep is None else lockstep[n - 1]

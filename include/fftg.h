@@ -72,11 +72,32 @@ typedef enum {
  *   iteration starting from the return map at E_new + eps*. */
 typedef enum { FFTG_PREDICTOR_TANGENT = 0, FFTG_PREDICTOR_NONE = 1 } fftg_predictor;
 
-/* Isotropic J2 phase (Sec. 4.2, Eqs. model:plas:stress and model:plas:yield):
- * bulk modulus K > 0, shear modulus G > 0, initial yield stress
- * sigma_y0 > 0, hardening modulus H >= 0, hardening exponent n (only 1). */
+/* Constitutive law of a phase (Sec. 4). */
+typedef enum {
+  FFTG_LAW_J2 = 0,                /* elasto-plasticity, Sec. 4.2 */
+  FFTG_LAW_NONLINEAR_ELASTIC = 1, /* non-linear elasticity, Sec. 4.1 */
+  FFTG_LAW_VISCO = 2              /* visco-plasticity, Sec. 4.3 */
+} fftg_law;
+
+/* One phase.  Fields by law:
+ * J2 (Eqs. model:plas:stress, model:plas:yield): bulk modulus K > 0, shear
+ *   modulus G > 0, initial yield stress sigma_y0 > 0, hardening modulus
+ *   H >= 0, hardening exponent 0 < n <= 1 (n = 1: closed-form return; else
+ *   the scalar return equation is solved per voxel); eps0, t0 unused.
+ * NONLINEAR_ELASTIC (Eq. model:nlin:stress): K > 0, reference stress
+ *   sigma_y0 = sigma_0 > 0, reference strain eps0 > 0, exponent n >= 1; G > 0
+ *   only sets the ELASTIC product (fftg_apply_GK) of the phase; H unused.
+ *   Its tangent at zero strain has no deviatoric stiffness for n > 1, so
+ *   solves of such phases take FFTG_PREDICTOR_NONE.
+ * VISCO (Eq. model:visco:gammadot): K > 0, G > 0, sigma_y0 = sigma_0 > 0,
+ *   rate-sensitivity exponent 0 < n <= 1, eps0 > 0, t0 > 0 (gamma_0 =
+ *   eps0 / t0); the time step is fftg_options.dt; H unused.
+ * Other exponents give FFTG_E_UNSUPPORTED (the compact consistent tangent
+ * stores the rank-one term with one sign per phase). */
 typedef struct {
   double K, G, sigma_y0, H, n;
+  int law;            /* fftg_law */
+  double eps0, t0;
 } fftg_material;
 
 typedef struct {
@@ -90,6 +111,7 @@ typedef struct {
   double mixed_cg_floor;  /* MIXED only: effective eta_CG >= this, and the floor of the
                              FP32-evaluated predictor right-hand side (default 1e-5) */
   int cg_chunk;           /* CG iterations enqueued between host checks (default 16) */
+  double dt;              /* real time step of every increment, for VISCO phases (default 1) */
 } fftg_options;
 
 #define FFTG_MAX_NEWTON 64
@@ -113,7 +135,7 @@ typedef struct fftg_batch_s* fftg_batch;
 
 /* Fills *opt with defaults: FP64, tol_newton 1e-5, tol_cg 1e-8,
  * max_newton 50, max_cg 2000, TANGENT predictor, rhs_floor 1e-14,
- * mixed_cg_floor 1e-5, cg_chunk 16. */
+ * mixed_cg_floor 1e-5, cg_chunk 16, dt 1. */
 void fftg_options_default(fftg_options* opt);
 
 /* Creates a plan for one RVE (Sec. 2.3 grid, Sec. 4.2 phases).

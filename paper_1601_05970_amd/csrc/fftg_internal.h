@@ -49,8 +49,17 @@ struct AxisDev {
   const cx<float>* bi32;
 };
 
+// A phase on the device.  The elasto-plastic and visco-plastic laws share
+// one return equation, seq_tr - 3G dg - sy - Hh (a0 + dg)^n = 0, with
+// (sy, Hh, a0) = (sigma_y0, H, eps_p_bar) for J2 and (0, sigma_0 /
+// (gamma_0 dt)^n, 0) for Norton's rule integrated by backward Euler; the
+// non-linear elastic law uses sy = sigma_0 and e0 = eps_0.  csign is the sign
+// of the rank-one term of the compact tangent (-1 except non-linear
+// elasticity with n > 1).
+enum LawDev { LAW_J2 = 0, LAW_NLE = 1, LAW_VISCO = 2 };
 struct MatDev {
-  double K, G, sy0, H;
+  double K, G, sy, Hh, n, csign, e0;
+  int law, pad_;
 };
 
 // Per-RVE scalar state of the CG solve and the reductions.

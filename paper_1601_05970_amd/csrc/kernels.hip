@@ -197,14 +197,14 @@ __device__ __forceinline__ int done_publish(int v) {
 }
 
 // Compact consistent tangent applied to a Mandel vector:
-// tau = (K - g2/3) tr(p) [1,1,1,0,0,0] + g2 p - (m.p) m.
+// tau = (K - g2/3) tr(p) [1,1,1,0,0,0] + g2 p + csign (m.p) m.
 template <class T>
-__device__ __forceinline__ void tangent_apply(const T p[6], T K, T g2, const T m[6], T tau[6]) {
+__device__ __forceinline__ void tangent_apply(const T p[6], T K, T g2, const T m[6], T csign, T tau[6]) {
   const T tr = p[0] + p[1] + p[2];
-  const T mp = m[0] * p[0] + m[1] * p[1] + m[2] * p[2] + m[3] * p[3] + m[4] * p[4] + m[5] * p[5];
+  const T mp = csign * (m[0] * p[0] + m[1] * p[1] + m[2] * p[2] + m[3] * p[3] + m[4] * p[4] + m[5] * p[5]);
   const T lam = (K - g2 * T(1.0 / 3.0)) * tr;
 #pragma unroll
-  for (int c = 0; c < 6; ++c) tau[c] = g2 * p[c] - mp * m[c] + (c < 3 ? lam : T(0));
+  for (int c = 0; c < 6; ++c) tau[c] = g2 * p[c] + mp * m[c] + (c < 3 ? lam : T(0));
 }
 
 // G^(k) : T for a complex Mandel vector t, q = xi/|xi| (Appendix A):
@@ -406,7 +406,7 @@ __device__ __forceinline__ double voxel_compute(const VoxIn<T>& vi, long long v,
 #pragma unroll
       for (int c = 0; c < 6; ++c) m[c] = vi.m[c];
     }
-    tangent_apply<T>(p, T(mt.K), g2, m, tau);
+    tangent_apply<T>(p, T(mt.K), g2, m, T(mt.csign), tau);
   }
   double d = 0.0;
   if (update_p) {
@@ -423,7 +423,8 @@ __device__ __forceinline__ double voxel_compute(const VoxIn<T>& vi, long long v,
 __device__ __forceinline__ MatDev mats_fetch(const MatDev* mats, int n) {
   const int i = min((int)threadIdx.x, n - 1);
   const FFTG_GLOBAL double* m = gmem(&mats[i].K);
-  return MatDev{m[0], m[1], m[2], m[3]};
+  const FFTG_GLOBAL int* l = gmem(&mats[i].law);
+  return MatDev{m[0], m[1], m[2], m[3], m[4], m[5], m[6], l[0], 0};
 }
 __device__ __forceinline__ void mats_store(const MatDev& m, int n, MatDev* s_mats) {
   s_mats[min((int)threadIdx.x, n - 1)] = m;
@@ -1355,11 +1356,44 @@ __global__ void __launch_bounds__(256) k_newton_update(const RveDev* __restrict_
   put_partials(&s, 1, rv.partial, rv.tiles[P_VEC], tile);
 }
 
-// ------------------------------------------------ J2 return map (Sec. 4.2)
-// Trial state from the committed history; elastic when Phi_tr <= 0, else
-// closed-form dgamma = Phi_tr / (3G + H) (n = 1) along N = 3/2 s_tr/seq_tr.
-// Writes sigma (Mandel), the compact tangent {2G', m = sqrt(-c) N} with
-// 2G' = 2G (1 - 3G dgamma/seq_tr), c = 4G^2 (dgamma/seq_tr - 1/(3G+H)),
+// ------------------------------------------------ return maps (Sec. 4)
+// Root of f(dg) = seq - 3G dg - sy - Hh (a0 + dg)^n, n != 1, given
+// f(0) = phi > 0: f falls monotonically and f(phi / 3G) <= 0, so Newton's
+// method is kept inside the bracket [lo, hi] that every evaluation narrows
+// (a step that would leave it bisects instead), started from the right end
+// (where the derivative is finite even at a0 = 0).  Stops when the step is
+// below a few ulps of dg; slope returns 3G + n Hh (a0 + dg)^(n-1).
+__device__ double return_root(double seq, double a0, double G, double sy, double Hh, double n, double phi,
+                              double& slope) {
+  double lo = 0.0, hi = phi / (3.0 * G), x = hi;
+  for (int it = 0; it < 200; ++it) {
+    const double ax = a0 + x;
+    const double pw = pow(ax, n);
+    const double f = seq - 3.0 * G * x - sy - Hh * pw;
+    if (f > 0.0) lo = x;
+    else hi = x;
+    const double df = -3.0 * G - n * Hh * pw / ax;
+    double xn = x - f / df;
+    if (!(xn > lo && xn < hi)) xn = 0.5 * (lo + hi);
+    const bool done = fabs(xn - x) <= 4e-16 * x || !(hi - lo > 4e-16 * hi);
+    x = xn;
+    if (done) break;
+  }
+  slope = 3.0 * G + n * Hh * pow(a0 + x, n - 1.0);
+  return x;
+}
+
+// Per voxel, by the phase's law: trial state from the committed history;
+// elasto-plastic (Sec. 4.2): elastic when Phi_tr <= 0, else the return
+// equation (closed form dg = Phi_tr / (3G + H) for n = 1) along
+// N = 3/2 s_tr / seq_tr; visco-plastic (Sec. 4.3): the same equation with
+// sy = 0, Hh = sigma_0 / (gamma_0 dt)^n, a0 = 0, flowing whenever seq_tr > 0;
+// non-linear elastic (Sec. 4.1): sigma = K tr(eps) I + sigma_0 (eps_eq /
+// eps_0)^n N, N = 2/3 eps_d / eps_eq, no history.  Writes sigma (Mandel),
+// the compact tangent {2G', m} with C = K I(x)I + 2G' I_d + csign m (x) m:
+// inelastic 2G' = 2G (1 - 3G dg/seq_tr), m = sqrt(-c) N,
+// c = 4G^2 (dg/seq_tr - 1/slope); non-linear elastic 2G' = 2/3 s/eps_eq,
+// m = sqrt(|c|) N, c = (n - 1) s/eps_eq with s = sigma_0 (eps_eq/eps_0)^n;
 // and, when committing, the new history and per-tile sums of sigma.
 template <class TT>
 __global__ void __launch_bounds__(256) k_constitutive(const RveDev* __restrict__ rvs, int nrve, int vox_per_tile,
@@ -1398,35 +1432,67 @@ __global__ void __launch_bounds__(256) k_constitutive(const RveDev* __restrict__
     double dd = 0.0;
 #pragma unroll
     for (int c = 0; c < 6; ++c) dd += d[c] * d[c];
-    const double G = mt.G, K = mt.K;
-    const double seq = 2.0 * G * sqrt(1.5 * dd);
-    const double phi = seq - (mt.sy0 + mt.H * ebv);
+    const double G = mt.G, K = mt.K, n = mt.n;
     double sig[6], g2, m[6];
-    if (phi > 0.0) {
-      const double dg = phi / (3.0 * G + mt.H);
-      const double ns = 1.5 * 2.0 * G / seq;   // N = ns * d
-      double Nv[6];
+    if (mt.law == LAW_NLE) {
+      // no plastic strain: d is the strain deviator, tr its trace
+      const double eeq = sqrt((2.0 / 3.0) * dd);
+      if (eeq > 0.0) {
+        const double s = mt.sy * pow(eeq / mt.e0, n);
+        const double f = s / eeq;
+        const double sm = sqrt(fabs((n - 1.0) * f));
+        g2 = (2.0 / 3.0) * f;
 #pragma unroll
-      for (int c = 0; c < 6; ++c) Nv[c] = ns * d[c];
-      const double cc = 4.0 * G * G * (dg / seq - 1.0 / (3.0 * G + mt.H));
-      const double sm = sqrt(-cc);
-      g2 = 2.0 * G * (1.0 - 3.0 * G * dg / seq);
+        for (int c = 0; c < 6; ++c) {
+          const double Nc = (2.0 / 3.0) * d[c] / eeq;
+          sig[c] = s * Nc + (c < 3 ? K * tr : 0.0);
+          m[c] = sm * Nc;
+        }
+      } else {
+        g2 = n == 1.0 ? (2.0 / 3.0) * mt.sy / mt.e0 : 0.0;
 #pragma unroll
-      for (int c = 0; c < 6; ++c) {
-        sig[c] = 2.0 * G * (d[c] - dg * Nv[c]) + (c < 3 ? K * tr : 0.0);
-        m[c] = sm * Nv[c];
-      }
-      if (commit) {
-#pragma unroll
-        for (int c = 0; c < 6; ++c) ep[c * nvox + v] = epv[c] + dg * Nv[c];
-        eb[v] = ebv + dg;
+        for (int c = 0; c < 6; ++c) {
+          sig[c] = c < 3 ? K * tr : 0.0;
+          m[c] = 0.0;
+        }
       }
     } else {
-      g2 = 2.0 * G;
+      const double seq = 2.0 * G * sqrt(1.5 * dd);
+      const double a0 = mt.law == LAW_VISCO ? 0.0 : ebv;
+      const double hard = n == 1.0 ? mt.Hh * a0 : (a0 > 0.0 ? mt.Hh * pow(a0, n) : 0.0);
+      const double phi = seq - (mt.sy + hard);
+      if (phi > 0.0) {
+        double dg, slope;
+        if (n == 1.0) {
+          dg = phi / (3.0 * G + mt.Hh);
+          slope = 3.0 * G + mt.Hh;
+        } else {
+          dg = return_root(seq, a0, G, mt.sy, mt.Hh, n, phi, slope);
+        }
+        const double ns = 1.5 * 2.0 * G / seq;   // N = ns * d
+        double Nv[6];
 #pragma unroll
-      for (int c = 0; c < 6; ++c) {
-        sig[c] = 2.0 * G * d[c] + (c < 3 ? K * tr : 0.0);
-        m[c] = 0.0;
+        for (int c = 0; c < 6; ++c) Nv[c] = ns * d[c];
+        const double cc = 4.0 * G * G * (dg / seq - 1.0 / slope);
+        const double sm = sqrt(-cc);
+        g2 = 2.0 * G * (1.0 - 3.0 * G * dg / seq);
+#pragma unroll
+        for (int c = 0; c < 6; ++c) {
+          sig[c] = 2.0 * G * (d[c] - dg * Nv[c]) + (c < 3 ? K * tr : 0.0);
+          m[c] = sm * Nv[c];
+        }
+        if (commit) {
+#pragma unroll
+          for (int c = 0; c < 6; ++c) ep[c * nvox + v] = epv[c] + dg * Nv[c];
+          eb[v] = ebv + dg;
+        }
+      } else {
+        g2 = 2.0 * G;
+#pragma unroll
+        for (int c = 0; c < 6; ++c) {
+          sig[c] = 2.0 * G * d[c] + (c < 3 ? K * tr : 0.0);
+          m[c] = 0.0;
+        }
       }
     }
 #pragma unroll

@@ -189,10 +189,10 @@ extern "C" fftg_status fftg_apply_GK_noalloc(int n0, int n1, int n2, const doubl
   d.phase = d_phase;
   if (mode == FFTG_TANGENT_ELASTIC) {
     d.n_phases = n_phases;
-    for (int i = 0; i < n_phases; ++i) d.mats[i] = MatDev{mats[i].K, mats[i].G, mats[i].sigma_y0, mats[i].H};
+    for (int i = 0; i < n_phases; ++i) d.mats[i] = MatDev{mats[i].K, mats[i].G, 0.0, 0.0, 1.0, -1.0, 1.0, LAW_J2, 0};
   } else {
     d.n_phases = 1;  // the passes load the table even where the identity needs none
-    d.mats[0] = MatDev{1.0, 0.5, 1.0, 0.0};
+    d.mats[0] = MatDev{1.0, 0.5, 0.0, 0.0, 1.0, -1.0, 1.0, LAW_J2, 0};
   }
   d.mixed = 0;
   d.cg = reinterpret_cast<CgState*>(base + kCgOff);

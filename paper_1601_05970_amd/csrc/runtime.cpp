@@ -19,6 +19,11 @@
 
 using namespace fftg;
 
+// the Python binding mirrors these layouts
+static_assert(sizeof(fftg_material) == 64, "fftg_material layout");
+static_assert(sizeof(fftg_options) == 72, "fftg_options layout");
+static_assert(sizeof(fftg_stats) == 4 + 4 * 64 + 4 + 8 * 64 + 8 * 6 + 4 + 4 + 8 + 8, "fftg_stats layout");
+
 
 // ------------------------------------------------------------------ errors
 static thread_local std::string g_err;
@@ -292,6 +297,7 @@ void fftg_options_default(fftg_options* o) {
   o->rhs_floor = 1e-14;
   o->mixed_cg_floor = 1e-5;
   o->cg_chunk = 16;
+  o->dt = 1.0;
 }
 
 // Tile sizes fit the FP64 passes in an LDS budget (default 128 KB; mixed
@@ -434,6 +440,48 @@ static void plan_free(fftg_plan pl) {
   delete pl;
 }
 
+// Checks a phase's parameters for its law (Sec. 4) and forms its device
+// entry; dt is the real time step of the visco-plastic law.
+static fftg_status material_dev(const fftg_material& m, double dt, int i, MatDev& d) {
+  const std::string who = "material " + std::to_string(i) + ": ";
+  d = MatDev{};
+  d.K = m.K;
+  d.G = m.G;
+  d.n = m.n;
+  d.csign = -1.0;
+  d.e0 = 1.0;
+  switch (m.law) {
+    case FFTG_LAW_J2:
+      if (!(m.K > 0) || !(m.G > 0) || !(m.sigma_y0 > 0) || !(m.H >= 0) || !(m.n > 0))
+        return fail(FFTG_E_INVALID, who + "J2 needs K > 0, G > 0, sigma_y0 > 0, H >= 0, n > 0");
+      if (m.n > 1.0) return fail(FFTG_E_UNSUPPORTED, who + "J2 hardening exponent n > 1 is not supported");
+      d.law = LAW_J2;
+      d.sy = m.sigma_y0;
+      d.Hh = m.H;
+      return FFTG_OK;
+    case FFTG_LAW_NONLINEAR_ELASTIC:
+      if (!(m.K > 0) || !(m.G > 0) || !(m.sigma_y0 > 0) || !(m.eps0 > 0) || !(m.n > 0))
+        return fail(FFTG_E_INVALID, who + "non-linear elasticity needs K > 0, G > 0, sigma_0 > 0, eps0 > 0, n > 0");
+      if (m.n < 1.0) return fail(FFTG_E_UNSUPPORTED, who + "non-linear elastic exponent n < 1 is not supported");
+      d.law = LAW_NLE;
+      d.sy = m.sigma_y0;
+      d.e0 = m.eps0;
+      d.csign = m.n > 1.0 ? 1.0 : -1.0;
+      return FFTG_OK;
+    case FFTG_LAW_VISCO: {
+      if (!(m.K > 0) || !(m.G > 0) || !(m.sigma_y0 > 0) || !(m.eps0 > 0) || !(m.t0 > 0) || !(m.n > 0))
+        return fail(FFTG_E_INVALID, who + "visco-plasticity needs K > 0, G > 0, sigma_0 > 0, eps0 > 0, t0 > 0, n > 0");
+      if (m.n > 1.0) return fail(FFTG_E_UNSUPPORTED, who + "visco-plastic exponent n > 1 is not supported");
+      d.law = LAW_VISCO;
+      d.sy = 0.0;
+      d.Hh = m.sigma_y0 / std::pow(m.eps0 / m.t0 * dt, m.n);   // sigma_0 / (gamma_0 dt)^n
+      return FFTG_OK;
+    }
+    default:
+      return fail(FFTG_E_INVALID, who + "unknown law");
+  }
+}
+
 fftg_status fftg_plan_create(fftg_plan* out, int n0, int n1, int n2, const uint8_t* phase, int n_phases,
                              const fftg_material* mats, const fftg_options* opt, void* hip_stream) {
   if (!out) return fail(FFTG_E_INVALID, "out is NULL");
@@ -443,22 +491,21 @@ fftg_status fftg_plan_create(fftg_plan* out, int n0, int n1, int n2, const uint8
     if (ns[i] < 1 || ns[i] % 2 == 0) return fail(FFTG_E_INVALID, "grid extents must be odd and >= 1");
   if (!phase || !mats) return fail(FFTG_E_INVALID, "phase / mats is NULL");
   if (n_phases < 1 || n_phases > kMaxPhases) return fail(FFTG_E_INVALID, "n_phases must be in 1..16");
-  for (int i = 0; i < n_phases; ++i) {
-    const fftg_material& m = mats[i];
-    if (!(m.K > 0) || !(m.G > 0) || !(m.sigma_y0 > 0) || !(m.H >= 0))
-      return fail(FFTG_E_INVALID, "material " + std::to_string(i) + ": need K > 0, G > 0, sigma_y0 > 0, H >= 0");
-    if (m.n != 1.0) return fail(FFTG_E_UNSUPPORTED, "only linear hardening (n = 1) is implemented");
-  }
-  const long long nvox = (long long)n0 * n1 * n2;
-  for (long long v = 0; v < nvox; ++v)
-    if (phase[v] >= n_phases) return fail(FFTG_E_INVALID, "phase id out of range");
   fftg_options o;
   fftg_options_default(&o);
   if (opt) o = *opt;
   if (o.precision != FFTG_FP64 && o.precision != FFTG_MIXED) return fail(FFTG_E_INVALID, "bad precision");
   if (o.max_newton < 1 || o.max_newton > FFTG_MAX_NEWTON) return fail(FFTG_E_INVALID, "max_newton out of range");
-  if (o.max_cg < 1 || !(o.tol_cg >= 0) || !(o.tol_newton >= 0) || o.cg_chunk < 1)
-    return fail(FFTG_E_INVALID, "bad tolerances / iteration caps");
+  if (o.max_cg < 1 || !(o.tol_cg >= 0) || !(o.tol_newton >= 0) || o.cg_chunk < 1 || !(o.dt > 0))
+    return fail(FFTG_E_INVALID, "bad tolerances / iteration caps / time step");
+  MatDev md[kMaxPhases];
+  for (int i = 0; i < n_phases; ++i) {
+    const fftg_status ms = material_dev(mats[i], o.dt, i, md[i]);
+    if (ms != FFTG_OK) return ms;
+  }
+  const long long nvox = (long long)n0 * n1 * n2;
+  for (long long v = 0; v < nvox; ++v)
+    if (phase[v] >= n_phases) return fail(FFTG_E_INVALID, "phase id out of range");
 
   fftg_plan pl = new fftg_plan_s();
   memset(pl->stage_ev, 0, sizeof(pl->stage_ev));
@@ -472,7 +519,7 @@ fftg_status fftg_plan_create(fftg_plan* out, int n0, int n1, int n2, const uint8
   pl->mixed = o.precision == FFTG_MIXED;
   pl->stream = (hipStream_t)hip_stream;
   pl->n_phases = n_phases;
-  for (int i = 0; i < n_phases; ++i) pl->mats[i] = {mats[i].K, mats[i].G, mats[i].sigma_y0, mats[i].H};
+  for (int i = 0; i < n_phases; ++i) pl->mats[i] = md[i];
   fftg_status st = FFTG_OK;
   // transforms
   std::map<int, int> idx;

@@ -48,15 +48,30 @@ FFTG_KERNEL_ZFWD, FFTG_KERNEL_Y_FWD, FFTG_KERNEL_X_PROJ, FFTG_KERNEL_Y_INV, FFTG
 FFTG_KERNEL_FINALIZE, FFTG_KERNEL_CONSTITUTIVE, FFTG_KERNEL_NEWTON = range(5, 8)
 
 
+FFTG_LAW_J2, FFTG_LAW_NONLINEAR_ELASTIC, FFTG_LAW_VISCO = 0, 1, 2
+
+
 class fftg_material(C.Structure):
     _fields_ = [("K", C.c_double), ("G", C.c_double), ("sigma_y0", C.c_double), ("H", C.c_double),
-                ("n", C.c_double)]
+                ("n", C.c_double), ("law", C.c_int), ("eps0", C.c_double), ("t0", C.c_double)]
+
+
+def material(row) -> fftg_material:
+    """(K, G, sigma_y0, H, n) for an elasto-plastic phase, or
+    (K, G, sigma_y0, H, n, law, eps0, t0) naming the law."""
+    r = [float(v) for v in row]
+    if len(r) == 5:
+        r += [FFTG_LAW_J2, 1.0, 1.0]
+    if len(r) != 8:
+        raise ValueError("material rows are (K, G, s0, H, n) or (K, G, s0, H, n, law, eps0, t0)")
+    return fftg_material(r[0], r[1], r[2], r[3], r[4], int(r[5]), r[6], r[7])
 
 
 class fftg_options(C.Structure):
     _fields_ = [("precision", C.c_int), ("tol_newton", C.c_double), ("tol_cg", C.c_double),
                 ("max_newton", C.c_int), ("max_cg", C.c_int), ("predictor", C.c_int),
-                ("rhs_floor", C.c_double), ("mixed_cg_floor", C.c_double), ("cg_chunk", C.c_int)]
+                ("rhs_floor", C.c_double), ("mixed_cg_floor", C.c_double), ("cg_chunk", C.c_int),
+                ("dt", C.c_double)]
 
 
 class fftg_stats(C.Structure):
@@ -219,7 +234,7 @@ class Plan:
         if ph.ndim != 3:
             raise ValueError("phase must be 3-D")
         self.shape = tuple(int(s) for s in ph.shape)
-        mats = (fftg_material * len(materials))(*[fftg_material(*[float(v) for v in m]) for m in materials])
+        mats = (fftg_material * len(materials))(*[material(m) for m in materials])
         self.options = options if options is not None else fftg_options_default()
         self.stream = stream if stream is not None else torch.cuda.current_stream()
         h = C.c_void_p()
@@ -262,7 +277,7 @@ def fftg_apply_GK_noalloc(d_in, d_out, mode=FFTG_TANGENT_IDENTITY, d_phase=None,
     _check_field(d_in, shape, 6, "float64")
     _check_field(d_out, shape, 6, "float64")
     if materials:
-        mats = (fftg_material * len(materials))(*[fftg_material(*[float(v) for v in m]) for m in materials])
+        mats = (fftg_material * len(materials))(*[material(m) for m in materials])
         nm = len(materials)
     else:
         mats, nm = None, 0

@@ -326,9 +326,18 @@ def test_error_paths():
     with pytest.raises(fftg.FFTGError) as e:
         fftg.Plan(np.zeros((69, 5, 5), np.uint8), [synth.SOFT])
     assert e.value.status == fftg.FFTG_E_UNSUPPORTED
-    with pytest.raises(fftg.FFTGError) as e:
-        fftg.Plan(np.zeros((5, 5, 5), np.uint8), [(0.833, 0.386, 0.003, 0.004, 0.5)])
-    assert e.value.status == fftg.FFTG_E_UNSUPPORTED
+    # exponents whose rank-one tangent term would change sign per voxel
+    for mat in [(0.833, 0.386, 0.003, 0.004, 1.5),                          # J2, n > 1
+                (0.833, 0.386, 0.1, 0.0, 0.5, fftg.FFTG_LAW_NONLINEAR_ELASTIC, 0.1, 1.0),   # n < 1
+                (0.833, 0.386, 0.1, 0.0, 2.0, fftg.FFTG_LAW_VISCO, 0.1, 0.1)]:             # n > 1
+        with pytest.raises(fftg.FFTGError) as e:
+            fftg.Plan(np.zeros((5, 5, 5), np.uint8), [mat])
+        assert e.value.status == fftg.FFTG_E_UNSUPPORTED, mat
+    for mat in [(0.833, 0.386, 0.003, 0.004, 0.5, 7, 1.0, 1.0),              # unknown law
+                (0.833, 0.386, 0.1, 0.0, 0.3, fftg.FFTG_LAW_VISCO, 0.0, 0.1)]:  # eps0 = 0
+        with pytest.raises(fftg.FFTGError) as e:
+            fftg.Plan(np.zeros((5, 5, 5), np.uint8), [mat])
+        assert e.value.status == fftg.FFTG_E_INVALID, mat
     with pytest.raises(fftg.FFTGError) as e:
         fftg.Plan(np.full((5, 5, 5), 2, np.uint8), [synth.SOFT, synth.HARD])
     assert e.value.status == fftg.FFTG_E_INVALID

@@ -72,6 +72,18 @@ typedef enum {
  *   iteration starting from the return map at E_new + eps*. */
 typedef enum { FFTG_PREDICTOR_TANGENT = 0, FFTG_PREDICTOR_NONE = 1 } fftg_predictor;
 
+/* How each linearised system is set up and solved.
+ * GALERKIN: G C d = -G sigma (Eq. linear_system) by conjugate gradients
+ *   (Algorithm 1).
+ * BASIC: the collocation scheme of Sec. 3.2, Gamma_ref C d = -Gamma_ref sigma
+ *   (Eqs. L-S_discrete, linear_system_L-S) with Gamma_ref of Appendix A
+ *   (Eq. Gamma_explicit) for C_ref = 1/2 (lambda_min + lambda_max) I_s, the
+ *   extreme eigenvalues of the tangent over all voxels, renewed every Newton
+ *   iteration, solved by the Richardson iteration d <- d - Gamma_ref (C d +
+ *   sigma) (the basic scheme); iteration counts grow with lambda_max /
+ *   lambda_min instead of its square root.  FP64 plans only. */
+typedef enum { FFTG_SCHEME_GALERKIN = 0, FFTG_SCHEME_BASIC = 1 } fftg_scheme;
+
 /* Constitutive law of a phase (Sec. 4). */
 typedef enum {
   FFTG_LAW_J2 = 0,                /* elasto-plasticity, Sec. 4.2 */
@@ -112,6 +124,7 @@ typedef struct {
                              FP32-evaluated predictor right-hand side (default 1e-5) */
   int cg_chunk;           /* CG iterations enqueued between host checks (default 16) */
   double dt;              /* real time step of every increment, for VISCO phases (default 1) */
+  int scheme;             /* fftg_scheme (default GALERKIN) */
 } fftg_options;
 
 #define FFTG_MAX_NEWTON 64
@@ -135,7 +148,7 @@ typedef struct fftg_batch_s* fftg_batch;
 
 /* Fills *opt with defaults: FP64, tol_newton 1e-5, tol_cg 1e-8,
  * max_newton 50, max_cg 2000, TANGENT predictor, rhs_floor 1e-14,
- * mixed_cg_floor 1e-5, cg_chunk 16, dt 1. */
+ * mixed_cg_floor 1e-5, cg_chunk 16, dt 1, GALERKIN scheme. */
 void fftg_options_default(fftg_options* opt);
 
 /* Creates a plan for one RVE (Sec. 2.3 grid, Sec. 4.2 phases).
@@ -167,6 +180,14 @@ fftg_status fftg_solve_increment(fftg_plan plan, fftg_history hist, const double
  * may be NULL for IDENTITY / ELASTIC.  Asynchronous on the plan's stream. */
 fftg_status fftg_apply_GK(fftg_plan plan, fftg_history hist, const double* d_in, void* d_out,
                           fftg_tangent_mode mode);
+
+/* d_out = Gamma_ref : d_in, the Green operator of the collocation scheme
+ * (Sec. 3.2, Eq. L-S_discrete) for the isotropic reference medium
+ * C_ref = lam0 I(x)I + 2 mu0 I_s (mu0 > 0, lam0 + 2 mu0 > 0), built per
+ * frequency from the acoustic tensor (Appendix A, Eq. Gamma_explicit); with
+ * lam0 = 0, mu0 = 1/2 (C_ref = I_s) it is G.  d_in, d_out: device double,
+ * 6 planes.  FP64 plans only.  Asynchronous on the plan's stream. */
+fftg_status fftg_apply_Gamma(fftg_plan plan, const double* d_in, double* d_out, double lam0, double mu0);
 
 /* Return map (Sec. 4.2) at the total strain d_eps (device double, 6 planes)
  * from the history's committed eps_p, eps_p_bar, without committing.

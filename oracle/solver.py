@@ -7,6 +7,10 @@
   (Eq. trapz) with equal weights, whose common factor cancels.  The stopping
   test is the relative residual of Algorithm 1's CG loop, evaluated with the
   CG recurrence residual (equal to the true residual in exact arithmetic).
+* ``richardson`` -- the fixed-point iteration of the basic scheme (Sec. 3.2),
+  used with Gamma_ref of C_ref = 1/2 (lambda_min + lambda_max) I_s, the extreme
+  eigenvalues of the tangent's Mandel blocks over the grid, renewed every
+  Newton iteration (scheme="basic").
 * ``Solver`` -- the incremental-iterative Newton loop of Algorithm 1:
   increments of the mean strain E; Newton iterations until
   ||d_eps|| / ||E|| <= eta_NW, with ||E|| taken as the norm of the nodal
@@ -95,6 +99,42 @@ def cg(apply_A, b: np.ndarray, tol: float, max_iter: int = 2000,
     return CGResult(x, k, math.sqrt(rr) / bnorm if bnorm > 0 else 0.0)
 
 
+def richardson(apply_A, b: np.ndarray, tol: float, max_iter: int = 2000,
+               force_iters: Optional[int] = None, atol: float = 0.0) -> CGResult:
+    """Richardson (fixed-point) iteration x <- x + (b - A x) from x0 = 0 with
+    unit step, the basic scheme's solver of Sec. 3.2 (the reference medium
+    inside A sets the step).  Residual recurrence r <- r - A r; stopping as
+    in cg."""
+    x = np.zeros_like(b)
+    r = b.copy()
+    rr = fdot(r, r)
+    bnorm = math.sqrt(rr)
+    target = max(tol * bnorm, atol)
+    if force_iters is None and bnorm <= target:
+        return CGResult(x, 0, 0.0 if bnorm == 0.0 else 1.0)
+    k = 0
+    limit = force_iters if force_iters is not None else max_iter
+    while k < limit:
+        x = x + r
+        r = r - apply_A(r)
+        rr = fdot(r, r)
+        k += 1
+        if force_iters is None and math.sqrt(rr) <= target:
+            break
+    return CGResult(x, k, math.sqrt(rr) / bnorm if bnorm > 0 else 0.0)
+
+
+def tangent_eigen_bounds(C: np.ndarray):
+    """Smallest and largest eigenvalue of the 6x6 Mandel blocks of a
+    fourth-order tangent field over all voxels (Sec. 3.2, the extreme
+    eigenvalues of D over the grid)."""
+    from .projection import mandel_block
+    M = mandel_block(C)
+    Mv = np.moveaxis(M.reshape(6, 6, -1), -1, 0)
+    w = np.linalg.eigvalsh(Mv)
+    return float(w.min()), float(w.max())
+
+
 @dataclasses.dataclass
 class IncrementStats:
     newton_iters: int
@@ -110,7 +150,7 @@ class Solver:
 
     def __init__(self, phase, materials, tol_newton=1e-5, tol_cg=1e-8,
                  max_newton=50, max_cg=2000, zero_rhs_rel=1e-14,
-                 predictor: str = "tangent", dt: float = 1.0):
+                 predictor: str = "tangent", dt: float = 1.0, scheme: str = "galerkin"):
         self.phase = np.asarray(phase)
         self.shape = tuple(self.phase.shape)
         for n in self.shape:
@@ -128,6 +168,14 @@ class Solver:
         if predictor not in ("tangent", "none"):
             raise ValueError("predictor must be 'tangent' or 'none'")
         self.predictor = predictor
+        if scheme not in ("galerkin", "basic"):
+            raise ValueError("scheme must be 'galerkin' or 'basic'")
+        # galerkin: G C d = -G sigma by CG (Eq. linear_system); basic: the
+        # collocation system Gamma_ref C d = -Gamma_ref sigma (Eq.
+        # linear_system_L-S) with C_ref = 1/2 (lmin + lmax) I_s of the tangent
+        # of each Newton iteration, by Richardson (Sec. 3.2)
+        self.scheme = scheme
+        self.c_ref: List[float] = []       # reference stiffness of each linear solve (basic scheme)
         z = (3, 3) + self.shape
         self.eps_fl = np.zeros(z)          # fluctuation eps*
         self.eps_p = np.zeros(z)           # committed plastic strain
@@ -147,8 +195,21 @@ class Solver:
         eps = eps_fl + self.E[:, :, None, None, None]
         return laws.constitutive(self.phase, self.materials, eps, self.eps_p, self.epbar, self.dt)
 
-    def _linear_step(self, C, b, force):
-        """CG solve of G C d = b.
+    def _operator(self, C):
+        """The operator of the linear system about tangent C: G, or for the
+        basic scheme Gamma_ref of C_ref = 1/2 (lmin + lmax) I_s (Appendix A,
+        Eq. Gamma_explicit)."""
+        if self.scheme == "galerkin":
+            return apply_G
+        from .projection import apply_operator_hat, gamma_ref_hat
+        lo, hi = tangent_eigen_bounds(C)
+        c = 0.5 * (lo + hi)
+        self.c_ref.append(c)
+        Gh = gamma_ref_hat(self.shape, c * j2.I4S)
+        return lambda tau: apply_operator_hat(Gh, tau)
+
+    def _linear_step(self, C, b, force, op=apply_G):
+        """CG (or, basic scheme, Richardson) solve of op C d = b.
 
         The residual target is max(eta_CG ||b||, 1e-14 ||s||), where s is
         the field whose projection gave b (sigma, or C_last : dE for the
@@ -156,9 +217,10 @@ class Solver:
         of s, so a target below that floor is unreachable.  A right-hand
         side already under the target gives d = 0 without iterating.
         """
-        res = cg(lambda p: apply_G(j2.ddot42(C, p)), b, self.tol_cg,
-                 self.max_cg, force_iters=force,
-                 atol=self.zero_rhs_rel * self._rhs_scale)
+        solve = cg if self.scheme == "galerkin" else richardson
+        res = solve(lambda p: op(j2.ddot42(C, p)), b, self.tol_cg,
+                    self.max_cg, force_iters=force,
+                    atol=self.zero_rhs_rel * self._rhs_scale)
         if res.breakdown:
             raise FloatingPointError("CG breakdown: indefinite tangent")
         return res.x, res.iters
@@ -192,10 +254,11 @@ class Solver:
         if self.predictor == "tangent":
             dE_field = np.broadcast_to(dE[:, :, None, None, None], (3, 3) + self.shape)
             t = j2.ddot42(self.C_last, dE_field)
-            b = -apply_G(t)
+            op = self._operator(self.C_last)
+            b = -op(t)
             self._rhs_scale = math.sqrt(fdot(t, t))
             force = None if lockstep is None else lockstep[0]
-            d, its = self._linear_step(self.C_last, b, force)
+            d, its = self._linear_step(self.C_last, b, force, op)
             self.eps_fl = self.eps_fl + d
             cg_counts.append(its)
             res_hist.append(math.sqrt(fdot(d, d)) / Enorm)
@@ -208,10 +271,11 @@ class Solver:
             if lockstep is None and i >= self.max_newton:
                 break
             sigma, C, _, _, _ = self.constitutive(self.eps_fl)
-            b = -apply_G(sigma)
+            op = self._operator(C)
+            b = -op(sigma)
             self._rhs_scale = math.sqrt(fdot(sigma, sigma))
             force = None if lockstep is None else lockstep[i]
-            d, its = self._linear_step(C, b, force)
+            d, its = self._linear_step(C, b, force, op)
             self.eps_fl = self.eps_fl + d
             r = math.sqrt(fdot(d, d)) / Enorm
             cg_counts.append(its)
@@ -233,9 +297,9 @@ class Solver:
         return self.eps_fl + self.E[:, :, None, None, None]
 
 
-def run_workload(w, lockstep=None, n_inc=None, predictor="tangent", dt=1.0):
+def run_workload(w, lockstep=None, n_inc=None, predictor="tangent", dt=1.0, scheme="galerkin"):
     """Run the load path of a synth.Workload; returns (solver, [stats])."""
-    s = Solver(w.phase, w.materials, w.tol_newton, w.tol_cg, predictor=predictor, dt=dt)
+    s = Solver(w.phase, w.materials, w.tol_newton, w.tol_cg, predictor=predictor, dt=dt, scheme=scheme)
     out = []
     for n in range(1, (n_inc or w.n_inc) + 1):
         ls = None if lockstep is None else lockstep[n - 1]

@@ -69,12 +69,15 @@ struct CgState {
   double bnorm2, target2, snorm2, dnorm2;
   double eta2, floor2;
   double Sigma[6];
+  // reference medium of the collocation scheme, C_ref = lam0 I(x)I + 2 mu0 I_s,
+  // and the extreme eigenvalues of the tangent it was chosen from
+  double lam0, mu0, lmin, lmax;
   int iters, done, force, max_iter, status;
-  int pad_;
+  int rich;                            // 1: Richardson iteration (beta = 0, unit step) instead of CG
 };
 
 // Scalar steps of k_finalize (which partial sums it totals, and what for).
-enum FinStep { FIN_SNORM = 0, FIN_RESID, FIN_PAP, FIN_RR, FIN_DNORM, FIN_SIGMA };
+enum FinStep { FIN_SNORM = 0, FIN_RESID, FIN_PAP, FIN_RR, FIN_DNORM, FIN_SIGMA, FIN_LAMBDA };
 
 enum CgStatus { CG_RUNNING = 0, CG_CONVERGED = 1, CG_MAXITER = 2, CG_BREAKDOWN = 3, CG_FORCED = 4 };
 
@@ -169,7 +172,9 @@ hipError_t launch_zfwd(int mixed, const RveDev* rv, int nrve, int tiles, const L
 hipError_t launch_ypass(int mixed, int dir, const RveDev* rv, int nrve, int tiles, const LaunchCfg& cfg,
                         size_t lds, int check_done, hipStream_t s);
 hipError_t launch_xpass(int mixed, const RveDev* rv, int nrve, int tiles, const LaunchCfg& cfg, size_t lds,
-                        double scale, int check_done, hipStream_t s);
+                        double scale, int check_done, hipStream_t s, int gamma = 0);
+hipError_t launch_tangent_bounds(const RveDev* rv, int nrve, int tiles, const LaunchCfg& cfg, hipStream_t s);
+hipError_t launch_set_cref(const RveDev* rv, int nrve, double lam0, double mu0, hipStream_t s);
 hipError_t launch_zinv(int mixed, const RveDev* rv, int nrve, int tiles, const LaunchCfg& cfg, size_t lds,
                        int out_mode, int out_role, int check_done, int p_role, hipStream_t s);
 hipError_t launch_slab_fwd(int mixed, const RveDev* rv, int nrve, int tiles, const LaunchCfg& cfg, size_t lds,
@@ -182,6 +187,6 @@ hipError_t launch_finalize(const RveDev* rv, int nrve, int step, hipStream_t s);
 hipError_t launch_constitutive(int mixed, const RveDev* rv, int nrve, int tiles, const LaunchCfg& cfg,
                                int eps_role, int commit, hipStream_t s);
 hipError_t launch_cg_setup(const RveDev* rv, int nrve, double eta2, double floor2, int max_iter, int force,
-                           hipStream_t s);
+                           hipStream_t s, int rich = 0);
 
 }  // namespace fftg

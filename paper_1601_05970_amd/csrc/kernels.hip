@@ -229,6 +229,41 @@ __device__ __forceinline__ void ghat_apply(cx<T> t[6], T q0, T q1, T q2, T scale
   t[5] = {s2 * (q0 * v1.re + q1 * v0.re - a.re * q0 * q1), s2 * (q0 * v1.im + q1 * v0.im - a.im * q0 * q1)};
 }
 
+// Gamma^ref(k) : T of the collocation scheme (Appendix A, Eq.
+// Gamma_explicit) for an isotropic reference medium
+// C_ref = lam0 I(x)I + 2 mu0 I_s: with the acoustic tensor
+// A_il = C_ijlm q_j q_m = mu0 (q.q) delta_il + (lam0 + mu0) q_i q_l (q = xi/|xi|,
+// Gamma^ref is of degree 0 in xi), w = A^-1 (T q) and
+// (Gamma^ref : T)_ij = (q_i w_j + q_j w_i) / 2, i.e. the four terms of the
+// explicit form contracted with a symmetric T.  A is inverted by cofactors.
+template <class T>
+__device__ __forceinline__ void gamma_apply(cx<T> t[6], T q0, T q1, T q2, T lam0, T mu0, T scale) {
+  const T r2 = T(1.0 / kSqrt2);
+  const cx<T> T11 = t[0], T22 = t[1], T33 = t[2];
+  const cx<T> T23 = {t[3].re * r2, t[3].im * r2};
+  const cx<T> T13 = {t[4].re * r2, t[4].im * r2};
+  const cx<T> T12 = {t[5].re * r2, t[5].im * r2};
+  const T qq = q0 * q0 + q1 * q1 + q2 * q2, a = lam0 + mu0;
+  const T A00 = mu0 * qq + a * q0 * q0, A11 = mu0 * qq + a * q1 * q1, A22 = mu0 * qq + a * q2 * q2;
+  const T A01 = a * q0 * q1, A02 = a * q0 * q2, A12 = a * q1 * q2;
+  const T c00 = A11 * A22 - A12 * A12, c01 = A02 * A12 - A01 * A22, c02 = A01 * A12 - A02 * A11;
+  const T c11 = A00 * A22 - A02 * A02, c12 = A01 * A02 - A00 * A12, c22 = A00 * A11 - A01 * A01;
+  const T id = T(1) / (A00 * c00 + A01 * c01 + A02 * c02);
+  const cx<T> v0 = {T11.re * q0 + T12.re * q1 + T13.re * q2, T11.im * q0 + T12.im * q1 + T13.im * q2};
+  const cx<T> v1 = {T12.re * q0 + T22.re * q1 + T23.re * q2, T12.im * q0 + T22.im * q1 + T23.im * q2};
+  const cx<T> v2 = {T13.re * q0 + T23.re * q1 + T33.re * q2, T13.im * q0 + T23.im * q1 + T33.im * q2};
+  const cx<T> w0 = {id * (c00 * v0.re + c01 * v1.re + c02 * v2.re), id * (c00 * v0.im + c01 * v1.im + c02 * v2.im)};
+  const cx<T> w1 = {id * (c01 * v0.re + c11 * v1.re + c12 * v2.re), id * (c01 * v0.im + c11 * v1.im + c12 * v2.im)};
+  const cx<T> w2 = {id * (c02 * v0.re + c12 * v1.re + c22 * v2.re), id * (c02 * v0.im + c12 * v1.im + c22 * v2.im)};
+  const T hs = T(0.5 * kSqrt2) * scale;
+  t[0] = {scale * q0 * w0.re, scale * q0 * w0.im};
+  t[1] = {scale * q1 * w1.re, scale * q1 * w1.im};
+  t[2] = {scale * q2 * w2.re, scale * q2 * w2.im};
+  t[3] = {hs * (q1 * w2.re + q2 * w1.re), hs * (q1 * w2.im + q2 * w1.im)};
+  t[4] = {hs * (q0 * w2.re + q2 * w0.re), hs * (q0 * w2.im + q2 * w0.im)};
+  t[5] = {hs * (q0 * w1.re + q1 * w0.re), hs * (q0 * w1.im + q1 * w0.im)};
+}
+
 __device__ __forceinline__ int sfreq(int m, int n) { return (2 * m < n) ? m : m - n; }
 
 // LDS carve-up for a tile: axis tables, then nl lines of stride ld, the
@@ -257,7 +292,7 @@ struct TileLds {
 // asm): values loaded from a uniform address are otherwise moved to scalar
 // registers, and so waited for, right where they are loaded.
 struct CgPeekB {
-  int done, iters, status, force, max_iter;
+  int done, iters, status, force, max_iter, rich;
   double rr_prev, target2, beta;
 };
 __device__ __forceinline__ const FFTG_GLOBAL CgState* cg_vaddr(CgState* cg) {
@@ -266,7 +301,7 @@ __device__ __forceinline__ const FFTG_GLOBAL CgState* cg_vaddr(CgState* cg) {
 }
 __device__ __forceinline__ CgPeekB cg_peek_b(CgState* cg) {
   const FFTG_GLOBAL CgState* g = cg_vaddr(cg);
-  return CgPeekB{g->done, g->iters, g->status, g->force, g->max_iter, g->rr_prev, g->target2, g->beta};
+  return CgPeekB{g->done, g->iters, g->status, g->force, g->max_iter, g->rich, g->rr_prev, g->target2, g->beta};
 }
 
 
@@ -315,7 +350,7 @@ __device__ bool cg_begin_iter(const RveDev& rv, int tile, int dn, const CgPeekB&
   } else if (it >= pk.max_iter) {
     st = CG_MAXITER;
   }
-  const double b = rr / pk.rr_prev;
+  const double b = pk.rich ? 0.0 : rr / pk.rr_prev;   // Richardson: p = r
   if (tile == 0 && threadIdx.x == 0) {
     cg->rr = rr;
     cg->rr_new = rr;
@@ -596,7 +631,9 @@ __global__ void __launch_bounds__(256) k_ypass(const RveDev* __restrict__ rvs, i
 }
 
 // --------------------------------------------------- x pass with G^(k)
-template <class T, int BIG, int NF>
+// (GAMMA = 1: the collocation scheme's Gamma^ref(k) of the reference medium
+// held in the CG state instead of G^(k).)
+template <class T, int BIG, int NF, int GAMMA = 0>
 __global__ void __launch_bounds__(256) k_xpass(const RveDev* __restrict__ rvs, int nrve, int lines_per_tile,
                                                int ldmax, double scale_in, int check_done) {
   extern __shared__ __align__(16) char smem[];
@@ -648,6 +685,12 @@ __global__ void __launch_bounds__(256) k_xpass(const RveDev* __restrict__ rvs, i
   // projection on every frequency (k0, k1, k2) of the tile; xi_i = k_i / L_i, L_i = n_i
   const T scale = T(scale_in / double(nvox));   // inverse DFT normalisation 1/|N|
   const double k1 = double(sfreq(i1, n1)) / double(n1);
+  T lam0 = T(0), mu0 = T(0);
+  if constexpr (GAMMA) {
+    const FFTG_GLOBAL CgState* g = cg_vaddr(cg);
+    lam0 = T(g->lam0);
+    mu0 = T(g->mu0);
+  }
   for (int t = threadIdx.x; t < n0 * nh; t += blockDim.x) {
     const int x = fnh.div(t);
     const int hh = t - x * nh;
@@ -662,7 +705,8 @@ __global__ void __launch_bounds__(256) k_xpass(const RveDev* __restrict__ rvs, i
       for (int c = 0; c < 6; ++c) v[c] = cx<T>{T(0), T(0)};
     } else {
       const double inv = 1.0 / sqrt(nn);
-      ghat_apply<T>(v, T(k0 * inv), T(k1 * inv), T(k2 * inv), scale);
+      if constexpr (GAMMA) gamma_apply<T>(v, T(k0 * inv), T(k1 * inv), T(k2 * inv), lam0, mu0, scale);
+      else ghat_apply<T>(v, T(k0 * inv), T(k1 * inv), T(k2 * inv), scale);
     }
 #pragma unroll
     for (int c = 0; c < 6; ++c) res[(c * nh + hh) * ld + x] = v[c];
@@ -701,12 +745,12 @@ __global__ void __launch_bounds__(256) k_xpass(const RveDev* __restrict__ rvs, i
 // flag, of which thread 0's copy counts) and used after the step's barrier,
 // when the loads have landed.
 struct CgPeek {
-  int done;
+  int done, rich;
   double rr, alpha;
 };
 __device__ __forceinline__ CgPeek cg_peek(CgState* cg) {
   const FFTG_GLOBAL CgState* g = cg_vaddr(cg);
-  return CgPeek{g->done, g->rr, g->alpha};
+  return CgPeek{g->done, g->rich, g->rr, g->alpha};
 }
 
 // alpha = r.r / p.(C:p) for the CG vector update of the inverse z pass.  p is
@@ -740,19 +784,21 @@ __device__ bool cg_alpha(const RveDev& rv, int tile, const CgPeek& pk, bool chec
   }
   if (timing) return true;
   const double rr = pk.rr;
-  const bool brk = !(pap > 0.0) || !(pap < INFINITY);
+  // Richardson: unit step, no curvature test (its operator need not be SPD)
+  const bool brk = !pk.rich && (!(pap > 0.0) || !(pap < INFINITY));
+  const double a = pk.rich ? 1.0 : rr / pap;
   if (tile == 0 && threadIdx.x == 0) {
     cg->pAp = pap;
     if (brk) {
       cg->status = CG_BREAKDOWN;
     } else {
-      cg->alpha = rr / pap;
+      cg->alpha = a;
       cg->rr_prev = rr;
       cg->iters += 1;
     }
   }
   if (brk) return false;
-  alpha = rr / pap;
+  alpha = a;
   return true;
 }
 
@@ -1532,6 +1578,29 @@ __global__ void __launch_bounds__(256) k_finalize(const RveDev* __restrict__ rvs
   const int pass = (step == FIN_SNORM || step == FIN_PAP) ? P_ZF
                    : ((step == FIN_RESID || step == FIN_RR) ? P_ZI : P_VEC);
   const int nt = rv.tiles[pass];
+  if (step == FIN_LAMBDA) {
+    // smallest and largest tangent eigenvalue over the tiles; the collocation
+    // scheme's reference medium C_ref = 1/2 (lmin + lmax) I_s = 2 mu0 I_s
+    double lo = INFINITY, hi = 0.0;
+    for (int t = threadIdx.x; t < nt; t += blockDim.x) {
+      lo = fmin(lo, rv.partial[t]);
+      hi = fmax(hi, rv.partial[nt + t]);
+    }
+    __shared__ double slo[256], shi[256];
+    slo[threadIdx.x] = lo;
+    shi[threadIdx.x] = hi;
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    for (int i = 1; i < (int)blockDim.x; ++i) {
+      lo = fmin(lo, slo[i]);
+      hi = fmax(hi, shi[i]);
+    }
+    cg->lmin = lo;
+    cg->lmax = hi;
+    cg->lam0 = 0.0;
+    cg->mu0 = 0.25 * (lo + hi);
+    return;
+  }
   const int nv = step == FIN_SIGMA ? 6 : 1;
   const double* part = step == FIN_RR ? rv.partial_rr : rv.partial;
   double tot[6];
@@ -1560,7 +1629,9 @@ __global__ void __launch_bounds__(256) k_finalize(const RveDev* __restrict__ rvs
     }
     case FIN_PAP:
       cg->pAp = t;
-      if (!(t > 0.0) || !(t < INFINITY)) {
+      if (cg->rich) {
+        cg->alpha = 1.0;
+      } else if (!(t > 0.0) || !(t < INFINITY)) {
         cg->done = 1;
         cg->status = CG_BREAKDOWN;
       } else {
@@ -1583,7 +1654,7 @@ __global__ void __launch_bounds__(256) k_finalize(const RveDev* __restrict__ rvs
         done = 1;
         st = CG_MAXITER;
       }
-      cg->beta = t / cg->rr;
+      cg->beta = cg->rich ? 0.0 : t / cg->rr;
       cg->rr = t;
       cg->status = st;
       cg->done = done;
@@ -1602,10 +1673,11 @@ __global__ void __launch_bounds__(256) k_finalize(const RveDev* __restrict__ rvs
 
 // CG configuration of every RVE of a launch before a linear solve.
 __global__ void k_cg_setup(RveDev* __restrict__ rvs, int nrve, double eta2, double floor2, int max_iter,
-                           int force) {
+                           int force, int rich) {
   const int r = blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= nrve) return;
   CgState* cg = rvs[r].cg;
+  cg->rich = rich;
   cg->eta2 = eta2;
   cg->floor2 = floor2;
   cg->max_iter = max_iter;
@@ -1613,6 +1685,56 @@ __global__ void k_cg_setup(RveDev* __restrict__ rvs, int nrve, double eta2, doub
   cg->iters = 0;
   cg->done = 0;
   cg->status = CG_RUNNING;
+}
+
+// Extreme eigenvalues of each voxel's consistent tangent, per tile (min in
+// partial[tile], max in partial[tiles + tile]).  For the compact tangent
+// C = K I(x)I + 2G' I_d + csign m (x) m with a deviatoric m they are 3K
+// (volumetric), 2G' (four deviatoric directions normal to m) and
+// 2G' + csign |m|^2 (along m).
+__global__ void __launch_bounds__(256) k_tangent_bounds(const RveDev* __restrict__ rvs, int nrve, int vox_per_tile) {
+  __shared__ double slo[256], shi[256];
+  int tile;
+  const int ri = find_rve(rvs, nrve, P_VEC, tile);
+  if (ri < 0) return;
+  const RveDev& rv = rvs[ri];
+  const long long nvox = rv.nvox;
+  const double* tg = (const double*)rv.tang;
+  const long long v0 = (long long)tile * vox_per_tile;
+  const int nv = (int)min((long long)vox_per_tile, nvox - v0);
+  double lo = INFINITY, hi = 0.0;
+  for (int t = threadIdx.x; t < nv; t += blockDim.x) {
+    const long long v = v0 + t;
+    const MatDev& mt = rv.mats[rv.phase[v]];
+    const double g2 = tg[v];
+    double mm = 0.0;
+#pragma unroll
+    for (int c = 0; c < 6; ++c) mm += tg[(c + 1) * nvox + v] * tg[(c + 1) * nvox + v];
+    const double a = 3.0 * mt.K, b = g2, c = g2 + mt.csign * mm;
+    lo = fmin(lo, fmin(a, fmin(b, c)));
+    hi = fmax(hi, fmax(a, fmax(b, c)));
+  }
+  slo[threadIdx.x] = lo;
+  shi[threadIdx.x] = hi;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int i = 1; i < (int)blockDim.x; ++i) {
+      lo = fmin(lo, slo[i]);
+      hi = fmax(hi, shi[i]);
+    }
+    const int nt = rv.tiles[P_VEC];
+    rv.partial[tile] = lo;
+    rv.partial[nt + tile] = hi;
+  }
+}
+
+// Reference medium C_ref = lam0 I(x)I + 2 mu0 I_s of every member (the
+// operator Gamma_ref of fftg_apply_Gamma).
+__global__ void k_set_cref(RveDev* __restrict__ rvs, int nrve, double lam0, double mu0) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= nrve) return;
+  rvs[r].cg->lam0 = lam0;
+  rvs[r].cg->mu0 = mu0;
 }
 
 __global__ void k_add_const(double* __restrict__ f, long long nvox, double e0, double e1, double e2, double e3,
@@ -1668,6 +1790,11 @@ template <class T, int BIG, int NF>
 static void xpass_go(dim3 G, dim3 B, size_t lds, hipStream_t s, const RveDev* rv, int nrve, int lines, int ldmax,
                      double scale, int check_done) {
   hipLaunchKernelGGL((k_xpass<T, BIG, NF>), G, B, lds, s, rv, nrve, lines, ldmax, scale, check_done);
+}
+template <int BIG>
+static void xpass_gamma_go(dim3 G, dim3 B, size_t lds, hipStream_t s, const RveDev* rv, int nrve, int lines,
+                           int ldmax, double scale, int check_done) {
+  hipLaunchKernelGGL((k_xpass<double, BIG, 0, 1>), G, B, lds, s, rv, nrve, lines, ldmax, scale, check_done);
 }
 template <class T, int BIG, int NF>
 static void zinv_go(dim3 G, dim3 B, size_t lds, hipStream_t s, const RveDev* rv, int nrve, int rows, int ldmax,
@@ -1732,9 +1859,18 @@ hipError_t launch_ypass(int mixed, int dir, const RveDev* rv, int nrve, int tile
 }
 
 hipError_t launch_xpass(int mixed, const RveDev* rv, int nrve, int tiles, const LaunchCfg& cfg, size_t lds,
-                        double scale, int check_done, hipStream_t s) {
+                        double scale, int check_done, hipStream_t s, int gamma) {
   if (tiles <= 0) return hipSuccess;
   const int nr = nrve_arg(nrve, cfg);
+  if (gamma) {
+    // the collocation operator runs in FP64 with the general transforms
+    if (mixed) return hipErrorInvalidValue;
+    if (cfg.big_radix)
+      xpass_gamma_go<1>(dim3(tiles), dim3(cfg.threads_x), lds, s, rv, nr, cfg.lines_x, cfg.n0max, scale, check_done);
+    else
+      xpass_gamma_go<0>(dim3(tiles), dim3(cfg.threads_x), lds, s, rv, nr, cfg.lines_x, cfg.n0max, scale, check_done);
+    return hipGetLastError();
+  }
   DISPATCH_TBF(xpass_go, 1, dim3(tiles), dim3(cfg.threads_x), lds, s, rv, nr, cfg.lines_x, cfg.n0max, scale,
               check_done);
   return hipGetLastError();
@@ -1795,9 +1931,21 @@ hipError_t launch_finalize(const RveDev* rv, int nrve, int step, hipStream_t s) 
 }
 
 hipError_t launch_cg_setup(const RveDev* rv, int nrve, double eta2, double floor2, int max_iter, int force,
-                           hipStream_t s) {
+                           hipStream_t s, int rich) {
   hipLaunchKernelGGL(k_cg_setup, dim3((nrve + 63) / 64), dim3(64), 0, s, (RveDev*)rv, nrve, eta2, floor2,
-                     max_iter, force);
+                     max_iter, force, rich);
+  return hipGetLastError();
+}
+
+hipError_t launch_tangent_bounds(const RveDev* rv, int nrve, int tiles, const LaunchCfg& cfg, hipStream_t s) {
+  if (tiles <= 0) return hipSuccess;
+  const int nr = nrve_arg(nrve, cfg);
+  hipLaunchKernelGGL(k_tangent_bounds, dim3(tiles), dim3(256), 0, s, rv, nr, cfg.vec_per_tile);
+  return hipGetLastError();
+}
+
+hipError_t launch_set_cref(const RveDev* rv, int nrve, double lam0, double mu0, hipStream_t s) {
+  hipLaunchKernelGGL(k_set_cref, dim3((nrve + 63) / 64), dim3(64), 0, s, (RveDev*)rv, nrve, lam0, mu0);
   return hipGetLastError();
 }
 

@@ -21,7 +21,7 @@ using namespace fftg;
 
 // the Python binding mirrors these layouts
 static_assert(sizeof(fftg_material) == 64, "fftg_material layout");
-static_assert(sizeof(fftg_options) == 72, "fftg_options layout");
+static_assert(sizeof(fftg_options) == 80, "fftg_options layout");
 static_assert(sizeof(fftg_stats) == 4 + 4 * 64 + 4 + 8 * 64 + 8 * 6 + 4 + 4 + 8 + 8, "fftg_stats layout");
 
 
@@ -298,6 +298,7 @@ void fftg_options_default(fftg_options* o) {
   o->mixed_cg_floor = 1e-5;
   o->cg_chunk = 16;
   o->dt = 1.0;
+  o->scheme = FFTG_SCHEME_GALERKIN;
 }
 
 // Tile sizes fit the FP64 passes in an LDS budget (default 128 KB; mixed
@@ -498,6 +499,9 @@ fftg_status fftg_plan_create(fftg_plan* out, int n0, int n1, int n2, const uint8
   if (o.max_newton < 1 || o.max_newton > FFTG_MAX_NEWTON) return fail(FFTG_E_INVALID, "max_newton out of range");
   if (o.max_cg < 1 || !(o.tol_cg >= 0) || !(o.tol_newton >= 0) || o.cg_chunk < 1 || !(o.dt > 0))
     return fail(FFTG_E_INVALID, "bad tolerances / iteration caps / time step");
+  if (o.scheme != FFTG_SCHEME_GALERKIN && o.scheme != FFTG_SCHEME_BASIC) return fail(FFTG_E_INVALID, "bad scheme");
+  if (o.scheme == FFTG_SCHEME_BASIC && o.precision != FFTG_FP64)
+    return fail(FFTG_E_UNSUPPORTED, "the collocation (basic) scheme runs in FP64 only");
   MatDev md[kMaxPhases];
   for (int i = 0; i < n_phases; ++i) {
     const fftg_status ms = material_dev(mats[i], o.dt, i, md[i]);
@@ -760,6 +764,7 @@ struct Group {
   bool own;                      // device arrays owned by the group
   double active_vox;             // voxels of the members not skipped
   bool need_fin = false;         // some active member runs the CG steps in k_finalize
+  int basic = 0;                 // collocation scheme: Gamma_ref products, Richardson iteration
 };
 
 static void fill_desc(RveDev& rv, fftg_plan pl, fftg_history h, const LaunchCfg& cfg) {
@@ -912,7 +917,7 @@ static void set_skip(Group& g, size_t i, bool skip) {
 // folded, k_finalize forms alpha between the passes and beta after them.
 static fftg_status enqueue_apply(Group& g, int mixed, int in_mode, int in_role, int tan_mode, int want_norm,
                                  int out_mode, int out_role, double scale, int check_done, int update_p = 0,
-                                 int p_in = R_P, int p_out = R_P) {
+                                 int p_in = R_P, int p_out = R_P, int gamma = 0) {
   const int nr = (int)g.h.size();
   const size_t lx = mixed ? g.lds_x32 : g.lds_x;
   if (g.cfg.slab) {
@@ -931,7 +936,8 @@ static fftg_status enqueue_apply(Group& g, int mixed, int in_mode, int in_role, 
     const size_t ly = mixed ? g.lds_y32 : g.lds_y;
     PROF_LAUNCH(FFTG_KERNEL_Y_FWD, launch_ypass(mixed, -1, g.d, nr, g.total[P_Y], g.cfg, ly, check_done, g.stream));
   }
-  PROF_LAUNCH(FFTG_KERNEL_X_PROJ, launch_xpass(mixed, g.d, nr, g.total[P_X], g.cfg, lx, scale, check_done, g.stream));
+  PROF_LAUNCH(FFTG_KERNEL_X_PROJ,
+              launch_xpass(mixed, g.d, nr, g.total[P_X], g.cfg, lx, scale, check_done, g.stream, gamma));
   if (g.cfg.slab) {
     const size_t ls = mixed ? g.lds_s32 : g.lds_s;
     PROF_LAUNCH(FFTG_KERNEL_ZINV, launch_slab_inv(mixed, g.d, nr, g.total[P_ZI], g.cfg, ls, out_mode, out_role,
@@ -962,7 +968,7 @@ static fftg_status enqueue_cg_iters(Group& g, int iters) {
     // one iteration of Algorithm 1 (CG part) is one product: the forward
     // pass forms p and p.Ap, the inverse pass updates x and r and sums r.r
     fftg_status st =
-        enqueue_apply(g, g.mixed, IN_ROLE, R_P, TAN_CURRENT, 0, OUT_CG, R_X, 1.0, 1, PU_CG, p_in, p_out);
+        enqueue_apply(g, g.mixed, IN_ROLE, R_P, TAN_CURRENT, 0, OUT_CG, R_X, 1.0, 1, PU_CG, p_in, p_out, g.basic);
     if (st != FFTG_OK) return st;
   }
   return FFTG_OK;
@@ -1110,14 +1116,23 @@ static fftg_status group_increment(Group& g, const double* dE_tensor, const int*
     // predictor) is only known to FP32 rounding of s = C_last:dE, so its
     // floor is mixed_cg_floor ||s|| instead of rhs_floor ||s||.
     const double fl2 = (pred_step && g.mixed) ? o.mixed_cg_floor * o.mixed_cg_floor : floor2;
-    HIP_TRY(launch_cg_setup(g.d, nr, eta2, fl2, o.max_cg, force, g.stream));
-    if (pred_step) {
-      // G C_last dE: constant input, CURRENT tangent, FP64 or mixed apply
-      st = enqueue_apply(g, g.mixed, IN_CONST_DE, R_P, TAN_CURRENT, 1, OUT_RESIDUAL, R_R, -1.0, 0);
-    } else {
+    HIP_TRY(launch_cg_setup(g.d, nr, eta2, fl2, o.max_cg, force, g.stream, g.basic));
+    if (!pred_step)
       PROF_LAUNCH(FFTG_KERNEL_CONSTITUTIVE,
                   launch_constitutive(g.mixed, g.d, nr, g.total[P_VEC], g.cfg, R_EPS_FL, 0, g.stream));
-      st = enqueue_apply(g, 0, IN_ROLE, R_SIG, TAN_IDENTITY, 1, OUT_RESIDUAL, R_R, -1.0, 0);
+    if (g.basic) {
+      // collocation scheme: reference medium C_ref = 1/2 (lmin + lmax) I_s of
+      // the tangent this iteration linearises about (the history's tangent:
+      // C_last for the predictor, else the one just evaluated)
+      HIP_TRY(launch_tangent_bounds(g.d, nr, g.total[P_VEC], g.cfg, g.stream));
+      PROF_LAUNCH(FFTG_KERNEL_FINALIZE, launch_finalize(g.d, nr, FIN_LAMBDA, g.stream));
+    }
+    if (pred_step) {
+      // G C_last dE: constant input, CURRENT tangent, FP64 or mixed apply
+      st = enqueue_apply(g, g.mixed, IN_CONST_DE, R_P, TAN_CURRENT, 1, OUT_RESIDUAL, R_R, -1.0, 0, 0, R_P, R_P,
+                         g.basic);
+    } else {
+      st = enqueue_apply(g, 0, IN_ROLE, R_SIG, TAN_IDENTITY, 1, OUT_RESIDUAL, R_R, -1.0, 0, 0, R_P, R_P, g.basic);
     }
     if (st != FFTG_OK) return st;
     st = run_cg(g, o.cg_chunk);
@@ -1471,6 +1486,7 @@ static fftg_status group_autotune(Group& g) {
 // Single-member group view on a plan (uses the plan's own descriptor slot).
 static fftg_status single_group(fftg_plan pl, fftg_history h, Group& g) {
   g.mixed = pl->mixed;
+  g.basic = pl->opt.scheme == FFTG_SCHEME_BASIC;
   g.stream = pl->stream;
   g.plans = {pl};
   g.hists = {h};
@@ -1550,6 +1566,30 @@ fftg_status fftg_apply_GK(fftg_plan pl, fftg_history h, const double* d_in, void
   st = group_upload(g);
   if (st == FFTG_OK)
     st = enqueue_apply(g, pl->mixed, IN_ROLE, R_USER_IN, (int)mode, 0, OUT_PLAIN, R_USER_OUT, 1.0, 0);
+  single_group_done(pl, g);
+  return st;
+}
+
+fftg_status fftg_apply_Gamma(fftg_plan pl, const double* d_in, double* d_out, double lam0, double mu0) {
+  if (!pl || !d_in || !d_out) return fail(FFTG_E_INVALID, "NULL argument");
+  if (pl->mixed) return fail(FFTG_E_UNSUPPORTED, "Gamma_ref products run on FP64 plans");
+  if (!(mu0 > 0) || !(lam0 + 2.0 * mu0 > 0)) return fail(FFTG_E_INVALID, "need mu0 > 0 and lam0 + 2 mu0 > 0");
+  Group g;
+  single_group(pl, nullptr, g);
+  fftg_status st = ensure_tuned(pl, g);
+  if (st != FFTG_OK) {
+    single_group_done(pl, g);
+    return st;
+  }
+  g.h[0].buf[R_USER_IN] = (void*)d_in;
+  g.h[0].buf[R_USER_OUT] = d_out;
+  st = group_upload(g);
+  if (st == FFTG_OK) {
+    const hipError_t e = launch_set_cref(g.d, 1, lam0, mu0, g.stream);
+    if (e != hipSuccess) st = fail(FFTG_E_HIP, hipGetErrorString(e));
+  }
+  if (st == FFTG_OK)
+    st = enqueue_apply(g, 0, IN_ROLE, R_USER_IN, TAN_IDENTITY, 0, OUT_PLAIN, R_USER_OUT, 1.0, 0, 0, R_P, R_P, 1);
   single_group_done(pl, g);
   return st;
 }
@@ -1714,12 +1754,14 @@ fftg_status fftg_batch_create(fftg_batch* out, int count, const fftg_plan* plans
   for (int i = 0; i < count; ++i) {
     if (!plans[i] || !hists[i] || hists[i]->plan != plans[i]) return fail(FFTG_E_INVALID, "bad batch member");
     if (plans[i]->mixed != plans[0]->mixed) return fail(FFTG_E_INVALID, "batch members must share precision");
+    if (plans[i]->opt.scheme != plans[0]->opt.scheme) return fail(FFTG_E_INVALID, "batch members must share scheme");
     for (int j = 0; j < i; ++j)
       if (plans[j] == plans[i]) return fail(FFTG_E_INVALID, "a plan may appear once per batch");
   }
   fftg_batch b = new fftg_batch_s();
   Group& g = b->g;
   g.mixed = plans[0]->mixed;
+  g.basic = plans[0]->opt.scheme == FFTG_SCHEME_BASIC;
   g.stream = plans[0]->stream;
   g.plans.assign(plans, plans + count);
   g.hists.assign(hists, hists + count);

@@ -42,13 +42,14 @@ EXPORTS = [
     "fftg_footprint_bytes", "fftg_batch_create", "fftg_batch_destroy", "fftg_batch_solve_increment",
     "fftg_profiler_start", "fftg_profiler_start_every", "fftg_profiler_stop", "fftg_profiler_seen",
     "fftg_profiler_start_set", "fftg_profiler_kind",
-    "fftg_last_error", "fftg_apply_GK_noalloc",
+    "fftg_last_error", "fftg_apply_GK_noalloc", "fftg_apply_Gamma",
 ]
 FFTG_KERNEL_ZFWD, FFTG_KERNEL_Y_FWD, FFTG_KERNEL_X_PROJ, FFTG_KERNEL_Y_INV, FFTG_KERNEL_ZINV = range(5)
 FFTG_KERNEL_FINALIZE, FFTG_KERNEL_CONSTITUTIVE, FFTG_KERNEL_NEWTON = range(5, 8)
 
 
 FFTG_LAW_J2, FFTG_LAW_NONLINEAR_ELASTIC, FFTG_LAW_VISCO = 0, 1, 2
+FFTG_SCHEME_GALERKIN, FFTG_SCHEME_BASIC = 0, 1
 
 
 class fftg_material(C.Structure):
@@ -71,7 +72,7 @@ class fftg_options(C.Structure):
     _fields_ = [("precision", C.c_int), ("tol_newton", C.c_double), ("tol_cg", C.c_double),
                 ("max_newton", C.c_int), ("max_cg", C.c_int), ("predictor", C.c_int),
                 ("rhs_floor", C.c_double), ("mixed_cg_floor", C.c_double), ("cg_chunk", C.c_int),
-                ("dt", C.c_double)]
+                ("dt", C.c_double), ("scheme", C.c_int)]
 
 
 class fftg_stats(C.Structure):
@@ -140,6 +141,7 @@ def lib():
     L.fftg_profiler_start_set.argtypes = [C.c_uint, ip]
     L.fftg_profiler_kind.argtypes = [ip, dp, C.POINTER(C.c_longlong), dp, C.POINTER(C.c_longlong)]
     L.fftg_apply_GK_noalloc.argtypes = [ip, ip, ip, vp, vp, ip, vp, ip, C.POINTER(fftg_material), vp]
+    L.fftg_apply_Gamma.argtypes = [vp, vp, vp, C.c_double, C.c_double]
     L.fftg_last_error.argtypes = []
     L.fftg_last_error.restype = C.c_char_p
     for name in ("fftg_plan_create", "fftg_history_create", "fftg_solve_increment", "fftg_apply_GK",
@@ -147,7 +149,7 @@ def lib():
                  "fftg_history_save", "fftg_history_restore", "fftg_batch_create",
                  "fftg_batch_solve_increment", "fftg_profiler_start", "fftg_profiler_start_every",
                  "fftg_profiler_stop", "fftg_apply_GK_noalloc", "fftg_profiler_start_set",
-                 "fftg_profiler_kind"):
+                 "fftg_profiler_kind", "fftg_apply_Gamma"):
         getattr(L, name).restype = C.c_int
     _lib = L
     return L
@@ -262,6 +264,12 @@ class Plan:
     def field(self, ncomp=6, dtype=None):
         import torch
         return torch.zeros((ncomp,) + self.shape, dtype=dtype or torch.float64, device="cuda")
+
+    def apply_Gamma(self, d_in, d_out, lam0: float, mu0: float):
+        """fftg_apply_Gamma: d_out = Gamma_ref(C_ref) : d_in, C_ref = lam0 I(x)I + 2 mu0 I_s."""
+        _check_field(d_in, self.shape, 6, "float64")
+        _check_field(d_out, self.shape, 6, "float64")
+        check(lib().fftg_apply_Gamma(self.handle, _dptr(d_in), _dptr(d_out), float(lam0), float(mu0)))
 
     def apply_GK(self, d_in, d_out, mode=FFTG_TANGENT_CURRENT, hist: "History" = None):
         """fftg_apply_GK: d_out = G:(C:d_in) on the plan's stream."""

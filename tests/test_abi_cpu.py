@@ -54,5 +54,5 @@ def test_struct_layouts_match_header():
     import ctypes as C
     from paper_1601_05970_amd import fftg
     assert C.sizeof(fftg.fftg_material) == 64
-    assert C.sizeof(fftg.fftg_options) == 72
+    assert C.sizeof(fftg.fftg_options) == 80
     assert C.sizeof(fftg.fftg_stats) == 4 + 4 * 64 + 4 + 8 * 64 + 8 * 6 + 4 + 4 + 8 + 8

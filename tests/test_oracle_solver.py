@@ -173,3 +173,58 @@ def test_cg_breakdown_on_indefinite_operator():
     b[0, 1, 1, 0, 0] = b[1, 0, 1, 0, 0] = 1.0
     res = S.cg(lambda p: -p, b, 1e-8)
     assert res.breakdown and res.iters == 0
+
+
+# ------------------------------------------------------------ basic scheme
+def _contrast(r, shape=(7, 7, 7)):
+    """Elastic two-phase RVE (never yields) with stiffness contrast r (both
+    moduli scaled): the tangent's eigenvalue ratio is r."""
+    ph = synth.bernoulli(shape, 0.3, 3)
+    soft = (0.833, 0.386, 1e30, 0.0, 1.0)
+    hard = (0.833 * r, 0.386 * r, 1e30, 0.0, 1.0)
+    return ph, [soft, hard]
+
+
+def test_gamma_ref_of_scaled_unit_tensor_is_scaled_G():
+    """Appendix A, Eq. Gamma_explicit: Gamma_ref is of degree -1 in C_ref, so
+    C_ref = c I_s gives G / c -- the reason the basic scheme with that
+    reference medium is Richardson's iteration with step 1/c on G C d = -G s."""
+    from oracle.j2 import I4S
+    from oracle.projection import gamma_ref_hat, ghat
+    shape = (5, 3, 7)
+    for c in (0.3, 2.5):
+        assert np.max(np.abs(gamma_ref_hat(shape, c * I4S) - ghat(shape) / c)) < 1e-14 / c
+
+
+def test_basic_scheme_reaches_the_galerkin_solution():
+    """The collocation system with Gamma_ref = G / c has the same solutions
+    as the Galerkin one (Sec. 3.2: the two formulations coincide up to the
+    solver), so Newton with the basic scheme lands on the CG result."""
+    w = synth.small_random((7, 9, 5), 0.35, 4, E_eq=0.01, n_inc=3)
+    a = S.Solver(w.phase, w.materials, 1e-9, 1e-11)
+    b = S.Solver(w.phase, w.materials, 1e-9, 1e-11, scheme="basic")
+    for n in range(1, 4):
+        sa, sb = a.solve_increment(w.E_at(n)), b.solve_increment(w.E_at(n))
+        assert sa.converged and sb.converged
+    assert np.max(np.abs(a.strain() - b.strain())) <= 1e-9 * 0.01
+    assert sum(sum(x) for x in [sb.cg_iters]) > sum(sa.cg_iters)
+    # one reference medium per linear solve, between the phases' elastic
+    # extremes 2G (deviatoric) and 3K (volumetric)
+    assert b.c_ref and all(0.0 < c < 3 * 0.833 for c in b.c_ref)
+
+
+def test_richardson_grows_with_kappa_and_cg_with_its_root():
+    """Sec. 3.2: with the optimal reference medium the basic scheme's
+    iteration count grows linearly with the tangent's eigenvalue ratio,
+    CG's with its square root.  Elastic contrast r = 2 and 16 (kappa 2, 16):
+    Richardson's count rises about 8-fold, CG's about 3-fold."""
+    counts = {}
+    for r in (2, 16):
+        ph, mats = _contrast(r)
+        for sch in ("galerkin", "basic"):
+            s = S.Solver(ph, mats, 1e-6, 1e-8, predictor="none", scheme=sch)
+            counts[(sch, r)] = s.solve_increment(synth.pure_shear_eq(0.01)).cg_iters[0]
+    rb = counts[("basic", 16)] / counts[("basic", 2)]
+    rc = counts[("galerkin", 16)] / counts[("galerkin", 2)]
+    assert 5.0 < rb < 12.0, counts
+    assert 2.0 < rc < 4.5, counts

@@ -364,6 +364,10 @@ def main():
                     help="profiling runs only: cut each load path to this many increments")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a device copy of MIB MiB 10 times (HBM counter calibration) and exit")
+    ap.add_argument("--serve", type=int, default=24, metavar="REQUESTS",
+                    help="served stream after the solves: this many requests of the serving recipe (sizes "
+                         "--serve-sizes), saturated and then Poisson at 0.8x the saturated rate; 0 for none")
+    ap.add_argument("--serve-sizes", default="31,63,127")
     ap.add_argument("--products", default="", metavar="N,N,...",
                     help="only time the product G:(Ce:p) (fftg_apply_GK, ELASTIC) on N^3 grids in FP64 and FP32 "
                          "and exit")
@@ -447,7 +451,36 @@ def main():
                 item["vs_fp64"] = {"strain_rel_err_max_over_rves": max(rel_err(a, b) for a, b in zip(st, ref["strain"]))}
             run.close()
             out["also"].append(item)
+    if args.serve:
+        out["serving"] = serve_stream(torch, args.serve, [int(n) for n in args.serve_sizes.split(",")])
     print(json.dumps(out))
+
+
+def serve_stream(torch, n_requests, sizes, rate_factor=0.8):
+    """The continuous-batching server on a stream of the serving recipe
+    (Voronoi RVEs of the listed sizes with the recipe's weights renormalised,
+    50-400 grains, 5-20 increments, FP64 or mixed at 50/50): first with every
+    request present at t = 0 (saturated throughput), then with Poisson
+    arrivals at rate_factor x that throughput; latency = completion - arrival."""
+    from paper_1601_05970_amd.serve import FftgExecutor, Server, summarize
+    allw = {31: 0.4, 63: 0.3, 127: 0.2, 255: 0.1}
+    wts = np.array([allw[n] for n in sizes])
+    wts = tuple(float(x) for x in wts / wts.sum())
+    free, _ = torch.cuda.mem_get_info()
+    ex = FftgExecutor()
+    base = synth.serving_stream(n_requests, rate=1e9, sizes=tuple(sizes), weights=wts)
+    for q in base:
+        q.arrival = 0.0
+    sat = summarize(Server(ex, int(0.8 * free)).run(base))
+    lam = rate_factor * sat["throughput_req_s"]
+    reqs = synth.serving_stream(n_requests, rate=lam, sizes=tuple(sizes), weights=wts)
+    run = summarize(Server(ex, int(0.8 * free)).run(reqs))
+    keep = ("requests", "ok", "p50_latency_s", "p99_latency_s", "mean_latency_s", "throughput_req_s",
+            "voxel_cg_iters_per_s", "makespan_s")
+    return {"workload": f"{n_requests} Poisson requests, Voronoi RVEs N in {sizes}, FP64/mixed 50/50, "
+                        f"5-20 increments; classes per precision and size, continuous batching",
+            "saturated": {k: sat[k] for k in keep},
+            "poisson": dict({k: run[k] for k in keep}, rate_factor=rate_factor, rate_req_s=lam)}
 
 
 if __name__ == "__main__":

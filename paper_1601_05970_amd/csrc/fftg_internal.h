@@ -100,7 +100,6 @@ struct RveDev {
   void* tang;                // 7 planes, double (FP64) or float (mixed)
   void* spec;                // 6 complex planes, sized for double
   const uint8_t* phase;
-  MatDev mats[kMaxPhases];
   int n_phases;
   int mixed;                 // apply precision: 0 double, 1 float
   CgState* cg;
@@ -111,6 +110,10 @@ struct RveDev {
   int tiles[P_NPASS];        // tiles of each pass for this RVE
   int skip;                  // 1: RVE masked out of batched launches
   int fold;                  // 1: CG scalar steps folded into the consumer kernels
+  // last: the kernels' scalar loads of the fields above stay within the
+  // first kilobyte (with the table in the middle, the CG pointer sat past
+  // 1.5 KB and the y and x passes of the 64-RVE batch ran 20 % slower)
+  MatDev mats[kMaxPhases];
 };
 
 // Apply modes (kernel flags)

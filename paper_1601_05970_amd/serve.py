@@ -8,12 +8,13 @@ increments, FP64 or mixed precision).  The server
   does not fit waits until finished requests free memory;
 * keeps every admitted request's plan and history (strain, plastic history,
   Krylov work buffers) resident on the device until it completes;
-* groups active requests into classes (precision x size band); each class is
-  advanced by its own worker thread on its own HIP stream, one increment of
-  every member per step, through one batched launch sequence
-  (fftg_batch_solve_increment).  Requests that arrive while a class is busy
-  join it at the next increment boundary, and different classes overlap on
-  the device;
+* groups active requests into classes (precision x grid size); each class
+  is advanced by its own worker thread on its own HIP stream, one increment
+  of every member per step, through one batched launch sequence
+  (fftg_batch_solve_increment) whose batch object persists until the class's
+  membership changes.  Requests that arrive while a class is busy join it at
+  the next increment boundary, and different classes overlap on the device:
+  a request never waits on the Newton loop of a request of another size;
 * records arrival, admission and completion times, so latency percentiles
   and throughput follow from the records.
 
@@ -83,14 +84,16 @@ def _tensor6(E):
 
 class FftgExecutor(Executor):
     """Executor on libfftg: one plan + history per request, one HIP stream
-    per class, batched increments per class."""
+    per class, batched increments per class through a batch that is kept
+    while the class's members stay the same."""
 
-    def __init__(self, size_split: int = 100):
+    def __init__(self, size_split: int = 0):
         import torch
         from . import fftg
         self.torch, self.fftg = torch, fftg
-        self.size_split = size_split
+        self.size_split = size_split     # > 0: two size bands instead of one class per grid size
         self.streams: Dict[Any, Any] = {}
+        self.batches: Dict[Any, Any] = {}   # class -> (member key, fftg.Batch)
         self.lock = threading.Lock()
 
     def footprint(self, req) -> int:
@@ -100,7 +103,9 @@ class FftgExecutor(Executor):
 
     def klass(self, req):
         w = req.workload
-        return (w.precision, "large" if max(w.shape) > self.size_split else "small")
+        if self.size_split > 0:
+            return (w.precision, "large" if max(w.shape) > self.size_split else "small")
+        return (w.precision, tuple(w.shape))
 
     def _stream(self, k):
         with self.lock:
@@ -123,18 +128,35 @@ class FftgExecutor(Executor):
             raise
         return (plan, hist)
 
+    def _batch(self, klass, plans, hists):
+        """The class's batch over exactly these members (rebuilt only when the
+        membership changed since the last step)."""
+        key = tuple(id(h) for h in hists)
+        with self.lock:
+            old = self.batches.get(klass)
+            if old is not None and old[0] == key:
+                return old[1]
+            if old is not None:
+                del self.batches[klass]
+        if old is not None:
+            old[1].close()
+        b = self.fftg.Batch(plans, hists)
+        with self.lock:
+            self.batches[klass] = (key, b)
+        return b
+
     def step(self, klass, handles, dEs):
-        fftg = self.fftg
         plans = [h[0] for h in handles]
         hists = [h[1] for h in handles]
         if len(handles) == 1:
+            with self.lock:
+                old = self.batches.pop(klass, None)
+            if old is not None:
+                old[1].close()
             st = [hists[0].solve_increment(_tensor6(dEs[0]), raise_on_error=False)]
         else:
-            b = fftg.Batch(plans, hists)
-            try:
-                st = b.solve_increment(np.array([_tensor6(d) for d in dEs]), raise_on_error=False)
-            finally:
-                b.close()
+            st = self._batch(klass, plans, hists).solve_increment(np.array([_tensor6(d) for d in dEs]),
+                                                                   raise_on_error=False)
         out = []
         for s in st:
             ok = bool(s["converged"])   # Newton converged (no breakdown, no cap)
@@ -144,6 +166,12 @@ class FftgExecutor(Executor):
 
     def release(self, handle):
         plan, hist = handle
+        # a batch that covers this member is dropped first (it refers to the history)
+        with self.lock:
+            drop = [k for k, (key, _) in self.batches.items() if id(hist) in key]
+            gone = [self.batches.pop(k)[1] for k in drop]
+        for b in gone:
+            b.close()
         hist.close()
         plan.close()
 

@@ -1,6 +1,8 @@
 """Served requests give the same results as the same requests solved alone
 (within the stated tolerance: 1e-10 FP64, 1e-6 mixed), with arrivals that
-overlap work already on the device."""
+overlap work already on the device: 15^3 requests join a class that is
+already stepping (its batch is rebuilt on the join and kept otherwise), and
+63^3 requests run in classes of their own beside the small ones."""
 import numpy as np
 import pytest
 
@@ -11,9 +13,10 @@ pytestmark = pytest.mark.gpu
 
 
 def _requests():
-    shapes = [(9, 9, 9), (15, 15, 15), (11, 13, 7), (15, 15, 15), (9, 11, 13), (13, 13, 13)]
-    precs = ["fp64", "mixed", "fp64", "fp64", "mixed", "mixed"]
-    arrivals = [0.0, 0.0, 0.002, 0.004, 0.006, 0.05]
+    shapes = [(9, 9, 9), (15, 15, 15), (11, 13, 7), (15, 15, 15), (9, 11, 13), (13, 13, 13), (63, 63, 63),
+              (15, 15, 15), (63, 63, 63)]
+    precs = ["fp64", "mixed", "fp64", "fp64", "mixed", "mixed", "fp64", "fp64", "mixed"]
+    arrivals = [0.0, 0.0, 0.002, 0.004, 0.006, 0.05, 0.01, 0.2, 0.3]
     out = []
     for i, (sh, pr, t) in enumerate(zip(shapes, precs, arrivals)):
         w = synth.small_random(sh, 0.35, 10 + i, E_eq=0.01, n_inc=3 + (i % 2))
@@ -36,10 +39,12 @@ def test_served_results_equal_alone():
     print("serve alone vs mix", flush=True)
     from paper_1601_05970_amd.serve import FftgExecutor, Server, summarize
     reqs = _requests()
-    srv = Server(FftgExecutor(size_split=12), 8 * 10 ** 9)
+    srv = Server(FftgExecutor(), 16 * 10 ** 9)
     recs = srv.run(reqs)
     assert all(r.status == "ok" for r in recs), [(r.rid, r.status, r.error) for r in recs]
-    for q, r in zip(reqs, recs):
+    by_id = {r.rid: r for r in recs}       # the server reports in arrival order
+    for q in reqs:
+        r = by_id[q.rid]
         ref = np.array(_alone(q.workload))
         got = np.array(r.sigma)
         tol = 1e-10 if q.workload.precision == "fp64" else 1e-6

@@ -152,3 +152,112 @@ def test_batch_of_config_sizes_equals_alone(precision):
         assert rel_err(got[0], alone[i][0][0]) < tol
         assert rel_err(got[1], alone[i][0][1]) < tol * 10
     b.close()
+
+
+def _fixture(name):
+    import os
+    d = np.load(os.path.join(os.path.dirname(__file__), "golden", name))
+    return {k: d[k] for k in d.files}
+
+
+def _sampled(h, fx, fftg):
+    idx = tuple(fx["sample"])
+    strain = m2t(to_host(h.get_field(fftg.FFTG_FIELD_STRAIN)))[(slice(None), slice(None)) + idx]
+    epbar = to_host(h.get_field(fftg.FFTG_FIELD_EPBAR))[0][idx]
+    return strain, epbar
+
+
+@pytest.mark.timeout(900)
+def test_voronoi127_fp64_lockstep_against_oracle_fixture():
+    """The 127^3 Voronoi workload in FP64 against the FP64 oracle's solve of
+    its first three increments (tests/golden/voronoi127_oracle.npz, written by
+    make_voronoi127_fixture.py from oracle/ and synth/ only): the GPU replays
+    the oracle's CG counts; Sigma after every increment, the total strain and
+    eps_p_bar at 4096 sampled voxels agree to 1e-10; the solve's own
+    ||G sigma||/||sigma|| agrees with the oracle's (and with the oracle's G
+    applied to the GPU's stress)."""
+    from paper_1601_05970_amd import fftg
+    fx = _fixture("voronoi127_oracle.npz")
+    w = synth.voronoi_127(precision="fp64")
+    print("full size", w.name, w.shape, "FP64 lockstep", flush=True)
+    pl = fftg.Plan(w.phase, w.materials, _opts(w))
+    h = fftg.History(pl)
+    off = fx["offsets"]
+    for n in range(1, len(off)):
+        ls = [int(c) for c in fx["cg_counts"][off[n - 1]:off[n]]]
+        st = h.solve_increment(tensor6(w.dE(n)), ls)
+        print("increment", n, "cg", st["cg_iters"], "rel_eq %.3e" % st["rel_equilibrium"], flush=True)
+        Sr = np.array(tensor6(fx["Sigma"][n - 1]))
+        assert np.max(np.abs(np.array(st["Sigma"]) - Sr)) <= 1e-10 * np.max(np.abs(Sr))
+        strain, epbar = _sampled(h, fx, fftg)
+        assert np.max(np.abs(strain - fx["strain_s"][n - 1])) <= 1e-10 * np.max(np.abs(fx["strain_s"][n - 1]))
+        if np.max(fx["epbar_s"][n - 1]) > 0:
+            assert np.max(np.abs(epbar - fx["epbar_s"][n - 1])) <= 1e-10 * np.max(fx["epbar_s"][n - 1])
+        re = fx["rel_eq"][n - 1]
+        assert abs(st["rel_equilibrium"] - re) <= 1e-3 * re + 1e-13
+    stress = m2t(to_host(h.get_field(fftg.FFTG_FIELD_STRESS)))
+    ref = float(np.linalg.norm(apply_G(stress)) / np.linalg.norm(stress))
+    assert abs(st["rel_equilibrium"] - ref) <= 1e-3 * ref + 1e-13
+
+
+def _natural_errors(fftg, w, opts, fixtures, n_inc):
+    """Natural-stopping solve of increments 1..n_inc; per increment and
+    fixture, the relative error of Sigma and of the sampled strain."""
+    pl = fftg.Plan(w.phase, w.materials, opts)
+    h = fftg.History(pl)
+    out = []
+    for n in range(1, n_inc + 1):
+        st = h.solve_increment(tensor6(w.dE(n)))
+        assert st["converged"]
+        strain, _ = _sampled(h, fixtures[0], fftg)
+        Sg = np.array(st["Sigma"])
+        row = []
+        for fx in fixtures:
+            Sr = np.array(tensor6(fx["Sigma"][n - 1]))
+            row.append((float(np.max(np.abs(Sg - Sr)) / np.max(np.abs(Sr))),
+                        float(np.max(np.abs(strain - fx["strain_s"][n - 1])) / np.max(np.abs(fx["strain_s"][n - 1])))))
+        out.append(row)
+    return out
+
+
+@pytest.mark.timeout(900)
+def test_voronoi127_accuracy_fp64_and_mixed():
+    """The 127^3 Voronoi workload solved with natural stopping, in FP64 and
+    with the FP32 product, against the FP64 oracle's discrete solution
+    (eta_NW 1e-10, eta_CG 1e-13: voronoi127_oracle_tight.npz) and its solve at
+    the configured tolerances (voronoi127_oracle.npz), over the first three
+    increments (the third is the first plastic one):
+    * at the configured tolerances (eta_NW 1e-5, eta_CG 1e-8) both GPU solves
+      sit at the tolerance's distance from the discrete solution (local strain
+      ~1e-5, Sigma ~1e-9), the mixed one no further than the FP64 one;
+    * against the oracle at the same configured tolerances the FP64 solve
+      agrees to 1e-10 and the mixed one to 1e-6;
+    * at tight tolerances (eta_NW 1e-10, eta_CG 1e-10) the mixed solve agrees
+      with the discrete solution to the 1e-6 mixed-precision bar.
+    The errors are printed for the record."""
+    from paper_1601_05970_amd import fftg
+    tight, conf = _fixture("voronoi127_oracle_tight.npz"), _fixture("voronoi127_oracle.npz")
+    n_inc = len(tight["offsets"]) - 1
+    res = {}
+    for prec, tn, tc in (("fp64", None, None), ("mixed", None, None), ("mixed", 1e-10, 1e-10)):
+        w = synth.voronoi_127(precision=prec)
+        o = _opts(w)
+        if tn is not None:
+            o.tol_newton, o.tol_cg = tn, tc
+        tag = prec + ("" if tn is None else " tight")
+        print("full size", w.name, w.shape, tag, "natural stopping", flush=True)
+        res[tag] = _natural_errors(fftg, w, o, (tight, conf), n_inc)
+        for n, row in enumerate(res[tag], start=1):
+            print(f"  {tag} increment {n}: vs discrete solution Sigma {row[0][0]:.2e} strain {row[0][1]:.2e}; "
+                  f"vs oracle at configured tolerances Sigma {row[1][0]:.2e} strain {row[1][1]:.2e}", flush=True)
+    for tag in ("fp64", "mixed"):
+        es, ee = res[tag][-1][0]
+        assert es <= 1e-8 and ee <= 5e-5, (tag, es, ee)
+    assert res["mixed"][-1][0][1] <= 2.0 * res["fp64"][-1][0][1] + 1e-6
+    # against the FP64 oracle at the same (configured) tolerances: the
+    # north-star bars, FP64 1e-10 and mixed 1e-6
+    for tag, bar in (("fp64", 1e-10), ("mixed", 1e-6)):
+        es, ee = res[tag][-1][1]
+        assert es <= bar and ee <= bar, (tag, es, ee)
+    es, ee = res["mixed tight"][-1][0]
+    assert es <= 1e-6 and ee <= 1e-6, (es, ee)

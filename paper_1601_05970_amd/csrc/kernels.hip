@@ -496,6 +496,11 @@ __global__ void __launch_bounds__(256) k_zfwd(const RveDev* __restrict__ rvs, in
                      "+s"(L.ax.g_tw)
                    :
                    : "memory");
+  // A launch over several RVEs tests the stop flag before any load, so that
+  // members that stopped in an earlier launch move no data (a single RVE
+  // loads it with its data).  Tile 0 may set the flag during this launch; a
+  // tile that already sees it takes the decision every tile takes.
+  if (check_done && !launch_single(nrve) && *gmem(&cg->done)) return;
   const int nrows_tot = n0 * n1;
   const int row0 = tile * rows_per_tile;
   const int nrows = min(rows_per_tile, nrows_tot - row0);
@@ -1037,6 +1042,8 @@ __global__ void __launch_bounds__(512) k_slab_fwd(const RveDev* __restrict__ rvs
                      "+s"(tang), "+s"(phase), "+s"(prr), "+s"(L.az.g_tw), "+s"(L.ay.g_tw)
                    :
                    : "memory");
+  // stop flag of a batched launch before any load (as in the z pass)
+  if (check_done && !launch_single(nrve) && *gmem(&cg->done)) return;
   const int x = tile / 3, pr = tile - 3 * (tile / 3);
   const long long v0 = (long long)x * n1 * n2;
   const int npl = n1 * n2;

@@ -347,6 +347,106 @@ __device__ void run_chain(cx<T>*& a, cx<T>*& b, int ld, int nl, const AxisLds<T>
   }
 }
 
+// Chains of compile-time length, each line owned by TL consecutive lanes of
+// one wavefront.  For the extents met most often (15, 63, 255) the radices,
+// butterfly counts and twiddle strides are constants, so a lane forms its
+// butterfly indices with a few integer operations, and the stages of a line
+// exchange data through LDS ordered by the wavefront alone: the LDS performs
+// one wavefront's operations in issue order, so a stage reads what the
+// previous one wrote without a workgroup barrier.  Same Stockham stages as
+// stockham_stage (butterfly j reads src[j + q M/R], twiddles by
+// w_M^(q k M/(Ns R)), k = j mod Ns, writes dst[(j - k) R + k + q Ns]).
+template <int TL_, int... Rs>
+struct CtSpec {
+  static constexpr int TL = TL_;                    // lanes per line
+  static constexpr int NST = (int)sizeof...(Rs);    // stages
+};
+template <int N>
+struct CtPlan {
+  static constexpr bool ok = false;
+};
+template <>
+struct CtPlan<15> {
+  static constexpr bool ok = true;
+  using spec = CtSpec<5, 3, 5>;     // 5 and 3 butterflies per stage
+};
+template <>
+struct CtPlan<63> {
+  static constexpr bool ok = true;
+  using spec = CtSpec<9, 9, 7>;     // 7 and 9 butterflies per stage
+};
+template <>
+struct CtPlan<255> {
+  static constexpr bool ok = true;
+  using spec = CtSpec<15, 3, 5, 17>;  // 85, 51 and 15 butterflies per stage
+};
+
+// Orders this wavefront's LDS accesses for the compiler (the hardware keeps
+// them in order); no instruction is emitted.
+__device__ __forceinline__ void wave_lds_order() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __asm__ volatile("" ::: "memory");
+}
+
+template <int R, int DIR, class T, int M, int NS, int TL>
+__device__ __forceinline__ void ct_stage(const cx<T>* src, cx<T>* dst, const cx<T>* __restrict__ tw, int g) {
+  constexpr int NB = M / R;
+  constexpr int TSTEP = M / (NS * R);
+  constexpr int IT = (NB + TL - 1) / TL;
+#pragma unroll 1
+  for (int it = 0; it < IT; ++it) {
+    const int j = g + it * TL;
+    if (NB % TL == 0 || it < IT - 1 || j < NB) {
+      const int k = NS > 1 ? j % NS : 0;
+      cx<T> v[R];
+#pragma unroll
+      for (int q = 0; q < R; ++q) v[q] = src[j + q * NB];
+      if constexpr (NS > 1) {
+#pragma unroll
+        for (int q = 1; q < R; ++q) {
+          cx<T> w = tw[q * k * TSTEP];
+          if (DIR > 0) w.im = -w.im;
+          v[q] = cmul(v[q], w);
+        }
+      }
+      cx<T>* d = dst + (j - k) * R + k;
+      Dft<R, DIR, T>::run_store(v, [&](int q, cx<T> x) { d[q * NS] = x; });
+    }
+  }
+}
+
+template <int DIR, class T, int M, int NS, int TL, int R, int... Rest>
+__device__ __forceinline__ void ct_run(cx<T>* a, cx<T>* b, const cx<T>* tw, int g) {
+  ct_stage<R, DIR, T, M, NS, TL>(a, b, tw, g);
+  wave_lds_order();
+  if constexpr (sizeof...(Rest) > 0) ct_run<DIR, T, M, NS * R, TL, Rest...>(b, a, tw, g);
+}
+
+template <int DIR, class T, int M, int TL, int... Rs>
+__device__ __forceinline__ void ct_line(cx<T>* a, cx<T>* b, const cx<T>* tw, int g, CtSpec<TL, Rs...>) {
+  ct_run<DIR, T, M, 1, TL, Rs...>(a, b, tw, g);
+}
+
+// nl lines of N points (stride ld) in line/scratch; returns the buffer that
+// holds the result.  Called by the whole workgroup (blockDim a multiple of
+// 64); ends with a workgroup barrier.
+template <int DIR, class T, int N>
+__device__ cx<T>* ct_fft(cx<T>* line, cx<T>* scratch, int ld, int nl, const cx<T>* tw) {
+  using S = typename CtPlan<N>::spec;
+  constexpr int TL = S::TL;
+  constexpr int G = 64 / TL;  // lines per wavefront
+  const int lane = (int)threadIdx.x & 63;
+  const int grp = lane / TL;
+  const int g = lane - grp * TL;
+  const int ngr = ((int)blockDim.x >> 6) * G;
+  if (grp < G) {
+    for (int l = ((int)threadIdx.x >> 6) * G + grp; l < nl; l += ngr)
+      ct_line<DIR, T, N>(line + l * ld, scratch + l * ld, tw, g, S{});
+  }
+  __syncthreads();
+  return (S::NST % 2 == 0) ? line : scratch;
+}
+
 // Direct DFT of nl odd-length lines: X_k = sum_j x_j w^(jk),
 // w = exp(-+ 2 pi i / N).  With s_j = x_j + x_(N-j) and d_j = x_j - x_(N-j)
 // (j = 1 .. (N-1)/2) and theta = 2 pi j k / N,
@@ -472,6 +572,11 @@ __device__ cx<T>* line_fft(cx<T>* line, cx<T>* scratch, int ld, int nl, const Ax
     return scratch;
   }
   if (P.rader == AX_CHAIN) {
+    if (P.M == 63) return ct_fft<DIR, T, 63>(line, scratch, ld, nl, P.tw);
+    if (P.M == 15) return ct_fft<DIR, T, 15>(line, scratch, ld, nl, P.tw);
+    if constexpr (BIG) {
+      if (P.M == 255) return ct_fft<DIR, T, 255>(line, scratch, ld, nl, P.tw);
+    }
     cx<T>* a = line;
     cx<T>* b = scratch;
     run_chain<DIR, T, BIG>(a, b, ld, nl, P);

@@ -342,6 +342,9 @@ def main(argv=None):
     args = ap.parse_args(argv)
     sizes = tuple(int(s) for s in args.sizes.split(","))
     weights = tuple(float(s) for s in args.weights.split(","))
+    if len(weights) != len(sizes) or min(weights) < 0 or sum(weights) <= 0:
+        ap.error("--weights needs one non-negative weight per size")
+    weights = tuple(w / sum(weights) for w in weights)   # renormalised over the sizes given
     free, _ = torch.cuda.mem_get_info()
     budget = int(args.budget_gb * 1e9) if args.budget_gb > 0 else int(0.8 * free)
     ex = FftgExecutor()

@@ -4,9 +4,11 @@
  * Method: Zeman, de Geus, Vondrejc, Peerlings, Geers, "A finite element
  * perspective on non-linear FFT-based micromechanical simulations"
  * (arXiv:1601.05970).  Given a periodic cell sampled on an odd regular grid
- * (Sec. 2.3), a phase map, isotropic J2 elasto-plastic phases (Sec. 4.2) and
- * a mean-strain path E(t), the library finds the fluctuating strain eps*
- * with G sigma(E + eps*) = 0 (Eq. nodal_equilibrium_equations) by the
+ * (Sec. 2.3), a phase map, phases of the three constitutive laws of Sec. 4
+ * (elasto-plasticity with power-law hardening, non-linear elasticity,
+ * visco-plasticity) and a mean-strain path E(t), the library finds the
+ * fluctuating strain eps* with G sigma(E + eps*) = 0 (Eq.
+ * nodal_equilibrium_equations) by the
  * incremental Newton--conjugate-gradient iteration of Algorithm 1, applying
  * the projection G = F^-1 G^ F (Eq. discrete_projection) matrix-free with
  * FFTs and G^(k) of Appendix A (Eq. FT_projection) evaluated on the fly.
@@ -151,7 +153,7 @@ typedef struct fftg_batch_s* fftg_batch;
  * mixed_cg_floor 1e-5, cg_chunk 16, dt 1, GALERKIN scheme. */
 void fftg_options_default(fftg_options* opt);
 
-/* Creates a plan for one RVE (Sec. 2.3 grid, Sec. 4.2 phases).
+/* Creates a plan for one RVE (Sec. 2.3 grid, Sec. 4 phases).
  * phase: host, n0*n1*n2 bytes, C order, values < n_phases.
  * mats: host, n_phases entries (n_phases <= 16).  opt: NULL = defaults.
  * hip_stream: a hipStream_t or NULL.  Allocates the device work buffers. */

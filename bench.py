@@ -475,8 +475,8 @@ def serve_stream(torch, n_requests, sizes, rate_factor=0.8):
     lam = rate_factor * sat["throughput_req_s"]
     reqs = synth.serving_stream(n_requests, rate=lam, sizes=tuple(sizes), weights=wts)
     run = summarize(Server(ex, int(0.8 * free)).run(reqs))
-    keep = ("requests", "ok", "p50_latency_s", "p99_latency_s", "mean_latency_s", "throughput_req_s",
-            "voxel_cg_iters_per_s", "makespan_s")
+    keep = ("requests", "ok", "failed", "p50_latency_s", "p99_latency_s", "mean_latency_s", "throughput_req_s",
+            "voxel_cg_iters_per_s", "makespan_s", "failures")
     return {"workload": f"{n_requests} Poisson requests, Voronoi RVEs N in {sizes}, FP64/mixed 50/50, "
                         f"5-20 increments; classes per precision and size, continuous batching",
             "saturated": {k: sat[k] for k in keep},

@@ -74,6 +74,12 @@ __device__ __forceinline__ void lds_gather(V* lds, const FFTG_GLOBAL V* g, int n
   }
 }
 
+// A compile-time integer passed by value (for generic lambdas).
+template <int V>
+struct IntC {
+  static constexpr int value = V;
+};
+
 template <class T>
 __device__ __forceinline__ cx<T> cadd(cx<T> a, cx<T> b) { return {a.re + b.re, a.im + b.im}; }
 template <class T>

@@ -208,9 +208,12 @@ __device__ __forceinline__ void tangent_apply(const T p[6], T K, T g2, const T m
 }
 
 // G^(k) : T for a complex Mandel vector t, q = xi/|xi| (Appendix A):
-// (G^ : T)_ij = q_i v_j + q_j v_i - (q.v) q_i q_j, v = T q.
+// (G^ : T)_ij = q_i v_j + q_j v_i - (q.v) q_i q_j, v = T q.  With q = xi
+// itself and as = 1/|xi|^2 (scale carrying another 1/|xi|^2) the same
+// expression gives G^ : T without the square root: every term is of degree
+// two in q once the (q.v) q q term carries the extra 1/|xi|^2.
 template <class T>
-__device__ __forceinline__ void ghat_apply(cx<T> t[6], T q0, T q1, T q2, T scale) {
+__device__ __forceinline__ void ghat_apply(cx<T> t[6], T q0, T q1, T q2, T scale, T as = T(1)) {
   const T r2 = T(1.0 / kSqrt2);
   cx<T> T11 = t[0], T22 = t[1], T33 = t[2];
   cx<T> T23 = {t[3].re * r2, t[3].im * r2};
@@ -219,7 +222,7 @@ __device__ __forceinline__ void ghat_apply(cx<T> t[6], T q0, T q1, T q2, T scale
   cx<T> v0 = {T11.re * q0 + T12.re * q1 + T13.re * q2, T11.im * q0 + T12.im * q1 + T13.im * q2};
   cx<T> v1 = {T12.re * q0 + T22.re * q1 + T23.re * q2, T12.im * q0 + T22.im * q1 + T23.im * q2};
   cx<T> v2 = {T13.re * q0 + T23.re * q1 + T33.re * q2, T13.im * q0 + T23.im * q1 + T33.im * q2};
-  cx<T> a = {q0 * v0.re + q1 * v1.re + q2 * v2.re, q0 * v0.im + q1 * v1.im + q2 * v2.im};
+  cx<T> a = {as * (q0 * v0.re + q1 * v1.re + q2 * v2.re), as * (q0 * v0.im + q1 * v1.im + q2 * v2.im)};
   const T s2 = T(kSqrt2) * scale;
   t[0] = {scale * (T(2) * q0 * v0.re - a.re * q0 * q0), scale * (T(2) * q0 * v0.im - a.im * q0 * q0)};
   t[1] = {scale * (T(2) * q1 * v1.re - a.re * q1 * q1), scale * (T(2) * q1 * v1.im - a.im * q1 * q1)};
@@ -667,21 +670,47 @@ __global__ void __launch_bounds__(256) k_xpass(const RveDev* __restrict__ rvs, i
   const int dn1 = cg_vaddr(cg)->done;  // unconditional: a guarded load would be waited for at its guard
   const long long rs = (long long)n1 * H;
   const long long off = (long long)i1 * H + h0;
-  const FastDiv fxn(n0 * nh), fnh(nh);
-  lds_gather<4>(
-      L.line, spec, 6 * n0 * nh,
-      [=](int t) {
-        const int cx_ = fxn.div(t);
-        const int r = t - cx_ * n0 * nh;
-        const int x = fnh.div(r);
-        return cx_ * nspec + x * rs + off + (r - x * nh);
-      },
-      [=](int t) {
-        const int cx_ = fxn.div(t);
-        const int r = t - cx_ * n0 * nh;
-        const int x = fnh.div(r);
-        return (cx_ * nh + (r - x * nh)) * ld + x;
-      });
+  const FastDiv fnh(nh);
+  // The tile's R = n0 nh pairs (x, hh), six components each.  For the
+  // gather and the scatter the threads form G groups (G the largest divisor
+  // of 6 with G R <= blockDim, else 1), group g owning components g, g + G,
+  // ...: a thread splits its pair index once and its component addresses
+  // differ by constants.  Line c nh + hh of LDS holds component c at kz
+  // index hh: element (c, x, hh) sits at c lcs + hh ld + x.
+  const int R = n0 * nh;
+  const int bd = blockDim.x;
+  const int G = (6 * R <= bd) ? 6 : (3 * R <= bd) ? 3 : (2 * R <= bd) ? 2 : 1;
+  const FastDiv fR(R);
+  const int grp = (G > 1) ? fR.div(threadIdx.x) : 0;
+  const int r0 = (int)threadIdx.x - grp * R;
+  const int rstep = (G > 1) ? R : bd;   // G > 1: one pair per thread
+  const int lcs = nh * ld;
+  const long long gstr = (long long)G * nspec;
+  auto xmove = [&](auto nu_c, auto&& op) {
+    constexpr int NU = decltype(nu_c)::value;
+    if (grp >= G) return;
+    for (int r = r0; r < R; r += rstep) {
+      const int x = fnh.div(r);
+      const int hh = r - x * nh;
+      op(IntC<NU>{}, spec + (long long)x * rs + off + hh + grp * nspec, hh * ld + x + grp * lcs);
+    }
+  };
+  auto xmove_any = [&](auto&& op) {
+    switch (G) {
+      case 6: xmove(IntC<1>{}, op); break;
+      case 3: xmove(IntC<2>{}, op); break;
+      case 2: xmove(IntC<3>{}, op); break;
+      default: xmove(IntC<6>{}, op); break;
+    }
+  };
+  xmove_any([&](auto nu_c, const FFTG_GLOBAL cx<T>* g, int l) {
+    constexpr int NU = decltype(nu_c)::value;
+    cx<T> v[NU];
+#pragma unroll
+    for (int u = 0; u < NU; ++u) v[u] = gload(g + u * gstr);
+#pragma unroll
+    for (int u = 0; u < NU; ++u) L.line[l + u * G * lcs] = v[u];
+  });
   axis_lds_store<T>(L.ax, tf);
   if (check_done && single && dn1) return;
   __syncthreads();
@@ -689,6 +718,7 @@ __global__ void __launch_bounds__(256) k_xpass(const RveDev* __restrict__ rvs, i
   cx<T>* oth = (res == L.line) ? L.scratch : L.line;
   // projection on every frequency (k0, k1, k2) of the tile; xi_i = k_i / L_i, L_i = n_i
   const T scale = T(scale_in / double(nvox));   // inverse DFT normalisation 1/|N|
+  const double inv_n0 = 1.0 / double(n0), inv_n2 = 1.0 / double(n2);
   const double k1 = double(sfreq(i1, n1)) / double(n1);
   T lam0 = T(0), mu0 = T(0);
   if constexpr (GAMMA) {
@@ -696,25 +726,28 @@ __global__ void __launch_bounds__(256) k_xpass(const RveDev* __restrict__ rvs, i
     lam0 = T(g->lam0);
     mu0 = T(g->mu0);
   }
-  for (int t = threadIdx.x; t < n0 * nh; t += blockDim.x) {
+  for (int t = threadIdx.x; t < R; t += bd) {
     const int x = fnh.div(t);
     const int hh = t - x * nh;
-    const double k0 = double(sfreq(x, n0)) / double(n0);
-    const double k2 = double(h0 + hh) / double(n2);
+    const double k0 = double(sfreq(x, n0)) * inv_n0;
+    const double k2 = double(h0 + hh) * inv_n2;
     const double nn = k0 * k0 + k1 * k1 + k2 * k2;
+    cx<T>* const e = res + hh * ld + x;
     cx<T> v[6];
 #pragma unroll
-    for (int c = 0; c < 6; ++c) v[c] = res[(c * nh + hh) * ld + x];
+    for (int c = 0; c < 6; ++c) v[c] = e[c * lcs];
     if (nn == 0.0) {
 #pragma unroll
       for (int c = 0; c < 6; ++c) v[c] = cx<T>{T(0), T(0)};
-    } else {
+    } else if constexpr (GAMMA) {
       const double inv = 1.0 / sqrt(nn);
-      if constexpr (GAMMA) gamma_apply<T>(v, T(k0 * inv), T(k1 * inv), T(k2 * inv), lam0, mu0, scale);
-      else ghat_apply<T>(v, T(k0 * inv), T(k1 * inv), T(k2 * inv), scale);
+      gamma_apply<T>(v, T(k0 * inv), T(k1 * inv), T(k2 * inv), lam0, mu0, scale);
+    } else {
+      const double i2 = 1.0 / nn;
+      ghat_apply<T>(v, T(k0), T(k1), T(k2), T(double(scale) * i2), T(i2));
     }
 #pragma unroll
-    for (int c = 0; c < 6; ++c) res[(c * nh + hh) * ld + x] = v[c];
+    for (int c = 0; c < 6; ++c) e[c * lcs] = v[c];
   }
   __syncthreads();
   if constexpr (NF > 0) {
@@ -735,13 +768,11 @@ __global__ void __launch_bounds__(256) k_xpass(const RveDev* __restrict__ rvs, i
         });
   } else {
     cx<T>* res2 = line_fft<1, T, BIG, NF>(res, oth, ld, nl, L.ax, L.dc);
-    for (int t = threadIdx.x; t < 6 * n0 * nh; t += blockDim.x) {
-      const int cx_ = fxn.div(t);
-      const int r = t - cx_ * n0 * nh;
-      const int x = fnh.div(r);
-      const int hh = r - x * nh;
-      gstore(spec + cx_ * nspec + x * rs + off + hh, res2[(cx_ * nh + hh) * ld + x]);
-    }
+    xmove_any([&](auto nu_c, FFTG_GLOBAL cx<T>* g, int l) {
+      constexpr int NU = decltype(nu_c)::value;
+#pragma unroll
+      for (int u = 0; u < NU; ++u) gstore(g + u * gstr, res2[l + u * G * lcs]);
+    });
   }
 }
 
@@ -844,23 +875,25 @@ __global__ void __launch_bounds__(256) k_zinv(const RveDev* __restrict__ rvs, in
   const bool late = cg_out && launch_single(nrve);
   if (check_done && !late && *gmem(&cg->done)) return;
   const AxisFetch<T> tf = axis_lds_fetch<T>(L.ax);
-  // Z_k = A_k + i B_k, Z_{n-k} = conj(A_k) + i conj(B_k).  Loads are issued
-  // in program order before anything that waits: this thread's first two
-  // elements, then the partials (a loop that waits as it sums), then the
-  // stop flag; the LDS stores come after.
-  const FastDiv fn2(n2), f3(3);
-  const int ne = nrows * 3 * n2;
+  // Z_k = A_k + i B_k, Z_{n-k} = conj(A_k) + i conj(B_k): each pair (A_k,
+  // B_k) of the half spectrum is loaded once and fills both z = k and
+  // z = n - k of its packed line.  Loads are issued in program order before
+  // anything that waits: this thread's first two pairs, then the partials (a
+  // loop that waits as it sums), then the stop flag; the LDS stores come
+  // after.
+  const FastDiv fn2(n2), fH(H), f3(3);
+  const int ne = nrows * 3 * H;
   const int bd = blockDim.x;
   cx<T> A[2], B[2];
   int ti[2];
   auto load2 = [&](int t0) {
 #pragma unroll
     for (int u = 0; u < 2; ++u) {
-      ti[u] = min(t0 + u * bd, ne - 1);
-      const int rp = fn2.div(ti[u]);
-      const int z = ti[u] - rp * n2;
+      ti[u] = min(t0 + u * bd, ne - 1);  // past the end: the last pair again, same values to the same places
+      const int rp = fH.div(ti[u]);
+      const int k = ti[u] - rp * H;
       const int r = f3.div(rp), pr = rp - 3 * r;
-      const long long o = (long long)(row0 + r) * H + (z < H ? z : n2 - z);
+      const long long o = (long long)(row0 + r) * H + k;
       A[u] = gload(spec + (2 * pr) * nspec + o);
       B[u] = gload(spec + (2 * pr + 1) * nspec + o);
     }
@@ -868,10 +901,11 @@ __global__ void __launch_bounds__(256) k_zinv(const RveDev* __restrict__ rvs, in
   auto store2 = [&]() {
 #pragma unroll
     for (int u = 0; u < 2; ++u) {
-      const int rp = fn2.div(ti[u]);
-      const int z = ti[u] - rp * n2;
-      L.line[rp * ld + z] = z < H ? cx<T>{A[u].re - B[u].im, A[u].im + B[u].re}
-                                  : cx<T>{A[u].re + B[u].im, -A[u].im + B[u].re};
+      const int rp = fH.div(ti[u]);
+      const int k = ti[u] - rp * H;
+      cx<T>* const ln = L.line + rp * ld;
+      ln[k] = cx<T>{A[u].re - B[u].im, A[u].im + B[u].re};
+      if (k > 0) ln[n2 - k] = cx<T>{A[u].re + B[u].im, -A[u].im + B[u].re};
     }
   };
   load2(threadIdx.x);

@@ -160,8 +160,12 @@ class FftgExecutor(Executor):
         out = []
         for s in st:
             ok = bool(s["converged"])   # Newton converged (no breakdown, no cap)
-            out.append({"ok": ok, "Sigma": s["Sigma"], "cg": s["total_cg"],
-                        "error": "" if ok else f"status {s['status']}"})
+            err = ""
+            if not ok:
+                res = s.get("newton_res") or [float("nan")]
+                err = (f"status {s['status']} after {s.get('newton_iters', len(res))} Newton iterations, "
+                       f"last residual {res[-1]:.3g}")
+            out.append({"ok": ok, "Sigma": s["Sigma"], "cg": s["total_cg"], "error": err})
         return out
 
     def release(self, handle):
@@ -227,8 +231,9 @@ class Server:
                 self.busy[k] = False
             for rec, h in finished:
                 if self.verbose:
+                    why = f" in increment {rec.done_inc + 1} of {rec.n_inc}: {rec.error}" if rec.status == "failed" else ""
                     print(f"serve: request {rec.rid} {rec.status} shape {rec.shape} {rec.precision} "
-                          f"latency {rec.latency:.3f} s", flush=True)
+                          f"latency {rec.latency:.3f} s{why}", flush=True)
                 try:
                     self.ex.release(h)
                 finally:
@@ -320,7 +325,10 @@ def summarize(records: Sequence[Record]) -> dict:
             "mean_latency_s": float(np.mean(lat)),
             "throughput_req_s": len(ok) / max(t_end - t_start, 1e-9),
             "voxel_cg_iters_per_s": vox_cg / max(t_end - t_start, 1e-9),
-            "makespan_s": t_end - t_start}
+            "makespan_s": t_end - t_start,
+            "failures": [{"rid": r.rid, "shape": list(r.shape), "precision": r.precision,
+                          "increment": r.done_inc + 1, "of": r.n_inc, "error": r.error}
+                         for r in records if r.status == "failed"]}
 
 
 def main(argv=None):

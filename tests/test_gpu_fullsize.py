@@ -124,7 +124,10 @@ def test_batch_of_config_sizes_equals_alone(precision):
     """Members of the 64-RVE batch recipe at its three sizes (63^3, 15^3,
     31^3) batched and alone over four increments, in FP64 and with the FP32
     product: batched launches give each member the result it gets alone (FP64
-    to 1e-10 with identical CG counts; mixed to the FP32 product's level)."""
+    to 1e-10 with the same Newton iterations, their CG counts equal or one
+    apart where a count sits at the stopping tolerance: batched and single
+    launches use different tiles, so the partial sums of r.r add up in a
+    different order; mixed to the FP32 product's level)."""
     from paper_1601_05970_amd import fftg
     ws = [synth.batch_rve(r, precision=precision) for r in (0, 3, 6)]
     print("batch vs alone", precision, [w.shape for w in ws], flush=True)
@@ -145,7 +148,8 @@ def test_batch_of_config_sizes_equals_alone(precision):
         print("increment", n, "cg", [s_["cg_iters"] for s_ in st], flush=True)
         for i in range(len(ws)):
             if precision == "fp64":
-                assert st[i]["cg_iters"] == alone[i][1][n - 1]["cg_iters"]
+                a, b_ = alone[i][1][n - 1]["cg_iters"], st[i]["cg_iters"]
+                assert len(a) == len(b_) and all(abs(x - y) <= 1 for x, y in zip(a, b_)), (a, b_)
     tol = 1e-10 if precision == "fp64" else 1e-6
     for i, h in enumerate(hists):
         got = [to_host(h.get_field(k)) for k in (fftg.FFTG_FIELD_STRAIN, fftg.FFTG_FIELD_EPBAR)]

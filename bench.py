@@ -471,14 +471,15 @@ def serve_stream(torch, n_requests, sizes, rate_factor=0.8):
     base = synth.serving_stream(n_requests, rate=1e9, sizes=tuple(sizes), weights=wts)
     for q in base:
         q.arrival = 0.0
-    sat = summarize(Server(ex, int(0.8 * free)).run(base))
+    sat = summarize(Server(ex, int(0.8 * free), max_split=3).run(base))
     lam = rate_factor * sat["throughput_req_s"]
     reqs = synth.serving_stream(n_requests, rate=lam, sizes=tuple(sizes), weights=wts)
-    run = summarize(Server(ex, int(0.8 * free)).run(reqs))
+    run = summarize(Server(ex, int(0.8 * free), max_split=3).run(reqs))
     keep = ("requests", "ok", "failed", "p50_latency_s", "p99_latency_s", "mean_latency_s", "throughput_req_s",
-            "voxel_cg_iters_per_s", "makespan_s", "failures")
+            "voxel_cg_iters_per_s", "makespan_s", "failures", "split_increments")
     return {"workload": f"{n_requests} Poisson requests, Voronoi RVEs N in {sizes}, FP64/mixed 50/50, "
-                        f"5-20 increments; classes per precision and size, continuous batching",
+                        f"5-20 increments; classes per precision and size, continuous batching; an increment whose "
+                        f"Newton iteration fails is halved, up to 3 times",
             "saturated": {k: sat[k] for k in keep},
             "poisson": dict({k: run[k] for k in keep}, rate_factor=rate_factor, rate_req_s=lam)}
 

@@ -383,6 +383,22 @@ class History:
         buf = C.create_string_buffer(data, len(data))
         check(lib().fftg_history_restore(self.plan.handle, self.handle, buf, len(data)))
 
+    def checkpoint_bytes(self) -> int:
+        n = C.c_size_t(0)
+        check(lib().fftg_history_save(self.plan.handle, self.handle, None, C.byref(n)))
+        return n.value
+
+    def save_into(self, ptr: int, size: int) -> int:
+        """fftg_history_save into caller memory at host address ptr (size
+        bytes, e.g. a pinned tensor's data_ptr()); returns the bytes written."""
+        n = C.c_size_t(size)
+        check(lib().fftg_history_save(self.plan.handle, self.handle, C.c_void_p(ptr), C.byref(n)))
+        return n.value
+
+    def restore_from(self, ptr: int, size: int):
+        """fftg_history_restore from host address ptr."""
+        check(lib().fftg_history_restore(self.plan.handle, self.handle, C.c_void_p(ptr), size))
+
 
 class Batch:
     """fftg_batch_create / fftg_batch_solve_increment over (plan, history) pairs."""

@@ -16,7 +16,15 @@ increments, FP64 or mixed precision).  The server
   the next increment boundary, and different classes overlap on the device:
   a request never waits on the Newton loop of a request of another size;
 * records arrival, admission and completion times, so latency percentiles
-  and throughput follow from the records.
+  and throughput follow from the records;
+* optionally (max_split > 0) splits an increment whose Newton iteration
+  fails (iteration cap, breakdown) into two halves, up to max_split times:
+  the request's state is copied to host memory at every increment boundary
+  and restored before the halves run.  Algorithm 1 with a large load step
+  can stall on an elasto-plastic microstructure (the Newton update keeps
+  the same size from one iteration to the next) where half the step
+  converges; the split path follows the same mean-strain path with finer
+  increments.
 
 The executor interface (footprint / admit / step / release) separates the
 scheduling logic from the device, so the scheduler is testable on the CPU
@@ -48,6 +56,9 @@ class Record:
     sigma: List[List[float]] = dataclasses.field(default_factory=list)
     cg_iters: int = 0
     error: str = ""
+    # sub-steps left in the current increment: (fraction of its dE, halvings)
+    parts: List[Any] = dataclasses.field(default_factory=lambda: [(1.0, 0)])
+    splits: int = 0
 
     @property
     def latency(self) -> Optional[float]:
@@ -77,6 +88,14 @@ class Executor:
     def release(self, handle) -> None:
         raise NotImplementedError
 
+    def checkpoint(self, handle) -> Any:
+        """Host copy of a request's state at an increment boundary, for
+        splitting an increment that fails; None when not supported."""
+        return None
+
+    def restore(self, handle, ckpt) -> None:
+        raise NotImplementedError
+
 
 def _tensor6(E):
     return [E[0, 0], E[1, 1], E[2, 2], E[1, 2], E[0, 2], E[0, 1]]
@@ -94,6 +113,7 @@ class FftgExecutor(Executor):
         self.size_split = size_split     # > 0: two size bands instead of one class per grid size
         self.streams: Dict[Any, Any] = {}
         self.batches: Dict[Any, Any] = {}   # class -> (member key, fftg.Batch)
+        self.ckpt_bufs: Dict[int, Any] = {}  # id(history) -> pinned host buffer
         self.lock = threading.Lock()
 
     def footprint(self, req) -> int:
@@ -168,8 +188,28 @@ class FftgExecutor(Executor):
             out.append({"ok": ok, "Sigma": s["Sigma"], "cg": s["total_cg"], "error": err})
         return out
 
+    def checkpoint(self, handle):
+        """The history's state in a pinned host buffer kept per request
+        (fftg_history_save); the buffer is reused at every step."""
+        plan, hist = handle
+        with self.lock:
+            buf = self.ckpt_bufs.get(id(hist))
+        if buf is None:
+            buf = self.torch.empty(hist.checkpoint_bytes(), dtype=self.torch.uint8, pin_memory=True)
+            with self.lock:
+                self.ckpt_bufs[id(hist)] = buf
+        n = hist.save_into(buf.data_ptr(), buf.numel())
+        return (buf, n)
+
+    def restore(self, handle, ckpt):
+        plan, hist = handle
+        buf, n = ckpt
+        hist.restore_from(buf.data_ptr(), n)
+
     def release(self, handle):
         plan, hist = handle
+        with self.lock:
+            self.ckpt_bufs.pop(id(hist), None)
         # a batch that covers this member is dropped first (it refers to the history)
         with self.lock:
             drop = [k for k, (key, _) in self.batches.items() if id(hist) in key]
@@ -184,9 +224,10 @@ class Server:
     """Admission + per-class stepping workers; see the module docstring."""
 
     def __init__(self, executor: Executor, mem_budget: int, clock: Callable[[], float] = time.perf_counter,
-                 verbose: bool = False):
+                 verbose: bool = False, max_split: int = 0):
         self.ex = executor
         self.verbose = verbose
+        self.max_split = int(max_split)
         self.budget = int(mem_budget)
         self.clock = clock
         self.cv = threading.Condition()
@@ -207,20 +248,46 @@ class Server:
                 members = list(self.active[k])
                 self.busy[k] = True
             handles = [m[1] for m in members]
-            dEs = [m[2].workload.dE(m[0].done_inc + 1) for m in members]
+            parts = [m[0].parts[0] for m in members]
+            dEs = [m[2].workload.dE(m[0].done_inc + 1) * f for m, (f, _) in zip(members, parts)]
+            ckpts = [None] * len(members)
+            if self.max_split > 0:
+                try:
+                    ckpts = [self.ex.checkpoint(h) for h in handles]
+                except Exception as e:   # no checkpoint: the step runs without the split fallback
+                    self.errors.append(f"checkpoint failed: {e!r}")
+                    ckpts = [None] * len(members)
             try:
                 res = self.ex.step(k, handles, dEs)
             except Exception as e:  # the whole step failed: fail its members only
                 res = [{"ok": False, "Sigma": [0.0] * 6, "cg": 0, "error": repr(e)} for _ in members]
+            # members whose sub-step failed and may be split: restored before
+            # the next step (this thread owns the class's members between steps)
+            for (rec, h, req), r, (f, depth), ck in zip(members, res, parts, ckpts):
+                if r["ok"] or ck is None or depth >= self.max_split:
+                    continue
+                try:
+                    self.ex.restore(h, ck)
+                    r["split"] = True
+                except Exception as e:
+                    r["error"] = f"{r.get('error', '')}; restore failed: {e!r}"
             now = self.clock() - t0
             finished = []
             with self.cv:
-                for (rec, h, req), r in zip(members, res):
+                for (rec, h, req), r, (f, depth) in zip(members, res, parts):
                     rec.cg_iters += int(r.get("cg", 0))
                     if not r["ok"]:
+                        if r.get("split"):
+                            rec.parts[0:1] = [(0.5 * f, depth + 1), (0.5 * f, depth + 1)]
+                            rec.splits += 1
+                            continue
                         rec.status, rec.error, rec.finished = "failed", r.get("error", ""), now
                         finished.append((rec, h))
                         continue
+                    rec.parts.pop(0)
+                    if rec.parts:
+                        continue             # more sub-steps of this increment
+                    rec.parts = [(1.0, 0)]
                     rec.sigma.append(list(r["Sigma"]))
                     rec.done_inc += 1
                     if rec.done_inc == rec.n_inc:
@@ -326,6 +393,7 @@ def summarize(records: Sequence[Record]) -> dict:
             "throughput_req_s": len(ok) / max(t_end - t_start, 1e-9),
             "voxel_cg_iters_per_s": vox_cg / max(t_end - t_start, 1e-9),
             "makespan_s": t_end - t_start,
+            "split_increments": sum(r.splits for r in records),
             "failures": [{"rid": r.rid, "shape": list(r.shape), "precision": r.precision,
                           "increment": r.done_inc + 1, "of": r.n_inc, "error": r.error}
                          for r in records if r.status == "failed"]}
@@ -347,6 +415,8 @@ def main(argv=None):
     ap.add_argument("--sizes", default="31,63,127,255")
     ap.add_argument("--weights", default="0.4,0.3,0.2,0.1")
     ap.add_argument("--budget-gb", type=float, default=0.0, help="0: 80 %% of free device memory")
+    ap.add_argument("--max-split", type=int, default=3,
+                    help="halvings allowed for an increment whose Newton iteration fails (0: fail the request)")
     args = ap.parse_args(argv)
     sizes = tuple(int(s) for s in args.sizes.split(","))
     weights = tuple(float(s) for s in args.weights.split(","))
@@ -360,14 +430,14 @@ def main(argv=None):
     base = synth.serving_stream(args.requests, rate=1e9, sizes=sizes, weights=weights)
     for q in base:
         q.arrival = 0.0
-    srv = Server(ex, budget, verbose=True)
+    srv = Server(ex, budget, verbose=True, max_split=args.max_split)
     sat = summarize(srv.run(base))
     out = {"saturated": sat, "budget_bytes": budget, "max_used_bytes": srv.max_used, "runs": []}
     print(json.dumps({"saturated": sat}), flush=True)
     for f in [float(x) for x in args.rate_factors.split(",") if x]:
         lam = f * sat["throughput_req_s"]
         reqs = synth.serving_stream(args.requests, rate=lam, sizes=sizes, weights=weights)
-        srv = Server(ex, budget, verbose=True)
+        srv = Server(ex, budget, verbose=True, max_split=args.max_split)
         s = summarize(srv.run(reqs))
         s["rate_factor"], s["rate_req_s"] = f, lam
         out["runs"].append(s)

@@ -7,7 +7,7 @@ import numpy as np
 import pytest
 
 import synth
-from tests.gpu_util import tensor6
+from tests.gpu_util import tensor6, to_host
 
 pytestmark = pytest.mark.gpu
 
@@ -52,3 +52,28 @@ def test_served_results_equal_alone():
         assert np.max(np.abs(got - ref)) <= tol * np.max(np.abs(ref)), (q.rid, q.workload.precision)
     s = summarize(recs)
     assert s["ok"] == len(reqs)
+
+
+def test_executor_checkpoint_restore_replays_an_increment():
+    """The state the server restores before splitting an increment: a
+    checkpoint taken at an increment boundary (pinned host buffer), one
+    increment solved, the checkpoint restored and the same increment solved
+    again gives the same Sigma and strain bit for bit."""
+    print("serve checkpoint/restore", flush=True)
+    from paper_1601_05970_amd import fftg
+    from paper_1601_05970_amd.serve import FftgExecutor
+    w = synth.small_random((15, 15, 15), 0.35, 3, E_eq=0.01, n_inc=3)
+    q = synth.Request(0, 0.0, w)
+    ex = FftgExecutor()
+    h = ex.admit(q)
+    k = ex.klass(q)
+    ex.step(k, [h], [w.dE(1)])
+    ck = ex.checkpoint(h)
+    a = ex.step(k, [h], [w.dE(2)])[0]
+    sa = to_host(h[1].get_field(fftg.FFTG_FIELD_STRAIN))
+    ex.restore(h, ck)
+    b = ex.step(k, [h], [w.dE(2)])[0]
+    sb = to_host(h[1].get_field(fftg.FFTG_FIELD_STRAIN))
+    assert a["ok"] and b["ok"] and a["Sigma"] == b["Sigma"]
+    assert np.array_equal(sa, sb)
+    ex.release(h)

@@ -123,3 +123,62 @@ def test_oversized_request_is_rejected():
     srv = Server(ScriptedExecutor(), 1000)
     recs = srv.run(reqs)
     assert recs[0].status == "rejected" and recs[1].status == "ok"
+
+
+class SplittingExecutor(ScriptedExecutor):
+    """Steps of request `rid` fail while its dE exceeds `limit` (a load step
+    too large for Newton); checkpoint / restore copy the scripted state."""
+
+    def __init__(self, rid, limit):
+        super().__init__()
+        self.rid, self.limit = rid, limit
+        self.restores = 0
+
+    def step(self, klass, handles, dEs):
+        out = super().step(klass, handles, dEs)
+        for h, dE, o in zip(handles, dEs, out):
+            if h["rid"] == self.rid and float(dE[0, 0]) > self.limit:
+                o.update(ok=False, error="scripted Newton cap")
+        return out
+
+    def checkpoint(self, h):
+        return dict(h)
+
+    def restore(self, h, ck):
+        h.update(ck)
+        self.restores += 1
+
+
+def test_failed_increment_is_split_and_the_request_completes():
+    """Request 0's steps fail while dE > 0.9 (increment n has dE = n): the
+    server restores the state and halves the failing sub-step, so increment
+    1 runs as 0.5 x 2, increment 2 as 0.5 x 4, increment 3 as 0.75 x 4 and
+    increment 4 as 0.5 x 8 (three halvings, the limit); the converged
+    sub-steps add up to each increment, one Sigma is recorded per increment,
+    and with max_split = 0 the same request fails."""
+    reqs = [FakeReq(0, 0.0, (9, 9, 9), 4), FakeReq(1, 0.0, (9, 9, 9), 3)]
+    ex = SplittingExecutor(0, 0.9)
+    srv = Server(ex, 10 ** 9, max_split=3)
+    recs = srv.run(reqs)
+    r0 = recs[0]
+    assert r0.status == "ok" and recs[1].status == "ok"
+    assert len(r0.sigma) == r0.n_inc == 4 and r0.done_inc == 4
+    seen = ex.seen_dE[0]
+    assert abs(sum(v for v in seen if v <= ex.limit) - (1 + 2 + 3 + 4)) < 1e-12
+    assert sorted(set(v for v in seen if v <= ex.limit)) == [0.5, 0.75]
+    assert r0.splits == ex.restores > 0
+    assert summarize(recs)["split_increments"] == r0.splits
+    assert not ex.live
+    ex2 = SplittingExecutor(0, ex.limit)
+    recs2 = Server(ex2, 10 ** 9, max_split=0).run(reqs)
+    assert recs2[0].status == "failed" and recs2[1].status == "ok"
+
+
+def test_split_depth_is_bounded():
+    """A step that fails at every size fails the request after max_split
+    halvings of one increment."""
+    reqs = [FakeReq(0, 0.0, (9, 9, 9), 2)]
+    ex = SplittingExecutor(0, -1.0)      # every dE fails
+    recs = Server(ex, 10 ** 9, max_split=2).run(reqs)
+    assert recs[0].status == "failed" and recs[0].splits == 2   # 1 -> 1/2 -> 1/4, which fails at the limit
+    assert ex.seen_dE[0] == [1.0, 0.5, 0.25]

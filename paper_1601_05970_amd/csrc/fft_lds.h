@@ -453,6 +453,60 @@ __device__ cx<T>* ct_fft(cx<T>* line, cx<T>* scratch, int ld, int nl, const cx<T
   return (S::NST % 2 == 0) ? line : scratch;
 }
 
+// Rader's algorithm for a prime N whose convolution length M = N - 1 has a
+// compile-time chain, each line owned by TL lanes of one wavefront (as
+// ct_fft): gather a_q = x_(g^q) into scratch, forward chain, multiply by
+// DFT_M(b)/M (keeping a's DFT at 0, the sum of x_1..x_(N-1)), inverse chain,
+// then X_(g^-m) = x_0 + (a (*) b)_m and X_0 = x_0 + that sum.  Every step is
+// line-local, so the steps are ordered by the wavefront alone; the chains
+// ping-pong between scratch and line + 1 (x_0 stays in line[0]).
+template <int N>
+struct CtRader {
+  static constexpr bool ok = false;
+};
+template <>
+struct CtRader<127> {
+  static constexpr bool ok = true;
+  using spec = CtSpec<9, 2, 7, 9>;   // 126 = 2 7 9: 63, 18 and 14 butterflies per stage
+};
+
+template <int DIR, class T, int N>
+__device__ cx<T>* ct_rader(cx<T>* line, cx<T>* scratch, int ld, int nl, const AxisLds<T>& P, cx<T>* dc) {
+  using S = typename CtRader<N>::spec;
+  constexpr int M = N - 1;
+  constexpr int TL = S::TL;
+  constexpr int G = 64 / TL;
+  static_assert(S::NST % 2 == 1, "the scatter below reads the inverse chain's result from scratch");
+  const int lane = (int)threadIdx.x & 63;
+  const int grp = lane / TL;
+  const int g = lane - grp * TL;
+  const int ngr = ((int)blockDim.x >> 6) * G;
+  const cx<T>* bh = DIR < 0 ? P.bf : P.bi;
+  if (grp < G) {
+    for (int l = ((int)threadIdx.x >> 6) * G + grp; l < nl; l += ngr) {
+      cx<T>* const ln = line + l * ld;
+      cx<T>* const sc = scratch + l * ld;
+      for (int q = g; q < M; q += TL) sc[q] = ln[P.pin[q]];
+      wave_lds_order();
+      ct_line<-1, T, M>(sc, ln + 1, P.tw, g, S{});   // odd stage count: result in ln + 1
+      for (int q = g; q < M; q += TL) {
+        const cx<T> v = ln[1 + q];
+        if (q == 0) dc[l] = v;
+        ln[1 + q] = cmul(v, bh[q]);
+      }
+      wave_lds_order();
+      ct_line<1, T, M>(ln + 1, sc, P.tw, g, S{});    // result in sc
+      const cx<T> x0 = ln[0];
+      for (int m = g; m < M; m += TL) ln[P.pout[m]] = cadd(x0, sc[m]);
+      wave_lds_order();
+      if (g == 0) ln[0] = cadd(x0, dc[l]);
+      wave_lds_order();
+    }
+  }
+  __syncthreads();
+  return line;
+}
+
 // Direct DFT of nl odd-length lines: X_k = sum_j x_j w^(jk),
 // w = exp(-+ 2 pi i / N).  With s_j = x_j + x_(N-j) and d_j = x_j - x_(N-j)
 // (j = 1 .. (N-1)/2) and theta = 2 pi j k / N,
@@ -593,6 +647,7 @@ __device__ cx<T>* line_fft(cx<T>* line, cx<T>* scratch, int ld, int nl, const Ax
     __syncthreads();
     return scratch;
   }
+  if (P.M == 126) return ct_rader<DIR, T, 127>(line, scratch, ld, nl, P, dc);
   const int M = P.M;
   const int total = nl * M;
   const FastDiv fm(M);

@@ -208,10 +208,12 @@ __device__ __forceinline__ void tangent_apply(const T p[6], T K, T g2, const T m
 }
 
 // G^(k) : T for a complex Mandel vector t, q = xi/|xi| (Appendix A):
-// (G^ : T)_ij = q_i v_j + q_j v_i - (q.v) q_i q_j, v = T q.  With q = xi
-// itself and as = 1/|xi|^2 (scale carrying another 1/|xi|^2) the same
-// expression gives G^ : T without the square root: every term is of degree
-// two in q once the (q.v) q q term carries the extra 1/|xi|^2.
+// (G^ : T)_ij = q_i v_j + q_j v_i - (q.v) q_i q_j, v = T q.  Called with
+// q = xi itself (not normalised), as = 1/|xi|^2 and scale carrying another
+// 1/|xi|^2, it gives the same G^ : T without a square root: q_i v_j is then
+// |xi|^2 times its normalised value and (q.v) q_i q_j is |xi|^4 times it,
+// so the (q.v) term takes the extra factor as and the whole the factor in
+// scale.
 template <class T>
 __device__ __forceinline__ void ghat_apply(cx<T> t[6], T q0, T q1, T q2, T scale, T as = T(1)) {
   const T r2 = T(1.0 / kSqrt2);

@@ -171,8 +171,12 @@ void fftg_history_destroy(fftg_history hist);
  * dE: host, 6 tensor components.  lockstep: NULL for natural stopping, or
  * n_lockstep CG counts that fix the number of Newton iterations and the CG
  * iterations of each (used to replay another implementation's path).
- * stats: may be NULL.  Returns FFTG_E_NOT_CONVERGED / FFTG_E_BREAKDOWN with
- * stats filled and the state committed at the last iterate. */
+ * stats: may be NULL.  Returns FFTG_E_NOT_CONVERGED / FFTG_E_BREAKDOWN /
+ * FFTG_E_NONFINITE with stats filled (Sigma: average stress at the last
+ * iterate) and the history not committed: E and eps* stay at the last
+ * iterate, eps_p and eps_p_bar keep the values committed at the end of the
+ * previous increment (a caller may restore a checkpoint and retry with a
+ * smaller dE). */
 fftg_status fftg_solve_increment(fftg_plan plan, fftg_history hist, const double dE[6], const int* lockstep,
                                  int n_lockstep, fftg_stats* stats);
 

@@ -95,12 +95,13 @@ __device__ __forceinline__ cx<T> mul_si(cx<T> a) {
 }
 
 // Integer division by a workgroup-uniform divisor through the FP32
-// reciprocal, exact for 0 <= t < 2^22: the float quotient is off by at most
-// one and a single remainder test corrects it.
+// reciprocal, exact for 0 <= t < 2^22: the reciprocal instruction is within
+// one unit in the last place, so the float quotient t * inv is off by less
+// than one and a single remainder test corrects it.
 struct FastDiv {
   float inv;
   int d;
-  __device__ __forceinline__ explicit FastDiv(int d_) : inv(1.0f / (float)d_), d(d_) {}
+  __device__ __forceinline__ explicit FastDiv(int d_) : inv(__builtin_amdgcn_rcpf((float)d_)), d(d_) {}
   __device__ __forceinline__ int div(int t) const {
     int q = (int)((float)t * inv);
     const int r = t - q * d;

@@ -1482,8 +1482,10 @@ __device__ double return_root(double seq, double a0, double G, double sy, double
 // the compact tangent {2G', m} with C = K I(x)I + 2G' I_d + csign m (x) m:
 // inelastic 2G' = 2G (1 - 3G dg/seq_tr), m = sqrt(-c) N,
 // c = 4G^2 (dg/seq_tr - 1/slope); non-linear elastic 2G' = 2/3 s/eps_eq,
-// m = sqrt(|c|) N, c = (n - 1) s/eps_eq with s = sigma_0 (eps_eq/eps_0)^n;
-// and, when committing, the new history and per-tile sums of sigma.
+// m = sqrt(|c|) N, c = (n - 1) s/eps_eq with s = sigma_0 (eps_eq/eps_0)^n.
+// commit: 0 evaluates only (Newton iterations); 1 also writes the new
+// history and per-tile sums of sigma (the end of an increment); 2 writes
+// the sums of sigma but leaves the history (an increment that failed).
 template <class TT>
 __global__ void __launch_bounds__(256) k_constitutive(const RveDev* __restrict__ rvs, int nrve, int vox_per_tile,
                                                       int eps_role, int commit) {
@@ -1570,7 +1572,7 @@ __global__ void __launch_bounds__(256) k_constitutive(const RveDev* __restrict__
           sig[c] = 2.0 * G * (d[c] - dg * Nv[c]) + (c < 3 ? K * tr : 0.0);
           m[c] = sm * Nv[c];
         }
-        if (commit) {
+        if (commit == 1) {
 #pragma unroll
           for (int c = 0; c < 6; ++c) ep[c * nvox + v] = epv[c] + dg * Nv[c];
           eb[v] = ebv + dg;

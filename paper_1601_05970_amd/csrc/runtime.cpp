@@ -1185,12 +1185,31 @@ static fftg_status group_increment(Group& g, const double* dE_tensor, const int*
       if (st != FFTG_OK) return st;
     }
   }
-  // commit every member at its last iterate
+  // Commit the members that converged.  A member whose Newton iteration
+  // failed (cap, breakdown, non-finite values) keeps the history committed
+  // at the end of its previous increment: its stress, tangent and Sigma are
+  // those of the last iterate, E and eps* stay at the last iterate, and
+  // eps_p, eps_p_bar are not updated.
+  bool any_failed = false;
+  for (size_t i = 0; i < n; ++i) any_failed = any_failed || !mr[i].converged;
+  if (any_failed) {
+    for (size_t i = 0; i < n; ++i) set_skip(g, i, !mr[i].converged);
+    st = group_upload(g);
+    if (st != FFTG_OK) return st;
+    PROF_LAUNCH(FFTG_KERNEL_CONSTITUTIVE,
+                launch_constitutive(g.mixed, g.d, nr, g.total[P_VEC], g.cfg, R_EPS_FL, 1, g.stream));
+    for (size_t i = 0; i < n; ++i) set_skip(g, i, mr[i].converged);
+    st = group_upload(g);
+    if (st != FFTG_OK) return st;
+    PROF_LAUNCH(FFTG_KERNEL_CONSTITUTIVE,
+                launch_constitutive(g.mixed, g.d, nr, g.total[P_VEC], g.cfg, R_EPS_FL, 2, g.stream));
+  }
   for (size_t i = 0; i < n; ++i) set_skip(g, i, false);
   st = group_upload(g);
   if (st != FFTG_OK) return st;
-  PROF_LAUNCH(FFTG_KERNEL_CONSTITUTIVE,
-              launch_constitutive(g.mixed, g.d, nr, g.total[P_VEC], g.cfg, R_EPS_FL, 1, g.stream));
+  if (!any_failed)
+    PROF_LAUNCH(FFTG_KERNEL_CONSTITUTIVE,
+                launch_constitutive(g.mixed, g.d, nr, g.total[P_VEC], g.cfg, R_EPS_FL, 1, g.stream));
   PROF_LAUNCH(FFTG_KERNEL_FINALIZE, launch_finalize(g.d, nr, FIN_SIGMA, g.stream));
   // equilibrium of the committed state: ||G sigma|| and ||sigma|| from one
   // FP64 identity product in residual form (it overwrites x, r and p, which
@@ -1202,7 +1221,7 @@ static fftg_status group_increment(Group& g, const double* dE_tensor, const int*
   const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   fftg_status ret = FFTG_OK;
   for (size_t i = 0; i < n; ++i) {
-    g.hists[i]->inc += 1;
+    if (mr[i].converged) g.hists[i]->inc += 1;
     const CgState& c = g.h_cg[i];
     bool finite = std::isfinite(c.snorm2) && std::isfinite(c.bnorm2);
     for (int k = 0; k < 6; ++k) finite = finite && std::isfinite(c.Sigma[k]);

@@ -357,6 +357,17 @@ def test_newton_cap_reports_not_converged():
     pl = fftg.Plan(w.phase, w.materials, o)
     h = fftg.History(pl)
     h.solve_increment(tensor6(w.dE(1)))
+    ep1 = to_host(h.get_field(fftg.FFTG_FIELD_EPS_P))
+    eb1 = to_host(h.get_field(fftg.FFTG_FIELD_EPBAR))
     st = h.solve_increment(tensor6(w.dE(2)), raise_on_error=False)
     assert st["status"] == fftg.FFTG_E_NOT_CONVERGED
     assert st["newton_iters"] == 2 and not st["converged"]
+    # not committed: the plastic history keeps increment 1's values (all zero:
+    # increment 1 is elastic), while the stress of the last iterate is plastic
+    assert np.array_equal(to_host(h.get_field(fftg.FFTG_FIELD_EPS_P)), ep1)
+    assert np.array_equal(to_host(h.get_field(fftg.FFTG_FIELD_EPBAR)), eb1)
+    assert not np.any(eb1) and np.all(np.isfinite(st["Sigma"]))
+    s_ = S.Solver(w.phase, w.materials, w.tol_newton, w.tol_cg)
+    s_.solve_increment(w.E_at(1))
+    ref = s_.solve_increment(w.E_at(2))      # the same increment converged in the oracle: plastic
+    assert np.max(s_.epbar) > 0 and ref.converged

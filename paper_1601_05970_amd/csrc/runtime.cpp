@@ -14,6 +14,8 @@
 #include <string>
 #include <vector>
 
+#include <dlfcn.h>
+
 #include "../../include/fftg.h"
 #include "fftg_internal.h"
 
@@ -1068,6 +1070,68 @@ static void set_E(Group& g, size_t i, const double E[6], const double dE[6]) {
   }
 }
 
+// ----------------------------------------------------- tracing and metrics
+// FFTG_TRACE=1 (read once, at the first increment) wraps every increment and
+// every Newton iteration in a roctx range, which rocprofv3 --marker-trace
+// records; the roctx library is opened at run time, so libfftg has no link
+// dependency on it and tracing does nothing where it is missing.
+// FFTG_METRICS=<path> (read at every increment) appends one JSON line per
+// member and increment to <path>: grid, precision, increment, status,
+// Newton and CG counts, Newton residuals, Sigma, equilibrium error and wall
+// time of the call.
+struct Roctx {
+  int (*push)(const char*) = nullptr;
+  int (*pop)() = nullptr;
+};
+static const Roctx& roctx() {
+  static const Roctx r = [] {
+    Roctx t;
+    if (env_long("FFTG_TRACE", 0) != 1) return t;
+    for (const char* lib : {"librocprofiler-sdk-roctx.so.1", "libroctx64.so.4"}) {
+      void* h = dlopen(lib, RTLD_NOW | RTLD_LOCAL);
+      if (!h) continue;
+      t.push = reinterpret_cast<int (*)(const char*)>(dlsym(h, "roctxRangePushA"));
+      t.pop = reinterpret_cast<int (*)()>(dlsym(h, "roctxRangePop"));
+      if (t.push && t.pop) break;
+      t.push = nullptr;
+      t.pop = nullptr;
+    }
+    return t;
+  }();
+  return r;
+}
+struct TraceRange {
+  bool on;
+  explicit TraceRange(const char* m) : on(roctx().push != nullptr) {
+    if (on) roctx().push(m);
+  }
+  ~TraceRange() {
+    if (on) roctx().pop();
+  }
+  TraceRange(const TraceRange&) = delete;
+  TraceRange& operator=(const TraceRange&) = delete;
+};
+
+static std::mutex g_metrics_mutex;
+static void write_metrics(const char* path, const fftg_plan pl, long long inc, int status, const fftg_stats& s) {
+  std::lock_guard<std::mutex> lk(g_metrics_mutex);
+  FILE* f = fopen(path, "a");
+  if (!f) return;
+  fprintf(f, "{\"grid\": [%d, %d, %d], \"precision\": \"%s\", \"increment\": %lld, \"status\": %d, "
+             "\"converged\": %d, \"newton\": %d, \"total_cg\": %d, \"seconds\": %.6g, "
+             "\"rel_equilibrium\": %.6g, \"Sigma\": [",
+          pl->n[0], pl->n[1], pl->n[2], pl->mixed ? "mixed" : "fp64", inc, status, s.converged, s.newton_iters,
+          s.total_cg, s.seconds, s.rel_equilibrium);
+  for (int c = 0; c < 6; ++c) fprintf(f, c ? ", %.17g" : "%.17g", s.Sigma[c]);
+  const int nn = std::min(s.newton_iters, FFTG_MAX_NEWTON);
+  fprintf(f, "], \"cg\": [");
+  for (int k = 0; k < nn; ++k) fprintf(f, k ? ", %d" : "%d", s.cg_iters[k]);
+  fprintf(f, "], \"newton_res\": [");
+  for (int k = 0; k < nn; ++k) fprintf(f, k ? ", %.6g" : "%.6g", s.newton_res[k]);
+  fprintf(f, "]}\n");
+  fclose(f);
+}
+
 struct MemberRun {
   int newton;
   int first_full;
@@ -1084,6 +1148,14 @@ static fftg_status group_increment(Group& g, const double* dE_tensor, const int*
   const size_t n = g.h.size();
   const fftg_options& o = g.plans[0]->opt;
   auto t0 = std::chrono::steady_clock::now();
+  TraceRange trace_inc("fftg increment");
+  const char* metrics = getenv("FFTG_METRICS");
+  if (metrics && !*metrics) metrics = nullptr;
+  std::vector<fftg_stats> local_stats;
+  if (metrics && !stats) {
+    local_stats.resize(n);
+    stats = local_stats.data();
+  }
   std::vector<MemberRun> mr(n);
   int nr = (int)n;
   for (size_t i = 0; i < n; ++i) {
@@ -1110,6 +1182,9 @@ static fftg_status group_increment(Group& g, const double* dE_tensor, const int*
     bool any = false;
     for (size_t i = 0; i < n; ++i) any = any || mr[i].active;
     if (!any || it >= max_newton) break;
+    char trace_name[32];
+    snprintf(trace_name, sizeof(trace_name), "fftg newton %d", it);
+    TraceRange trace_it(trace_name);
     const bool pred_step = predictor && it == 0;
     const int force = lockstep ? lockstep[it] : -1;
     // A right-hand side evaluated with the FP32 product (the mixed-mode
@@ -1233,12 +1308,9 @@ static fftg_status group_increment(Group& g, const double* dE_tensor, const int*
       mr[i].stats->seconds = secs;
       mr[i].stats->rel_equilibrium = c.snorm2 > 0.0 ? std::sqrt(c.bnorm2 / c.snorm2) : 0.0;
     }
-    if (ret == FFTG_OK) {
-      if (mr[i].err != FFTG_OK)
-        ret = (fftg_status)mr[i].err;
-      else if (!mr[i].converged)
-        ret = FFTG_E_NOT_CONVERGED;
-    }
+    const int member_status = mr[i].err != FFTG_OK ? mr[i].err : (mr[i].converged ? FFTG_OK : FFTG_E_NOT_CONVERGED);
+    if (ret == FFTG_OK) ret = (fftg_status)member_status;
+    if (metrics && mr[i].stats) write_metrics(metrics, g.plans[i], g.hists[i]->inc, member_status, *mr[i].stats);
   }
   if (ret == FFTG_E_BREAKDOWN) g_err = "CG breakdown (p.Ap <= 0 or not finite)";
   if (ret == FFTG_E_NONFINITE) g_err = "non-finite stress or Newton update";

@@ -434,12 +434,69 @@ __device__ __forceinline__ void ct_line(cx<T>* a, cx<T>* b, const cx<T>* tw, int
   ct_run<DIR, T, M, 1, TL, Rs...>(a, b, tw, g);
 }
 
+// The same stage in place: every lane loads the inputs of all its
+// butterflies, the wavefront's reads are ordered before its writes, and the
+// outputs go back to the same line.  A stage reads and writes every point
+// of the line exactly once and the line belongs to one wavefront, so no
+// write can land before a read of the old value.  The inputs of all the
+// lane's butterflies are live at once (IT x R points).
+template <int R, int DIR, class T, int M, int NS, int TL>
+__device__ __forceinline__ void ct_stage_ip(cx<T>* buf, const cx<T>* __restrict__ tw, int g) {
+  constexpr int NB = M / R;
+  constexpr int TSTEP = M / (NS * R);
+  constexpr int IT = (NB + TL - 1) / TL;
+  cx<T> v[IT][R];
+#pragma unroll
+  for (int it = 0; it < IT; ++it) {
+    const int j = g + it * TL;
+    if (NB % TL == 0 || it < IT - 1 || j < NB) {
+#pragma unroll
+      for (int q = 0; q < R; ++q) v[it][q] = buf[j + q * NB];
+    }
+  }
+  wave_lds_order();
+#pragma unroll
+  for (int it = 0; it < IT; ++it) {
+    const int j = g + it * TL;
+    if (NB % TL == 0 || it < IT - 1 || j < NB) {
+      const int k = NS > 1 ? j % NS : 0;
+      if constexpr (NS > 1) {
+#pragma unroll
+        for (int q = 1; q < R; ++q) {
+          cx<T> w = tw[q * k * TSTEP];
+          if (DIR > 0) w.im = -w.im;
+          v[it][q] = cmul(v[it][q], w);
+        }
+      }
+      cx<T>* d = buf + (j - k) * R + k;
+      Dft<R, DIR, T>::run_store(v[it], [&](int q, cx<T> x) { d[q * NS] = x; });
+    }
+  }
+}
+
+template <int DIR, class T, int M, int NS, int TL, int R, int... Rest>
+__device__ __forceinline__ void ct_run_ip(cx<T>* a, const cx<T>* tw, int g) {
+  ct_stage_ip<R, DIR, T, M, NS, TL>(a, tw, g);
+  wave_lds_order();
+  if constexpr (sizeof...(Rest) > 0) ct_run_ip<DIR, T, M, NS * R, TL, Rest...>(a, tw, g);
+}
+
+template <int DIR, class T, int M, int TL, int... Rs>
+__device__ __forceinline__ void ct_line_ip(cx<T>* a, const cx<T>* tw, int g, CtSpec<TL, Rs...>) {
+  ct_run_ip<DIR, T, M, 1, TL, Rs...>(a, tw, g);
+}
+
 // nl lines of N points (stride ld) in line/scratch; returns the buffer that
-// holds the result.  Called by the whole workgroup (blockDim a multiple of
-// 64); ends with a workgroup barrier.
+// holds the result.  Lengths for which inplace_axis holds run in place in
+// line (every stage loads a single butterfly per lane, so holding its
+// inputs costs no registers) and never touch scratch, which may alias line;
+// the 255-point chain (up to 20 points per lane per stage in place) keeps
+// the ping-pong pair.  Called by the whole workgroup (blockDim a multiple
+// of 64); ends with a workgroup barrier.
 template <int DIR, class T, int N>
 __device__ cx<T>* ct_fft(cx<T>* line, cx<T>* scratch, int ld, int nl, const cx<T>* tw) {
   using S = typename CtPlan<N>::spec;
+  constexpr bool IP = inplace_axis(AX_CHAIN, N);
   constexpr int TL = S::TL;
   constexpr int G = 64 / TL;  // lines per wavefront
   const int lane = (int)threadIdx.x & 63;
@@ -447,11 +504,15 @@ __device__ cx<T>* ct_fft(cx<T>* line, cx<T>* scratch, int ld, int nl, const cx<T
   const int g = lane - grp * TL;
   const int ngr = ((int)blockDim.x >> 6) * G;
   if (grp < G) {
-    for (int l = ((int)threadIdx.x >> 6) * G + grp; l < nl; l += ngr)
-      ct_line<DIR, T, N>(line + l * ld, scratch + l * ld, tw, g, S{});
+    for (int l = ((int)threadIdx.x >> 6) * G + grp; l < nl; l += ngr) {
+      if constexpr (IP)
+        ct_line_ip<DIR, T, N>(line + l * ld, tw, g, S{});
+      else
+        ct_line<DIR, T, N>(line + l * ld, scratch + l * ld, tw, g, S{});
+    }
   }
   __syncthreads();
-  return (S::NST % 2 == 0) ? line : scratch;
+  return (IP || S::NST % 2 == 0) ? line : scratch;
 }
 
 // Rader's algorithm for a prime N whose convolution length M = N - 1 has a
@@ -617,9 +678,10 @@ __device__ __forceinline__ void direct_dft(const cx<T>* line, cx<T>* scratch, in
 
 // In-LDS FFT of nl lines of length P.N, DIR = -1 forward, +1 inverse
 // (unnormalised); NF > 0 compiles only the unrolled direct DFT of NF-point
-// lines.  line and scratch each hold nl lines of stride ld >= N; dc holds
-// nl scratch slots (Rader only).  Returns the buffer holding the result
-// (line or scratch).  Must be called by the whole workgroup.
+// lines.  line and scratch each hold nl lines of stride ld >= N (scratch
+// may alias line where inplace_axis holds); dc holds nl scratch slots
+// (Rader only).  Returns the buffer holding the result (line or scratch).
+// Must be called by the whole workgroup.
 template <int DIR, class T, int BIG, int NF = 0>
 __device__ cx<T>* line_fft(cx<T>* line, cx<T>* scratch, int ld, int nl, const AxisLds<T>& P, cx<T>* dc) {
   if constexpr (NF > 0) {

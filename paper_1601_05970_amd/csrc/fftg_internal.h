@@ -142,9 +142,22 @@ struct LaunchCfg {
   int threads_s;       // slab passes
   int big_radix;       // 1 when some axis needs the radix-11/13/17 codelets
   int direct31;        // bit a (0 x, 1 y, 2 z): every member takes axis a by the 31-point direct DFT
+  int lext[3];         // per axis (0 x, 1 y, 2 z): LDS line-buffer extent, points per line (0: 2 x extent)
   int xcd_remap;       // 1: blocks mapped to tiles XCD-contiguously
   int n0max, n1max, n2max;  // largest extents of the launch (LDS table sizing)
 };
+
+// Axes whose transform runs in place (the compile-time chains of 15 and 63
+// points): their lines need one buffer in LDS instead of two.  Host (tile
+// sizing) and device (buffer carving) agree through this test.
+__host__ __device__ constexpr bool inplace_axis(int rader, int M) {
+  return rader == AX_CHAIN && (M == 15 || M == 63);
+}
+// LDS points per line that a member's transform of an n-point axis needs:
+// n in place, 2n for a ping-pong pair.  A launch sizes its tiles for the
+// largest value over its members, so in-place members of a mixed launch
+// still save space (a 63-point line in place takes what a 31-point pair does).
+__host__ __device__ constexpr int line_ext(int rader, int M, int n) { return inplace_axis(rader, M) ? n : 2 * n; }
 
 // Sizes of the RVEs a launch covers, from which the launch configuration is
 // chosen (host).
@@ -157,6 +170,7 @@ struct GridSum {
   long long vox = 0;
   int big = 0;
   int direct31 = 7;                 // bit a: every member's axis a is the 31-point direct DFT
+  int lext[3] = {0, 0, 0};          // per axis: largest line_ext over members (0: 2 x extent)
 };
 
 // Host side (runtime.cpp): the heuristic launch configuration and the tile
@@ -165,9 +179,11 @@ LaunchCfg choose_cfg(const GridSum& gs);
 void compute_tiles(const LaunchCfg& c, int n0, int n1, int n2, long long nvox, int tiles[P_NPASS]);
 
 // Host side (kernels.hip): LDS bytes of the pass kernels and their launchers.
-size_t lds_z(int mixed, int rows, int n2);
-size_t lds_y(int mixed, int lines, int n1);
-size_t lds_x(int mixed, int lines, int n0);
+// (n is the largest extent of the launch, which sizes the root tables; ext
+// the largest line_ext, 0 for 2n.)
+size_t lds_z(int mixed, int rows, int n2, int ext = 0);
+size_t lds_y(int mixed, int lines, int n1, int ext = 0);
+size_t lds_x(int mixed, int lines, int n0, int ext = 0);
 size_t lds_slab(int mixed, int n1, int n2);
 hipError_t launch_zfwd(int mixed, const RveDev* rv, int nrve, int tiles, const LaunchCfg& cfg, size_t lds,
                        int in_mode, int in_role, int tan_mode, int want_norm, int check_done, int update_p,

@@ -282,10 +282,12 @@ struct TileLds {
   double* red;
   // The tables are only carved out: the kernel copies them with
   // axis_lds_fetch / axis_lds_store around its own loads.
+  // An axis transformed in place has no second buffer (scratch aliases
+  // line; the host sized the tile for the largest line_ext of the launch).
   __device__ TileLds(char* base, int nl, int ld, const AxisDev& P, int ldmax) {
     axis_lds_setup<T>(P, base, ax);
     line = reinterpret_cast<cx<T>*>(base + axis_lds_bytes<T>(ldmax));
-    scratch = line + (size_t)nl * ld;
+    scratch = inplace_axis(ax.rader, ax.M) ? line : line + (size_t)nl * ld;
     dc = scratch + (size_t)nl * ld;
     red = reinterpret_cast<double*>(dc + nl + (nl & 1));
   }
@@ -1792,18 +1794,22 @@ __global__ void k_add_const(double* __restrict__ f, long long nvox, double e0, d
 }
 
 // ------------------------------------------------------------ launchers
+// nl lines of ext points each (line and, unless in place, scratch), the
+// Rader slots and the reduction scratch
 template <class T>
-static size_t tile_lds(int nl, int ld) {
-  return (size_t)2 * nl * ld * sizeof(cx<T>) + (size_t)(nl + 2) * sizeof(cx<T>) + 16 * sizeof(double) + 64;
+static size_t tile_lds(int nl, int ext) {
+  return (size_t)nl * ext * sizeof(cx<T>) + (size_t)(nl + 2) * sizeof(cx<T>) + 16 * sizeof(double) + 64;
 }
 
-size_t lds_z(int mixed, int rows, int n2) {
-  return mixed ? tile_lds<float>(3 * rows, n2) + axis_lds_bytes<float>(n2)
-               : tile_lds<double>(3 * rows, n2) + axis_lds_bytes<double>(n2);
+size_t lds_z(int mixed, int rows, int n2, int ext) {
+  if (ext <= 0) ext = 2 * n2;
+  return mixed ? tile_lds<float>(3 * rows, ext) + axis_lds_bytes<float>(n2)
+               : tile_lds<double>(3 * rows, ext) + axis_lds_bytes<double>(n2);
 }
-size_t lds_y(int mixed, int lines, int n1) {
-  return mixed ? tile_lds<float>(lines, n1) + axis_lds_bytes<float>(n1)
-               : tile_lds<double>(lines, n1) + axis_lds_bytes<double>(n1);
+size_t lds_y(int mixed, int lines, int n1, int ext) {
+  if (ext <= 0) ext = 2 * n1;
+  return mixed ? tile_lds<float>(lines, ext) + axis_lds_bytes<float>(n1)
+               : tile_lds<double>(lines, ext) + axis_lds_bytes<double>(n1);
 }
 template <class T>
 static size_t slab_lds(int n1, int n2) {
@@ -1812,9 +1818,10 @@ static size_t slab_lds(int n1, int n2) {
          (size_t)(nd + 2) * sizeof(cx<T>) + 32 * sizeof(double) + 64;
 }
 size_t lds_slab(int mixed, int n1, int n2) { return mixed ? slab_lds<float>(n1, n2) : slab_lds<double>(n1, n2); }
-size_t lds_x(int mixed, int lines, int n0) {
-  return mixed ? tile_lds<float>(6 * lines, n0) + axis_lds_bytes<float>(n0)
-               : tile_lds<double>(6 * lines, n0) + axis_lds_bytes<double>(n0);
+size_t lds_x(int mixed, int lines, int n0, int ext) {
+  if (ext <= 0) ext = 2 * n0;
+  return mixed ? tile_lds<float>(6 * lines, ext) + axis_lds_bytes<float>(n0)
+               : tile_lds<double>(6 * lines, ext) + axis_lds_bytes<double>(n0);
 }
 
 template <class T, int BIG, int NF>

@@ -343,17 +343,17 @@ LaunchCfg fftg::choose_cfg(const GridSum& gs) {
   const long long kMinTiles = env_long("FFTG_MIN_TILES", 2048, 1);
   const long long H = gs.hmax;
   int R = 8;
-  while (R > 1 && lds_z(0, R, gs.n2) > budget) --R;
+  while (R > 1 && lds_z(0, R, gs.n2, gs.lext[2]) > budget) --R;
   while (R > 1 && (gs.rows + R - 1) / R < kMinTiles) --R;
   c.rows_per_tile = R;
   c.threads_z = threads_for((long long)3 * R * gs.n2 / 2);
   int L = 16;
-  while (L > 1 && lds_y(0, L, gs.n1) > budget) --L;
+  while (L > 1 && lds_y(0, L, gs.n1, gs.lext[1]) > budget) --L;
   while (L > 1 && gs.yl * ((H + L - 1) / L) < kMinTiles) --L;
   c.lines_y = L;
   c.threads_y = threads_for((long long)L * gs.n1 / 2);
   int Lx = 8;
-  while (Lx > 1 && lds_x(0, Lx, gs.n0) > budget) --Lx;
+  while (Lx > 1 && lds_x(0, Lx, gs.n0, gs.lext[0]) > budget) --Lx;
   while (Lx > 1 && gs.xl * ((H + Lx - 1) / Lx) < kMinTiles) --Lx;
   c.lines_x = Lx;
   c.threads_x = threads_for((long long)6 * Lx * gs.n0 / 2);
@@ -366,6 +366,7 @@ LaunchCfg fftg::choose_cfg(const GridSum& gs) {
   c.threads_s = 256;
   c.big_radix = gs.big;
   c.direct31 = gs.direct31;
+  for (int a = 0; a < 3; ++a) c.lext[a] = gs.lext[a];
   c.xcd_remap = env_long("FFTG_XCD_REMAP", 1) == 1 ? 1 : 0;
   c.n0max = gs.n0;
   c.n1max = gs.n1;
@@ -813,8 +814,10 @@ static GridSum group_gridsum(const Group& g) {
     gs.hmax = std::max<long long>(gs.hmax, pl->H);
     gs.vox += pl->nvox;
     gs.big = gs.big || pl->big_radix;
-    for (int a = 0; a < 3; ++a)
+    for (int a = 0; a < 3; ++a) {
       if (!(pl->ax_dev[a].rader == AX_DIRECT && pl->ax_dev[a].M == 31)) gs.direct31 &= ~(1 << a);
+      gs.lext[a] = std::max(gs.lext[a], line_ext(pl->ax_dev[a].rader, pl->ax_dev[a].M, pl->n[a]));
+    }
   }
   return gs;
 }
@@ -823,12 +826,12 @@ static GridSum group_gridsum(const Group& g) {
 static void group_set_cfg(Group& g, const LaunchCfg& c) {
   g.cfg = c;
   const int n0 = c.n0max, n1 = c.n1max, n2 = c.n2max;
-  g.lds_zf = lds_z(0, c.rows_per_tile, n2);
-  g.lds_y = lds_y(0, c.lines_y, n1);
-  g.lds_x = lds_x(0, c.lines_x, n0);
-  g.lds_zf32 = lds_z(1, c.rows_per_tile, n2);
-  g.lds_y32 = lds_y(1, c.lines_y, n1);
-  g.lds_x32 = lds_x(1, c.lines_x, n0);
+  g.lds_zf = lds_z(0, c.rows_per_tile, n2, c.lext[2]);
+  g.lds_y = lds_y(0, c.lines_y, n1, c.lext[1]);
+  g.lds_x = lds_x(0, c.lines_x, n0, c.lext[0]);
+  g.lds_zf32 = lds_z(1, c.rows_per_tile, n2, c.lext[2]);
+  g.lds_y32 = lds_y(1, c.lines_y, n1, c.lext[1]);
+  g.lds_x32 = lds_x(1, c.lines_x, n0, c.lext[0]);
   g.lds_s = lds_slab(0, n1, n2);
   g.lds_s32 = lds_slab(1, n1, n2);
   for (auto& rv : g.h)
@@ -1392,7 +1395,9 @@ static bool pinned_tiles(LaunchCfg& c, int n0, int n1, int n2) {
   if (!rows_ok(v[0]) || !thr_ok(v[1]) || !ly_ok(v[2]) || !thr_ok(v[3]) || !rows_ok(v[4]) || !thr_ok(v[5]))
     return false;
   const size_t budget = (size_t)env_long("FFTG_LDS_KB", 128, 1) * 1024;
-  if (lds_z(0, v[0], n2) > budget || lds_y(0, v[2], n1) > budget || lds_x(0, v[4], n0) > budget) return false;
+  if (lds_z(0, v[0], n2, c.lext[2]) > budget || lds_y(0, v[2], n1, c.lext[1]) > budget ||
+      lds_x(0, v[4], n0, c.lext[0]) > budget)
+    return false;
   c.rows_per_tile = v[0];
   c.threads_z = v[1];
   c.lines_y = v[2];
@@ -1434,7 +1439,7 @@ static fftg_status group_autotune(Group& g) {
     double tbest = 1e30;
     LaunchCfg cb = best;
     for (int R : {1, 2, 3, 4, 6, 8}) {
-      if (lds_z(0, R, gs.n2) > budget) break;
+      if (lds_z(0, R, gs.n2, gs.lext[2]) > budget) break;
       for (int t : thr) {
         LaunchCfg c = best;
         c.rows_per_tile = R;
@@ -1462,7 +1467,7 @@ static fftg_status group_autotune(Group& g) {
     double tbest = 1e30;
     LaunchCfg cb = best;
     for (int L : {1, 2, 4, 8, 12, 16}) {
-      if (lds_y(0, L, gs.n1) > budget) break;
+      if (lds_y(0, L, gs.n1, gs.lext[1]) > budget) break;
       for (int t : thr) {
         LaunchCfg c = best;
         c.lines_y = L;
@@ -1487,7 +1492,7 @@ static fftg_status group_autotune(Group& g) {
     double tbest = 1e30;
     LaunchCfg cb = best;
     for (int L : {1, 2, 3, 4, 6, 8}) {
-      if (lds_x(0, L, gs.n0) > budget) break;
+      if (lds_x(0, L, gs.n0, gs.lext[0]) > budget) break;
       for (int t : thr) {
         LaunchCfg c = best;
         c.lines_x = L;

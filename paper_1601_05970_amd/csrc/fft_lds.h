@@ -190,6 +190,30 @@ struct Dft<4, DIR, T> {
   }
 };
 
+// 15 points by the prime-factor (Good-Thomas) split 15 = 3 x 5, which
+// needs no twiddles: with input index n = (5 n1 + 3 n2) mod 15 and output
+// index k = (10 k1 + 6 k2) mod 15 (k1 = k mod 3, k2 = k mod 5) the kernel
+// w_15^(n k) factors into w_3^(n1 k1) w_5^(n2 k2), since 50 = 5, 30 = 0 and
+// 18 = 3 (mod 15).  Five 3-point DFTs over n1, then three 5-point DFTs over
+// n2, all indices fixed at compile time.
+template <int DIR, class T>
+struct Dft<15, DIR, T> {
+  template <class S>
+  __device__ __forceinline__ static void run_store(cx<T>* v, S&& st) {
+    cx<T> b[3][5];
+#pragma unroll
+    for (int n2 = 0; n2 < 5; ++n2) {
+      cx<T> a[3];
+#pragma unroll
+      for (int n1 = 0; n1 < 3; ++n1) a[n1] = v[(5 * n1 + 3 * n2) % 15];
+      Dft<3, DIR, T>::run_store(a, [&](int k1, cx<T> x) { b[k1][n2] = x; });
+    }
+#pragma unroll
+    for (int k1 = 0; k1 < 3; ++k1)
+      Dft<5, DIR, T>::run_store(b[k1], [&](int k2, cx<T> x) { st((10 * k1 + 6 * k2) % 15, x); });
+  }
+};
+
 // One Stockham stage of radix R over nl lines of an M-point chain.
 // Butterfly j of a line reads src[j + q M/R], twiddles by w_M^(q k M/(Ns R))
 // with k = j mod Ns, and writes dst[(j - k) R + k + q Ns].
@@ -385,7 +409,7 @@ struct CtPlan<63> {
 template <>
 struct CtPlan<255> {
   static constexpr bool ok = true;
-  using spec = CtSpec<15, 3, 5, 17>;  // 85, 51 and 15 butterflies per stage
+  using spec = CtSpec<17, 15, 17>;  // 17 and 15 butterflies per stage (radix 15 by the prime-factor split)
 };
 
 // Orders this wavefront's LDS accesses for the compiler (the hardware keeps
@@ -489,10 +513,9 @@ __device__ __forceinline__ void ct_line_ip(cx<T>* a, const cx<T>* tw, int g, CtS
 // nl lines of N points (stride ld) in line/scratch; returns the buffer that
 // holds the result.  Lengths for which inplace_axis holds run in place in
 // line (every stage loads a single butterfly per lane, so holding its
-// inputs costs no registers) and never touch scratch, which may alias line;
-// the 255-point chain (up to 20 points per lane per stage in place) keeps
-// the ping-pong pair.  Called by the whole workgroup (blockDim a multiple
-// of 64); ends with a workgroup barrier.
+// inputs costs no more registers than the butterfly itself) and never
+// touch scratch, which may alias line.  Called by the whole workgroup
+// (blockDim a multiple of 64); ends with a workgroup barrier.
 template <int DIR, class T, int N>
 __device__ cx<T>* ct_fft(cx<T>* line, cx<T>* scratch, int ld, int nl, const cx<T>* tw) {
   using S = typename CtPlan<N>::spec;

@@ -19,8 +19,12 @@ constexpr int kMaxStages = 8;
 constexpr int kMaxPhases = 16;
 constexpr int kMaxAxisLen = 1024;
 
+// Aligned to its size, so that the compiler may always move a complex
+// value with one 16-byte (FP64) or 8-byte (FP32) access: every complex
+// array here (device allocations, LDS carve-ups, host vectors) starts on
+// such a boundary and is indexed by whole elements.
 template <class T>
-struct cx {
+struct alignas(2 * sizeof(T)) cx {
   T re, im;
 };
 
@@ -147,11 +151,11 @@ struct LaunchCfg {
   int n0max, n1max, n2max;  // largest extents of the launch (LDS table sizing)
 };
 
-// Axes whose transform runs in place (the compile-time chains of 15 and 63
-// points): their lines need one buffer in LDS instead of two.  Host (tile
-// sizing) and device (buffer carving) agree through this test.
+// Axes whose transform runs in place (the compile-time chains of 15, 63 and
+// 255 points): their lines need one buffer in LDS instead of two.  Host
+// (tile sizing) and device (buffer carving) agree through this test.
 __host__ __device__ constexpr bool inplace_axis(int rader, int M) {
-  return rader == AX_CHAIN && (M == 15 || M == 63);
+  return rader == AX_CHAIN && (M == 15 || M == 63 || M == 255);
 }
 // LDS points per line that a member's transform of an n-point axis needs:
 // n in place, 2n for a ping-pong pair.  A launch sizes its tiles for the

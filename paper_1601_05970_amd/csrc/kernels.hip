@@ -271,8 +271,12 @@ __device__ __forceinline__ void gamma_apply(cx<T> t[6], T q0, T q1, T q2, T lam0
 
 __device__ __forceinline__ int sfreq(int m, int n) { return (2 * m < n) ? m : m - n; }
 
-// LDS carve-up for a tile: axis tables, then nl lines of stride ld, the
-// ping-pong scratch, Rader slots and the reduction scratch.
+// LDS carve-up for a tile: axis tables, Rader slots and the reduction
+// scratch, then nl lines of stride ld and the ping-pong scratch.  An axis
+// transformed in place never touches scratch, and the host sized the tile
+// for the largest line_ext of the launch, so scratch may lie past the end
+// of the allocation for such an axis: everything else sits before line, at
+// offsets that do not depend on the transform.
 template <class T>
 struct TileLds {
   AxisLds<T> ax;
@@ -282,14 +286,16 @@ struct TileLds {
   double* red;
   // The tables are only carved out: the kernel copies them with
   // axis_lds_fetch / axis_lds_store around its own loads.
-  // An axis transformed in place has no second buffer (scratch aliases
-  // line; the host sized the tile for the largest line_ext of the launch).
+  // Every offset is a multiple of 16 bytes that the compiler can see
+  // (rounded up explicitly), so it keeps 16-byte LDS accesses on the lines.
   __device__ TileLds(char* base, int nl, int ld, const AxisDev& P, int ldmax) {
     axis_lds_setup<T>(P, base, ax);
-    line = reinterpret_cast<cx<T>*>(base + axis_lds_bytes<T>(ldmax));
-    scratch = inplace_axis(ax.rader, ax.M) ? line : line + (size_t)nl * ld;
-    dc = scratch + (size_t)nl * ld;
-    red = reinterpret_cast<double*>(dc + nl + (nl & 1));
+    const size_t tb = axis_lds_bytes<T>(ldmax);
+    const size_t db = ((size_t)(nl + 1) * sizeof(cx<T>) + 15) / 16 * 16;
+    dc = reinterpret_cast<cx<T>*>(base + tb);
+    red = reinterpret_cast<double*>(base + tb + db);
+    line = reinterpret_cast<cx<T>*>(base + tb + db + 16 * sizeof(double));
+    scratch = line + (size_t)nl * ld;
   }
 };
 
@@ -1794,8 +1800,8 @@ __global__ void k_add_const(double* __restrict__ f, long long nvox, double e0, d
 }
 
 // ------------------------------------------------------------ launchers
-// nl lines of ext points each (line and, unless in place, scratch), the
-// Rader slots and the reduction scratch
+// the Rader slots, the reduction scratch and nl lines of ext points each
+// (line and, unless in place, scratch)
 template <class T>
 static size_t tile_lds(int nl, int ext) {
   return (size_t)nl * ext * sizeof(cx<T>) + (size_t)(nl + 2) * sizeof(cx<T>) + 16 * sizeof(double) + 64;

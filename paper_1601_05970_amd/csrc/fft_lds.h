@@ -190,29 +190,39 @@ struct Dft<4, DIR, T> {
   }
 };
 
-// 15 points by the prime-factor (Good-Thomas) split 15 = 3 x 5, which
-// needs no twiddles: with input index n = (5 n1 + 3 n2) mod 15 and output
-// index k = (10 k1 + 6 k2) mod 15 (k1 = k mod 3, k2 = k mod 5) the kernel
-// w_15^(n k) factors into w_3^(n1 k1) w_5^(n2 k2), since 50 = 5, 30 = 0 and
-// 18 = 3 (mod 15).  Five 3-point DFTs over n1, then three 5-point DFTs over
-// n2, all indices fixed at compile time.
-template <int DIR, class T>
-struct Dft<15, DIR, T> {
+// N1 N2 points (coprime factors) by the prime-factor (Good-Thomas) split,
+// which needs no twiddles: with input index n = (N2 n1 + N1 n2) mod N and
+// output index k = (c1 k1 + c2 k2) mod N, c1 = N2 (N2^-1 mod N1) and
+// c2 = N1 (N1^-1 mod N2) (so k1 = k mod N1, k2 = k mod N2), the kernel
+// w_N^(n k) factors into w_N1^(n1 k1) w_N2^(n2 k2).  N2 N1-point DFTs over
+// n1, then N1 N2-point DFTs over n2, all indices fixed at compile time.
+__host__ __device__ constexpr int inv_mod(int a, int m) {
+  int r = 1;
+  while ((a * r) % m != 1) ++r;
+  return r;
+}
+template <int N1, int N2, int DIR, class T>
+struct PfaDft {
+  static constexpr int N = N1 * N2;
+  static constexpr int c1 = N2 * inv_mod(N2 % N1, N1);
+  static constexpr int c2 = N1 * inv_mod(N1 % N2, N2);
   template <class S>
   __device__ __forceinline__ static void run_store(cx<T>* v, S&& st) {
-    cx<T> b[3][5];
+    cx<T> b[N1][N2];
 #pragma unroll
-    for (int n2 = 0; n2 < 5; ++n2) {
-      cx<T> a[3];
+    for (int n2 = 0; n2 < N2; ++n2) {
+      cx<T> a[N1];
 #pragma unroll
-      for (int n1 = 0; n1 < 3; ++n1) a[n1] = v[(5 * n1 + 3 * n2) % 15];
-      Dft<3, DIR, T>::run_store(a, [&](int k1, cx<T> x) { b[k1][n2] = x; });
+      for (int n1 = 0; n1 < N1; ++n1) a[n1] = v[(N2 * n1 + N1 * n2) % N];
+      Dft<N1, DIR, T>::run_store(a, [&](int k1, cx<T> x) { b[k1][n2] = x; });
     }
 #pragma unroll
-    for (int k1 = 0; k1 < 3; ++k1)
-      Dft<5, DIR, T>::run_store(b[k1], [&](int k2, cx<T> x) { st((10 * k1 + 6 * k2) % 15, x); });
+    for (int k1 = 0; k1 < N1; ++k1)
+      Dft<N2, DIR, T>::run_store(b[k1], [&](int k2, cx<T> x) { st((c1 * k1 + c2 * k2) % N, x); });
   }
 };
+template <int DIR, class T>
+struct Dft<15, DIR, T> : PfaDft<3, 5, DIR, T> {};
 
 // One Stockham stage of radix R over nl lines of an M-point chain.
 // Butterfly j of a line reads src[j + q M/R], twiddles by w_M^(q k M/(Ns R))
@@ -464,8 +474,12 @@ __device__ __forceinline__ void ct_line(cx<T>* a, cx<T>* b, const cx<T>* tw, int
 // of the line exactly once and the line belongs to one wavefront, so no
 // write can land before a read of the old value.  The inputs of all the
 // lane's butterflies are live at once (IT x R points).
-template <int R, int DIR, class T, int M, int NS, int TL>
-__device__ __forceinline__ void ct_stage_ip(cx<T>* buf, const cx<T>* __restrict__ tw, int g) {
+// (The loads and stores go through ldf(i) and stf(i, x) for chain position
+// i, so that a caller can fold a permutation or a pointwise step into a
+// stage: the reads of the stage still cover every position once before any
+// write.)
+template <int R, int DIR, class T, int M, int NS, int TL, class Ld, class St>
+__device__ __forceinline__ void ct_stage_io(Ld&& ldf, St&& stf, const cx<T>* __restrict__ tw, int g) {
   constexpr int NB = M / R;
   constexpr int TSTEP = M / (NS * R);
   constexpr int IT = (NB + TL - 1) / TL;
@@ -475,7 +489,7 @@ __device__ __forceinline__ void ct_stage_ip(cx<T>* buf, const cx<T>* __restrict_
     const int j = g + it * TL;
     if (NB % TL == 0 || it < IT - 1 || j < NB) {
 #pragma unroll
-      for (int q = 0; q < R; ++q) v[it][q] = buf[j + q * NB];
+      for (int q = 0; q < R; ++q) v[it][q] = ldf(j + q * NB);
     }
   }
   wave_lds_order();
@@ -492,10 +506,14 @@ __device__ __forceinline__ void ct_stage_ip(cx<T>* buf, const cx<T>* __restrict_
           v[it][q] = cmul(v[it][q], w);
         }
       }
-      cx<T>* d = buf + (j - k) * R + k;
-      Dft<R, DIR, T>::run_store(v[it], [&](int q, cx<T> x) { d[q * NS] = x; });
+      const int d = (j - k) * R + k;
+      Dft<R, DIR, T>::run_store(v[it], [&](int q, cx<T> x) { stf(d + q * NS, x); });
     }
   }
+}
+template <int R, int DIR, class T, int M, int NS, int TL>
+__device__ __forceinline__ void ct_stage_ip(cx<T>* buf, const cx<T>* __restrict__ tw, int g) {
+  ct_stage_io<R, DIR, T, M, NS, TL>([&](int i) { return buf[i]; }, [&](int i, cx<T> x) { buf[i] = x; }, tw, g);
 }
 
 template <int DIR, class T, int M, int NS, int TL, int R, int... Rest>
@@ -517,7 +535,7 @@ __device__ __forceinline__ void ct_line_ip(cx<T>* a, const cx<T>* tw, int g, CtS
 // touch scratch, which may alias line.  Called by the whole workgroup
 // (blockDim a multiple of 64); ends with a workgroup barrier.
 template <int DIR, class T, int N>
-__device__ cx<T>* ct_fft(cx<T>* line, cx<T>* scratch, int ld, int nl, const cx<T>* tw) {
+__device__ __forceinline__ cx<T>* ct_fft(cx<T>* line, cx<T>* scratch, int ld, int nl, const cx<T>* tw) {
   using S = typename CtPlan<N>::spec;
   constexpr bool IP = inplace_axis(AX_CHAIN, N);
   constexpr int TL = S::TL;
@@ -539,12 +557,15 @@ __device__ cx<T>* ct_fft(cx<T>* line, cx<T>* scratch, int ld, int nl, const cx<T
 }
 
 // Rader's algorithm for a prime N whose convolution length M = N - 1 has a
-// compile-time chain, each line owned by TL lanes of one wavefront (as
-// ct_fft): gather a_q = x_(g^q) into scratch, forward chain, multiply by
-// DFT_M(b)/M (keeping a's DFT at 0, the sum of x_1..x_(N-1)), inverse chain,
-// then X_(g^-m) = x_0 + (a (*) b)_m and X_0 = x_0 + that sum.  Every step is
-// line-local, so the steps are ordered by the wavefront alone; the chains
-// ping-pong between scratch and line + 1 (x_0 stays in line[0]).
+// compile-time chain, each line owned by TL lanes of one
+// wavefront (as ct_fft), all in place in the line.  x_0 stays in line[0];
+// the first forward stage reads a_q = x_(g^q) straight from its permuted
+// place, the last forward stage multiplies its outputs by DFT_M(b)/M
+// (keeping a's DFT at 0, the sum of x_1..x_(N-1), in dc), and the last
+// inverse stage writes X_(g^-m) = x_0 + (a (*) b)_m to its permuted place;
+// X_0 = x_0 + that sum.  Every stage reads all M points before it writes
+// (the gather and the scatter are permutations of line[1..M]), and every
+// step is line-local, so the steps are ordered by the wavefront alone.
 template <int N>
 struct CtRader {
   static constexpr bool ok = false;
@@ -552,16 +573,36 @@ struct CtRader {
 template <>
 struct CtRader<127> {
   static constexpr bool ok = true;
-  using spec = CtSpec<9, 2, 7, 9>;   // 126 = 2 7 9: 63, 18 and 14 butterflies per stage
+  using spec = CtSpec<18, 7, 2, 9>;   // 126 = 7 2 9: 18, 63 and 14 butterflies per stage
 };
 
+// The stages of a chain in place, the first reading through ldf and the
+// last writing through stf (the others read and write a).
+template <int... Rs>
+struct Radices {};
+template <int DIR, class T, int M, int NS, int TL, class Ld, class St, int R, int... Rest>
+__device__ __forceinline__ void ct_run_io(cx<T>* a, Ld&& ldf, St&& stf, const cx<T>* tw, int g,
+                                          Radices<R, Rest...>) {
+  if constexpr (sizeof...(Rest) == 0) {
+    ct_stage_io<R, DIR, T, M, NS, TL>(ldf, stf, tw, g);
+  } else {
+    ct_stage_io<R, DIR, T, M, NS, TL>(ldf, [&](int i, cx<T> x) { a[i] = x; }, tw, g);
+    wave_lds_order();
+    __builtin_amdgcn_sched_barrier(0);   // no stage's work moved into another's (register lifetimes)
+    ct_run_io<DIR, T, M, NS * R, TL>(a, [&](int i) { return a[i]; }, stf, tw, g, Radices<Rest...>{});
+  }
+}
+template <int DIR, class T, int M, int TL, class Ld, class St, int... Rs>
+__device__ __forceinline__ void ct_chain_io(cx<T>* a, Ld&& ldf, St&& stf, const cx<T>* tw, int g, CtSpec<TL, Rs...>) {
+  ct_run_io<DIR, T, M, 1, TL>(a, ldf, stf, tw, g, Radices<Rs...>{});
+}
+
 template <int DIR, class T, int N>
-__device__ cx<T>* ct_rader(cx<T>* line, cx<T>* scratch, int ld, int nl, const AxisLds<T>& P, cx<T>* dc) {
+__device__ __forceinline__ cx<T>* ct_rader(cx<T>* line, int ld, int nl, const AxisLds<T>& P, cx<T>* dc) {
   using S = typename CtRader<N>::spec;
   constexpr int M = N - 1;
   constexpr int TL = S::TL;
   constexpr int G = 64 / TL;
-  static_assert(S::NST % 2 == 1, "the scatter below reads the inverse chain's result from scratch");
   const int lane = (int)threadIdx.x & 63;
   const int grp = lane / TL;
   const int g = lane - grp * TL;
@@ -570,19 +611,18 @@ __device__ cx<T>* ct_rader(cx<T>* line, cx<T>* scratch, int ld, int nl, const Ax
   if (grp < G) {
     for (int l = ((int)threadIdx.x >> 6) * G + grp; l < nl; l += ngr) {
       cx<T>* const ln = line + l * ld;
-      cx<T>* const sc = scratch + l * ld;
-      for (int q = g; q < M; q += TL) sc[q] = ln[P.pin[q]];
-      wave_lds_order();
-      ct_line<-1, T, M>(sc, ln + 1, P.tw, g, S{});   // odd stage count: result in ln + 1
-      for (int q = g; q < M; q += TL) {
-        const cx<T> v = ln[1 + q];
-        if (q == 0) dc[l] = v;
-        ln[1 + q] = cmul(v, bh[q]);
-      }
-      wave_lds_order();
-      ct_line<1, T, M>(ln + 1, sc, P.tw, g, S{});    // result in sc
+      cx<T>* const a = ln + 1;
       const cx<T> x0 = ln[0];
-      for (int m = g; m < M; m += TL) ln[P.pout[m]] = cadd(x0, sc[m]);
+      ct_chain_io<-1, T, M>(
+          a, [&](int i) { return ln[P.pin[i]]; },
+          [&](int i, cx<T> x) {
+            if (i == 0) dc[l] = x;
+            a[i] = cmul(x, bh[i]);
+          },
+          P.tw, g, S{});
+      wave_lds_order();
+      ct_chain_io<1, T, M>(
+          a, [&](int i) { return a[i]; }, [&](int i, cx<T> x) { ln[P.pout[i]] = cadd(x0, x); }, P.tw, g, S{});
       wave_lds_order();
       if (g == 0) ln[0] = cadd(x0, dc[l]);
       wave_lds_order();
@@ -706,7 +746,7 @@ __device__ __forceinline__ void direct_dft(const cx<T>* line, cx<T>* scratch, in
 // (Rader only).  Returns the buffer holding the result (line or scratch).
 // Must be called by the whole workgroup.
 template <int DIR, class T, int BIG, int NF = 0>
-__device__ cx<T>* line_fft(cx<T>* line, cx<T>* scratch, int ld, int nl, const AxisLds<T>& P, cx<T>* dc) {
+__device__ __forceinline__ cx<T>* line_fft(cx<T>* line, cx<T>* scratch, int ld, int nl, const AxisLds<T>& P, cx<T>* dc) {
   if constexpr (NF > 0) {
     // kernels built for one line length run only where every line of the
     // launch takes the NF-point direct DFT (the host checks the plan's
@@ -733,7 +773,11 @@ __device__ cx<T>* line_fft(cx<T>* line, cx<T>* scratch, int ld, int nl, const Ax
     __syncthreads();
     return scratch;
   }
-  if (P.M == 126) return ct_rader<DIR, T, 127>(line, scratch, ld, nl, P, dc);
+  if constexpr (BIG) {
+    // 127 points: built only into the big-radix kernels (plans with such an
+    // axis take them), whose register budget the in-place stages fit
+    if (P.M == 126) return ct_rader<DIR, T, 127>(line, ld, nl, P, dc);
+  }
   const int M = P.M;
   const int total = nl * M;
   const FastDiv fm(M);

@@ -152,10 +152,11 @@ struct LaunchCfg {
 };
 
 // Axes whose transform runs in place (the compile-time chains of 15, 63 and
-// 255 points): their lines need one buffer in LDS instead of two.  Host
-// (tile sizing) and device (buffer carving) agree through this test.
+// 255 points, and Rader's algorithm for 127 points over its compile-time
+// 126-point chain): their lines need one buffer in LDS instead of two.
+// Host (tile sizing) and device (buffer carving) agree through this test.
 __host__ __device__ constexpr bool inplace_axis(int rader, int M) {
-  return rader == AX_CHAIN && (M == 15 || M == 63 || M == 255);
+  return (rader == AX_CHAIN && (M == 15 || M == 63 || M == 255)) || (rader == AX_RADER && M == 126);
 }
 // LDS points per line that a member's transform of an n-point axis needs:
 // n in place, 2n for a ping-pong pair.  A launch sizes its tiles for the

@@ -276,7 +276,7 @@ struct fftg_plan_s {
   CgState* h_cg;      // pinned, 3 slots (state reads + two CG snapshots)
   hipEvent_t snap_ev[2];
   int max_tiles;
-  int big_radix;      // an axis uses the radix-11/13/17 codelets
+  int big_radix;      // an axis uses the radix-11/13/17 codelets or 127-point Rader
   int tuned;          // cfg holds the autotuned launch configuration
   LaunchCfg cfg;
 };
@@ -540,10 +540,14 @@ fftg_status fftg_plan_create(fftg_plan* out, int n0, int n1, int n2, const uint8
     }
     idx[ns[i]] = (int)pl->axes.size() - 1;
   }
+  // kernels with the radix-11/13/17 codelets, the 255-point chain and the
+  // in-place 127-point Rader transform
   pl->big_radix = 0;
-  for (auto& a : pl->axes)
+  for (auto& a : pl->axes) {
     for (int s = 0; s < a.dev.nst; ++s)
       if (a.dev.radix[s] > 9) pl->big_radix = 1;
+    if (a.dev.rader == AX_RADER && a.dev.M == 126) pl->big_radix = 1;
+  }
   hipError_t e = hipSuccess;
 #define PLAN_TRY(expr)                                                            \
   do {                                                                            \

@@ -288,10 +288,13 @@ struct AxisLds {
   const cx<T>* g_tw;  // root table in global memory
 };
 
-// LDS bytes of the tables of an axis of length <= N.
+// LDS bytes of the tables of an axis of length <= N: the roots, and for
+// Rader's algorithm (rader != 0) its two kernel transforms and its two
+// permutations.  A multiple of 16 either way.
 template <class T>
-__host__ __device__ constexpr size_t axis_lds_bytes(int N) {
-  return (((size_t)N * (3 * sizeof(cx<T>) + 2 * sizeof(int))) + 15) / 16 * 16;
+__host__ __device__ constexpr size_t axis_lds_bytes(int N, int rader = 1) {
+  return rader ? (((size_t)N * (3 * sizeof(cx<T>) + 2 * sizeof(int))) + 15) / 16 * 16
+               : ((size_t)N * sizeof(cx<T>) + 15) / 16 * 16;
 }
 
 // Carves the tables out of base and reads the axis fields (no table loads).

@@ -147,6 +147,7 @@ struct LaunchCfg {
   int big_radix;       // 1 when some axis needs the radix-11/13/17 codelets
   int direct31;        // bit a (0 x, 1 y, 2 z): every member takes axis a by the 31-point direct DFT
   int lext[3];         // per axis (0 x, 1 y, 2 z): LDS line-buffer extent, points per line (0: 2 x extent)
+  int rtab[3];         // per axis: 1 when some member takes it by Rader's algorithm (full LDS tables)
   int xcd_remap;       // 1: blocks mapped to tiles XCD-contiguously
   int n0max, n1max, n2max;  // largest extents of the launch (LDS table sizing)
 };
@@ -176,6 +177,7 @@ struct GridSum {
   int big = 0;
   int direct31 = 7;                 // bit a: every member's axis a is the 31-point direct DFT
   int lext[3] = {0, 0, 0};          // per axis: largest line_ext over members (0: 2 x extent)
+  int rtab[3] = {0, 0, 0};          // per axis: some member takes it by Rader's algorithm
 };
 
 // Host side (runtime.cpp): the heuristic launch configuration and the tile
@@ -184,11 +186,12 @@ LaunchCfg choose_cfg(const GridSum& gs);
 void compute_tiles(const LaunchCfg& c, int n0, int n1, int n2, long long nvox, int tiles[P_NPASS]);
 
 // Host side (kernels.hip): LDS bytes of the pass kernels and their launchers.
-// (n is the largest extent of the launch, which sizes the root tables; ext
-// the largest line_ext, 0 for 2n.)
-size_t lds_z(int mixed, int rows, int n2, int ext = 0);
-size_t lds_y(int mixed, int lines, int n1, int ext = 0);
-size_t lds_x(int mixed, int lines, int n0, int ext = 0);
+// (n is the largest extent of the launch, which sizes the tables; ext the
+// largest line_ext, 0 for 2n; rtab 1 when some member takes the axis by
+// Rader's algorithm, whose tables are larger.)
+size_t lds_z(int mixed, int rows, int n2, int ext = 0, int rtab = 1);
+size_t lds_y(int mixed, int lines, int n1, int ext = 0, int rtab = 1);
+size_t lds_x(int mixed, int lines, int n0, int ext = 0, int rtab = 1);
 size_t lds_slab(int mixed, int n1, int n2);
 hipError_t launch_zfwd(int mixed, const RveDev* rv, int nrve, int tiles, const LaunchCfg& cfg, size_t lds,
                        int in_mode, int in_role, int tan_mode, int want_norm, int check_done, int update_p,

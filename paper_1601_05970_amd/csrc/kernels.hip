@@ -290,7 +290,7 @@ struct TileLds {
   // (rounded up explicitly), so it keeps 16-byte LDS accesses on the lines.
   __device__ TileLds(char* base, int nl, int ld, const AxisDev& P, int ldmax) {
     axis_lds_setup<T>(P, base, ax);
-    const size_t tb = axis_lds_bytes<T>(ldmax);
+    const size_t tb = axis_lds_bytes<T>(ldmax, P.rader == AX_RADER);
     const size_t db = ((size_t)(nl + 1) * sizeof(cx<T>) + 15) / 16 * 16;
     dc = reinterpret_cast<cx<T>*>(base + tb);
     red = reinterpret_cast<double*>(base + tb + db);
@@ -1807,15 +1807,15 @@ static size_t tile_lds(int nl, int ext) {
   return (size_t)nl * ext * sizeof(cx<T>) + (size_t)(nl + 2) * sizeof(cx<T>) + 16 * sizeof(double) + 64;
 }
 
-size_t lds_z(int mixed, int rows, int n2, int ext) {
+size_t lds_z(int mixed, int rows, int n2, int ext, int rtab) {
   if (ext <= 0) ext = 2 * n2;
-  return mixed ? tile_lds<float>(3 * rows, ext) + axis_lds_bytes<float>(n2)
-               : tile_lds<double>(3 * rows, ext) + axis_lds_bytes<double>(n2);
+  return mixed ? tile_lds<float>(3 * rows, ext) + axis_lds_bytes<float>(n2, rtab)
+               : tile_lds<double>(3 * rows, ext) + axis_lds_bytes<double>(n2, rtab);
 }
-size_t lds_y(int mixed, int lines, int n1, int ext) {
+size_t lds_y(int mixed, int lines, int n1, int ext, int rtab) {
   if (ext <= 0) ext = 2 * n1;
-  return mixed ? tile_lds<float>(lines, ext) + axis_lds_bytes<float>(n1)
-               : tile_lds<double>(lines, ext) + axis_lds_bytes<double>(n1);
+  return mixed ? tile_lds<float>(lines, ext) + axis_lds_bytes<float>(n1, rtab)
+               : tile_lds<double>(lines, ext) + axis_lds_bytes<double>(n1, rtab);
 }
 template <class T>
 static size_t slab_lds(int n1, int n2) {
@@ -1824,10 +1824,10 @@ static size_t slab_lds(int n1, int n2) {
          (size_t)(nd + 2) * sizeof(cx<T>) + 32 * sizeof(double) + 64;
 }
 size_t lds_slab(int mixed, int n1, int n2) { return mixed ? slab_lds<float>(n1, n2) : slab_lds<double>(n1, n2); }
-size_t lds_x(int mixed, int lines, int n0, int ext) {
+size_t lds_x(int mixed, int lines, int n0, int ext, int rtab) {
   if (ext <= 0) ext = 2 * n0;
-  return mixed ? tile_lds<float>(6 * lines, ext) + axis_lds_bytes<float>(n0)
-               : tile_lds<double>(6 * lines, ext) + axis_lds_bytes<double>(n0);
+  return mixed ? tile_lds<float>(6 * lines, ext) + axis_lds_bytes<float>(n0, rtab)
+               : tile_lds<double>(6 * lines, ext) + axis_lds_bytes<double>(n0, rtab);
 }
 
 template <class T, int BIG, int NF>

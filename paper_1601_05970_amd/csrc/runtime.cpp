@@ -343,17 +343,17 @@ LaunchCfg fftg::choose_cfg(const GridSum& gs) {
   const long long kMinTiles = env_long("FFTG_MIN_TILES", 2048, 1);
   const long long H = gs.hmax;
   int R = 8;
-  while (R > 1 && lds_z(0, R, gs.n2, gs.lext[2]) > budget) --R;
+  while (R > 1 && lds_z(0, R, gs.n2, gs.lext[2], gs.rtab[2]) > budget) --R;
   while (R > 1 && (gs.rows + R - 1) / R < kMinTiles) --R;
   c.rows_per_tile = R;
   c.threads_z = threads_for((long long)3 * R * gs.n2 / 2);
   int L = 16;
-  while (L > 1 && lds_y(0, L, gs.n1, gs.lext[1]) > budget) --L;
+  while (L > 1 && lds_y(0, L, gs.n1, gs.lext[1], gs.rtab[1]) > budget) --L;
   while (L > 1 && gs.yl * ((H + L - 1) / L) < kMinTiles) --L;
   c.lines_y = L;
   c.threads_y = threads_for((long long)L * gs.n1 / 2);
   int Lx = 8;
-  while (Lx > 1 && lds_x(0, Lx, gs.n0, gs.lext[0]) > budget) --Lx;
+  while (Lx > 1 && lds_x(0, Lx, gs.n0, gs.lext[0], gs.rtab[0]) > budget) --Lx;
   while (Lx > 1 && gs.xl * ((H + Lx - 1) / Lx) < kMinTiles) --Lx;
   c.lines_x = Lx;
   c.threads_x = threads_for((long long)6 * Lx * gs.n0 / 2);
@@ -366,7 +366,10 @@ LaunchCfg fftg::choose_cfg(const GridSum& gs) {
   c.threads_s = 256;
   c.big_radix = gs.big;
   c.direct31 = gs.direct31;
-  for (int a = 0; a < 3; ++a) c.lext[a] = gs.lext[a];
+  for (int a = 0; a < 3; ++a) {
+    c.lext[a] = gs.lext[a];
+    c.rtab[a] = gs.rtab[a];
+  }
   c.xcd_remap = env_long("FFTG_XCD_REMAP", 1) == 1 ? 1 : 0;
   c.n0max = gs.n0;
   c.n1max = gs.n1;
@@ -821,6 +824,7 @@ static GridSum group_gridsum(const Group& g) {
     for (int a = 0; a < 3; ++a) {
       if (!(pl->ax_dev[a].rader == AX_DIRECT && pl->ax_dev[a].M == 31)) gs.direct31 &= ~(1 << a);
       gs.lext[a] = std::max(gs.lext[a], line_ext(pl->ax_dev[a].rader, pl->ax_dev[a].M, pl->n[a]));
+      if (pl->ax_dev[a].rader == AX_RADER) gs.rtab[a] = 1;
     }
   }
   return gs;
@@ -830,12 +834,12 @@ static GridSum group_gridsum(const Group& g) {
 static void group_set_cfg(Group& g, const LaunchCfg& c) {
   g.cfg = c;
   const int n0 = c.n0max, n1 = c.n1max, n2 = c.n2max;
-  g.lds_zf = lds_z(0, c.rows_per_tile, n2, c.lext[2]);
-  g.lds_y = lds_y(0, c.lines_y, n1, c.lext[1]);
-  g.lds_x = lds_x(0, c.lines_x, n0, c.lext[0]);
-  g.lds_zf32 = lds_z(1, c.rows_per_tile, n2, c.lext[2]);
-  g.lds_y32 = lds_y(1, c.lines_y, n1, c.lext[1]);
-  g.lds_x32 = lds_x(1, c.lines_x, n0, c.lext[0]);
+  g.lds_zf = lds_z(0, c.rows_per_tile, n2, c.lext[2], c.rtab[2]);
+  g.lds_y = lds_y(0, c.lines_y, n1, c.lext[1], c.rtab[1]);
+  g.lds_x = lds_x(0, c.lines_x, n0, c.lext[0], c.rtab[0]);
+  g.lds_zf32 = lds_z(1, c.rows_per_tile, n2, c.lext[2], c.rtab[2]);
+  g.lds_y32 = lds_y(1, c.lines_y, n1, c.lext[1], c.rtab[1]);
+  g.lds_x32 = lds_x(1, c.lines_x, n0, c.lext[0], c.rtab[0]);
   g.lds_s = lds_slab(0, n1, n2);
   g.lds_s32 = lds_slab(1, n1, n2);
   for (auto& rv : g.h)
@@ -1399,8 +1403,8 @@ static bool pinned_tiles(LaunchCfg& c, int n0, int n1, int n2) {
   if (!rows_ok(v[0]) || !thr_ok(v[1]) || !ly_ok(v[2]) || !thr_ok(v[3]) || !rows_ok(v[4]) || !thr_ok(v[5]))
     return false;
   const size_t budget = (size_t)env_long("FFTG_LDS_KB", 128, 1) * 1024;
-  if (lds_z(0, v[0], n2, c.lext[2]) > budget || lds_y(0, v[2], n1, c.lext[1]) > budget ||
-      lds_x(0, v[4], n0, c.lext[0]) > budget)
+  if (lds_z(0, v[0], n2, c.lext[2], c.rtab[2]) > budget || lds_y(0, v[2], n1, c.lext[1], c.rtab[1]) > budget ||
+      lds_x(0, v[4], n0, c.lext[0], c.rtab[0]) > budget)
     return false;
   c.rows_per_tile = v[0];
   c.threads_z = v[1];
@@ -1443,7 +1447,7 @@ static fftg_status group_autotune(Group& g) {
     double tbest = 1e30;
     LaunchCfg cb = best;
     for (int R : {1, 2, 3, 4, 6, 8}) {
-      if (lds_z(0, R, gs.n2, gs.lext[2]) > budget) break;
+      if (lds_z(0, R, gs.n2, gs.lext[2], gs.rtab[2]) > budget) break;
       for (int t : thr) {
         LaunchCfg c = best;
         c.rows_per_tile = R;
@@ -1471,7 +1475,7 @@ static fftg_status group_autotune(Group& g) {
     double tbest = 1e30;
     LaunchCfg cb = best;
     for (int L : {1, 2, 4, 8, 12, 16}) {
-      if (lds_y(0, L, gs.n1, gs.lext[1]) > budget) break;
+      if (lds_y(0, L, gs.n1, gs.lext[1], gs.rtab[1]) > budget) break;
       for (int t : thr) {
         LaunchCfg c = best;
         c.lines_y = L;
@@ -1496,7 +1500,7 @@ static fftg_status group_autotune(Group& g) {
     double tbest = 1e30;
     LaunchCfg cb = best;
     for (int L : {1, 2, 3, 4, 6, 8}) {
-      if (lds_x(0, L, gs.n0, gs.lext[0]) > budget) break;
+      if (lds_x(0, L, gs.n0, gs.lext[0], gs.rtab[0]) > budget) break;
       for (int t : thr) {
         LaunchCfg c = best;
         c.lines_x = L;

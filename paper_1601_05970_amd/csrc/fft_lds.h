@@ -432,48 +432,9 @@ __device__ __forceinline__ void wave_lds_order() {
   __asm__ volatile("" ::: "memory");
 }
 
-template <int R, int DIR, class T, int M, int NS, int TL>
-__device__ __forceinline__ void ct_stage(const cx<T>* src, cx<T>* dst, const cx<T>* __restrict__ tw, int g) {
-  constexpr int NB = M / R;
-  constexpr int TSTEP = M / (NS * R);
-  constexpr int IT = (NB + TL - 1) / TL;
-#pragma unroll 1
-  for (int it = 0; it < IT; ++it) {
-    const int j = g + it * TL;
-    if (NB % TL == 0 || it < IT - 1 || j < NB) {
-      const int k = NS > 1 ? j % NS : 0;
-      cx<T> v[R];
-#pragma unroll
-      for (int q = 0; q < R; ++q) v[q] = src[j + q * NB];
-      if constexpr (NS > 1) {
-#pragma unroll
-        for (int q = 1; q < R; ++q) {
-          cx<T> w = tw[q * k * TSTEP];
-          if (DIR > 0) w.im = -w.im;
-          v[q] = cmul(v[q], w);
-        }
-      }
-      cx<T>* d = dst + (j - k) * R + k;
-      Dft<R, DIR, T>::run_store(v, [&](int q, cx<T> x) { d[q * NS] = x; });
-    }
-  }
-}
-
-template <int DIR, class T, int M, int NS, int TL, int R, int... Rest>
-__device__ __forceinline__ void ct_run(cx<T>* a, cx<T>* b, const cx<T>* tw, int g) {
-  ct_stage<R, DIR, T, M, NS, TL>(a, b, tw, g);
-  wave_lds_order();
-  if constexpr (sizeof...(Rest) > 0) ct_run<DIR, T, M, NS * R, TL, Rest...>(b, a, tw, g);
-}
-
-template <int DIR, class T, int M, int TL, int... Rs>
-__device__ __forceinline__ void ct_line(cx<T>* a, cx<T>* b, const cx<T>* tw, int g, CtSpec<TL, Rs...>) {
-  ct_run<DIR, T, M, 1, TL, Rs...>(a, b, tw, g);
-}
-
-// The same stage in place: every lane loads the inputs of all its
-// butterflies, the wavefront's reads are ordered before its writes, and the
-// outputs go back to the same line.  A stage reads and writes every point
+// One stage in place: every lane loads the inputs of all its butterflies,
+// the wavefront's reads are ordered before its writes, and the outputs go
+// back to the same line.  A stage reads and writes every point
 // of the line exactly once and the line belongs to one wavefront, so no
 // write can land before a read of the old value.  The inputs of all the
 // lane's butterflies are live at once (IT x R points).
@@ -514,33 +475,36 @@ __device__ __forceinline__ void ct_stage_io(Ld&& ldf, St&& stf, const cx<T>* __r
     }
   }
 }
-template <int R, int DIR, class T, int M, int NS, int TL>
-__device__ __forceinline__ void ct_stage_ip(cx<T>* buf, const cx<T>* __restrict__ tw, int g) {
-  ct_stage_io<R, DIR, T, M, NS, TL>([&](int i) { return buf[i]; }, [&](int i, cx<T> x) { buf[i] = x; }, tw, g);
+
+// The stages of a chain in place, the first reading through ldf and the
+// last writing through stf (the others read and write a).
+template <int... Rs>
+struct Radices {};
+template <int DIR, class T, int M, int NS, int TL, class Ld, class St, int R, int... Rest>
+__device__ __forceinline__ void ct_run_io(cx<T>* a, Ld&& ldf, St&& stf, const cx<T>* tw, int g,
+                                          Radices<R, Rest...>) {
+  if constexpr (sizeof...(Rest) == 0) {
+    ct_stage_io<R, DIR, T, M, NS, TL>(ldf, stf, tw, g);
+  } else {
+    ct_stage_io<R, DIR, T, M, NS, TL>(ldf, [&](int i, cx<T> x) { a[i] = x; }, tw, g);
+    wave_lds_order();
+    ct_run_io<DIR, T, M, NS * R, TL>(a, [&](int i) { return a[i]; }, stf, tw, g, Radices<Rest...>{});
+  }
+}
+template <int DIR, class T, int M, int TL, class Ld, class St, int... Rs>
+__device__ __forceinline__ void ct_chain_io(cx<T>* a, Ld&& ldf, St&& stf, const cx<T>* tw, int g, CtSpec<TL, Rs...>) {
+  ct_run_io<DIR, T, M, 1, TL>(a, ldf, stf, tw, g, Radices<Rs...>{});
 }
 
-template <int DIR, class T, int M, int NS, int TL, int R, int... Rest>
-__device__ __forceinline__ void ct_run_ip(cx<T>* a, const cx<T>* tw, int g) {
-  ct_stage_ip<R, DIR, T, M, NS, TL>(a, tw, g);
-  wave_lds_order();
-  if constexpr (sizeof...(Rest) > 0) ct_run_ip<DIR, T, M, NS * R, TL, Rest...>(a, tw, g);
-}
-
-template <int DIR, class T, int M, int TL, int... Rs>
-__device__ __forceinline__ void ct_line_ip(cx<T>* a, const cx<T>* tw, int g, CtSpec<TL, Rs...>) {
-  ct_run_ip<DIR, T, M, 1, TL, Rs...>(a, tw, g);
-}
-
-// nl lines of N points (stride ld) in line/scratch; returns the buffer that
-// holds the result.  Lengths for which inplace_axis holds run in place in
-// line (every stage loads a single butterfly per lane, so holding its
-// inputs costs no more registers than the butterfly itself) and never
-// touch scratch, which may alias line.  Called by the whole workgroup
-// (blockDim a multiple of 64); ends with a workgroup barrier.
+// nl lines of N points (stride ld) transformed in place in line (every
+// stage loads a single butterfly per lane, so holding its inputs costs no
+// more registers than the butterfly itself; no second buffer).  Called by
+// the whole workgroup (blockDim a multiple of 64); ends with a workgroup
+// barrier.
 template <int DIR, class T, int N>
-__device__ __forceinline__ cx<T>* ct_fft(cx<T>* line, cx<T>* scratch, int ld, int nl, const cx<T>* tw) {
+__device__ __forceinline__ cx<T>* ct_fft(cx<T>* line, int ld, int nl, const cx<T>* tw) {
   using S = typename CtPlan<N>::spec;
-  constexpr bool IP = inplace_axis(AX_CHAIN, N);
+  static_assert(inplace_axis(AX_CHAIN, N), "the host sizes these lines for one buffer");
   constexpr int TL = S::TL;
   constexpr int G = 64 / TL;  // lines per wavefront
   const int lane = (int)threadIdx.x & 63;
@@ -549,14 +513,12 @@ __device__ __forceinline__ cx<T>* ct_fft(cx<T>* line, cx<T>* scratch, int ld, in
   const int ngr = ((int)blockDim.x >> 6) * G;
   if (grp < G) {
     for (int l = ((int)threadIdx.x >> 6) * G + grp; l < nl; l += ngr) {
-      if constexpr (IP)
-        ct_line_ip<DIR, T, N>(line + l * ld, tw, g, S{});
-      else
-        ct_line<DIR, T, N>(line + l * ld, scratch + l * ld, tw, g, S{});
+      cx<T>* const a = line + l * ld;
+      ct_chain_io<DIR, T, N>(a, [&](int i) { return a[i]; }, [&](int i, cx<T> x) { a[i] = x; }, tw, g, S{});
     }
   }
   __syncthreads();
-  return (IP || S::NST % 2 == 0) ? line : scratch;
+  return line;
 }
 
 // Rader's algorithm for a prime N whose convolution length M = N - 1 has a
@@ -578,27 +540,6 @@ struct CtRader<127> {
   static constexpr bool ok = true;
   using spec = CtSpec<18, 7, 2, 9>;   // 126 = 7 2 9: 18, 63 and 14 butterflies per stage
 };
-
-// The stages of a chain in place, the first reading through ldf and the
-// last writing through stf (the others read and write a).
-template <int... Rs>
-struct Radices {};
-template <int DIR, class T, int M, int NS, int TL, class Ld, class St, int R, int... Rest>
-__device__ __forceinline__ void ct_run_io(cx<T>* a, Ld&& ldf, St&& stf, const cx<T>* tw, int g,
-                                          Radices<R, Rest...>) {
-  if constexpr (sizeof...(Rest) == 0) {
-    ct_stage_io<R, DIR, T, M, NS, TL>(ldf, stf, tw, g);
-  } else {
-    ct_stage_io<R, DIR, T, M, NS, TL>(ldf, [&](int i, cx<T> x) { a[i] = x; }, tw, g);
-    wave_lds_order();
-    __builtin_amdgcn_sched_barrier(0);   // no stage's work moved into another's (register lifetimes)
-    ct_run_io<DIR, T, M, NS * R, TL>(a, [&](int i) { return a[i]; }, stf, tw, g, Radices<Rest...>{});
-  }
-}
-template <int DIR, class T, int M, int TL, class Ld, class St, int... Rs>
-__device__ __forceinline__ void ct_chain_io(cx<T>* a, Ld&& ldf, St&& stf, const cx<T>* tw, int g, CtSpec<TL, Rs...>) {
-  ct_run_io<DIR, T, M, 1, TL>(a, ldf, stf, tw, g, Radices<Rs...>{});
-}
 
 template <int DIR, class T, int N>
 __device__ __forceinline__ cx<T>* ct_rader(cx<T>* line, int ld, int nl, const AxisLds<T>& P, cx<T>* dc) {
@@ -761,10 +702,10 @@ __device__ __forceinline__ cx<T>* line_fft(cx<T>* line, cx<T>* scratch, int ld, 
     return scratch;
   }
   if (P.rader == AX_CHAIN) {
-    if (P.M == 63) return ct_fft<DIR, T, 63>(line, scratch, ld, nl, P.tw);
-    if (P.M == 15) return ct_fft<DIR, T, 15>(line, scratch, ld, nl, P.tw);
+    if (P.M == 63) return ct_fft<DIR, T, 63>(line, ld, nl, P.tw);
+    if (P.M == 15) return ct_fft<DIR, T, 15>(line, ld, nl, P.tw);
     if constexpr (BIG) {
-      if (P.M == 255) return ct_fft<DIR, T, 255>(line, scratch, ld, nl, P.tw);
+      if (P.M == 255) return ct_fft<DIR, T, 255>(line, ld, nl, P.tw);
     }
     cx<T>* a = line;
     cx<T>* b = scratch;

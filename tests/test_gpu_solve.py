@@ -317,24 +317,25 @@ def test_batch_with_31_point_axes_equals_alone():
             assert rel_err(f[k], alone[i][0][k]) < 1e-10, k
 
 
-def test_batch_mixing_transform_kinds_equals_alone():
+@pytest.mark.parametrize("precision", [0, 1])
+def test_batch_mixing_transform_kinds_equals_alone(precision):
     """One batched launch over members whose axes take every transform kind:
     the 127-point Rader transform in place (on x, y and z in turn), the
     in-place 63- and 255-point chains, the 31-point direct DFT and the
     general Rader path for 61 points (both with a ping-pong pair).  Tiles are
     sized for the largest line extent and table of the launch while each
     member carves LDS for its own transform; every member agrees with its
-    solve alone."""
-    print("batch vs alone, mixed transform kinds", flush=True)
+    solve alone, in FP64 and with the FP32 product (precision 1)."""
+    print("batch vs alone, mixed transform kinds, precision", precision, flush=True)
     from paper_1601_05970_amd import fftg
     shapes = [(127, 3, 5), (5, 127, 3), (3, 5, 127), (63, 3, 5), (3, 255, 3), (31, 5, 3), (61, 3, 3)]
     # 0.002 equivalent strain per increment, two increments
     ws = [synth.small_random(sh, 0.35, i + 40, E_eq=0.01, n_inc=5) for i, sh in enumerate(shapes)]
     alone = []
     for w in ws:
-        _, h, st = _run_gpu(w, _opts(w), n_inc=2)
+        _, h, st = _run_gpu(w, _opts(w, precision=precision), n_inc=2)
         alone.append((_fields(h), st))
-    plans = [fftg.Plan(w.phase, w.materials, _opts(w)) for w in ws]
+    plans = [fftg.Plan(w.phase, w.materials, _opts(w, precision=precision)) for w in ws]
     hists = [fftg.History(p) for p in plans]
     b = fftg.Batch(plans, hists)
     for n in range(1, 3):
@@ -346,14 +347,16 @@ def test_batch_mixing_transform_kinds_equals_alone():
             # alone, some members take other kernel builds (31-point lines, no big radices): the
             # same transforms up to rounding, so a CG count may differ by one
             assert all(abs(x - y) <= 1 for x, y in zip(a, r)), (shapes[i], n, a, r)
+    # the FP32 product rounds differently in the other kernel builds a member takes alone
+    tol = 1e-10 if precision == 0 else 1e-6
     for i, h in enumerate(hists):
         f = _fields(h)
         for k in f:
-            assert rel_err(f[k], alone[i][0][k]) < 1e-10, (shapes[i], k)
+            assert rel_err(f[k], alone[i][0][k]) < tol, (shapes[i], k)
     # and the members whose axes take the in-place transforms agree with the FP64 oracle
     for i in (0, 1, 2, 3, 4):
         s, st_ref = S.run_workload(ws[i], n_inc=2)
-        _compare(hists[i], s, 1e-8)
+        _compare(hists[i], s, 1e-8 if precision == 0 else 1e-5)
 
 
 def test_error_paths():

@@ -873,9 +873,12 @@ static void group_totals(Group& g) {
 // r.r) run inside the consumer kernels when every one of their tiles can
 // total the producer's partials cheaply: the L2 reads of that redundant sum
 // grow as (forward-pass tiles) x (inverse-pass tiles).  Larger RVEs use
-// k_finalize.  FFTG_FOLD_MAX overrides the bound (0 sends every RVE through
-// k_finalize; read when descriptors are uploaded).
-constexpr long long kFoldMax = 1LL << 23;
+// k_finalize.  The bound admits a 63^3 RVE with one-row z tiles (3969 x 3969
+// tiles; the mixed 64-RVE batch is 2 % faster folded, FP64 0.3 %), a 127^3
+// one only with four rows per tile or more, and no 255^3 one.  FFTG_FOLD_MAX
+// overrides it (0 sends every RVE through k_finalize; read when descriptors
+// are uploaded).
+constexpr long long kFoldMax = 1LL << 24;
 static bool fold_ok(const RveDev& rv, long long fold_max) {
   return (long long)rv.tiles[P_ZF] * rv.tiles[P_ZI] <= fold_max;
 }

@@ -96,11 +96,14 @@ def test_voronoi127_mixed_invariants_and_sampled_return_map():
 
 
 @pytest.mark.timeout(900)
-def test_batch_member_63_lockstep_with_oracle():
+@pytest.mark.parametrize("fold", ["default", "0"])
+def test_batch_member_63_lockstep_with_oracle(fold, monkeypatch):
     """A 63^3 member of the 64-RVE batch alone, in lockstep with the oracle
-    over its first three increments: at this size the CG scalar steps run in
-    k_finalize (the product of forward and inverse tiles exceeds the fold
-    bound), which is how every 63^3 member of the batch solves."""
+    over its first three increments, with the CG scalar steps folded into the
+    product passes (the default at this size) and in k_finalize
+    (FFTG_FOLD_MAX=0, the path of larger RVEs) at full-size tiles."""
+    if fold != "default":
+        monkeypatch.setenv("FFTG_FOLD_MAX", fold)
     from paper_1601_05970_amd import fftg
     w = synth.batch_rve(0)
     print("full size", w.name, w.shape, flush=True)

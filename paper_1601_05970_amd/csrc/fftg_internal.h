@@ -147,6 +147,7 @@ struct LaunchCfg {
   int big_radix;       // 1 when some axis needs the radix-11/13/17 codelets
   int direct31;        // bit a (0 x, 1 y, 2 z): every member takes axis a by the 31-point direct DFT
   int lext[3];         // per axis (0 x, 1 y, 2 z): LDS line-buffer extent, points per line (0: 2 x extent)
+  int lext32x;         // the same for the FP32 x pass (its lines are not padded)
   int rtab[3];         // per axis: 1 when some member takes it by Rader's algorithm (full LDS tables)
   int xcd_remap;       // 1: blocks mapped to tiles XCD-contiguously
   int n0max, n1max, n2max;  // largest extents of the launch (LDS table sizing)
@@ -159,11 +160,23 @@ struct LaunchCfg {
 __host__ __device__ constexpr bool inplace_axis(int rader, int M) {
   return (rader == AX_CHAIN && (M == 15 || M == 63 || M == 255)) || (rader == AX_RADER && M == 126);
 }
-// LDS points per line that a member's transform of an n-point axis needs:
-// n in place, 2n for a ping-pong pair.  A launch sizes its tiles for the
-// largest value over its members, so in-place members of a mixed launch
-// still save space (a 63-point line in place takes what a 31-point pair does).
-__host__ __device__ constexpr int line_ext(int rader, int M, int n) { return inplace_axis(rader, M) ? n : 2 * n; }
+// LDS stride (points) of the x pass's lines of an n-point axis.  FP64
+// 63-point lines are padded to 73 points: at stride 63 (-1 mod 16 in 16-byte
+// units) the neighbouring lines of an in-place stage and the h-neighbours of
+// the gather hit the same LDS banks, at 73 (9 mod 16) far fewer do (x pass
+// 114 -> 110 us on the FP64 64-RVE batch).  FP32 lines, and the y and z
+// passes' lines, keep stride n: padded, they ran slower.
+__host__ __device__ constexpr int xline_stride(int rader, int M, int n, int fp32) {
+  return (!fp32 && rader == AX_CHAIN && M == 63) ? 73 : n;
+}
+// LDS points per line that a member's transform of an n-point axis needs
+// (xpass64: the FP64 x pass's stride): one stride in place, two for a
+// ping-pong pair.  A launch sizes its tiles for the largest value over its
+// members, so in-place members of a mixed launch still save space (a
+// 63-point line in place takes about what a 31-point pair does).
+__host__ __device__ constexpr int line_ext(int rader, int M, int n, int xpass64 = 0) {
+  return (inplace_axis(rader, M) ? 1 : 2) * (xpass64 ? xline_stride(rader, M, n, 0) : n);
+}
 
 // Sizes of the RVEs a launch covers, from which the launch configuration is
 // chosen (host).
@@ -177,6 +190,7 @@ struct GridSum {
   int big = 0;
   int direct31 = 7;                 // bit a: every member's axis a is the 31-point direct DFT
   int lext[3] = {0, 0, 0};          // per axis: largest line_ext over members (0: 2 x extent)
+  int lext32x = 0;                  // the FP32 x pass's (unpadded lines)
   int rtab[3] = {0, 0, 0};          // per axis: some member takes it by Rader's algorithm
 };
 

@@ -271,6 +271,9 @@ __device__ __forceinline__ void gamma_apply(cx<T> t[6], T q0, T q1, T q2, T lam0
 
 __device__ __forceinline__ int sfreq(int m, int n) { return (2 * m < n) ? m : m - n; }
 
+template <class T>
+constexpr int kFp32 = std::is_same<T, float>::value ? 1 : 0;
+
 // LDS carve-up for a tile: axis tables, Rader slots and the reduction
 // scratch, then nl lines of stride ld and the ping-pong scratch.  An axis
 // transformed in place never touches scratch, and the host sized the tile
@@ -665,13 +668,14 @@ __global__ void __launch_bounds__(256) k_xpass(const RveDev* __restrict__ rvs, i
   const long long nspec = rv.nspec, nvox = rv.nvox;
   FFTG_GLOBAL cx<T>* const spec = gmem((cx<T>*)rv.spec);
   CgState* const cg = rv.cg;
-  TileLds<T> L(smem, 6 * lines_per_tile, n0, rv.ax[0], ldmax);
+  TileLds<T> L(smem, 6 * lines_per_tile, xline_stride(rv.ax[0].rader, rv.ax[0].M, n0, kFp32<T>), rv.ax[0],
+               ldmax);
   __asm__ volatile("" : "+s"(n0), "+s"(n1), "+s"(n2), "+s"(H) : : "memory");
   const int nhb = (H + lines_per_tile - 1) / lines_per_tile;
   const int i1 = tile / nhb;
   const int h0 = (tile - i1 * nhb) * lines_per_tile;
   const int nh = min(lines_per_tile, H - h0);
-  const int ld = n0;
+  const int ld = xline_stride(L.ax.rader, L.ax.M, n0, kFp32<T>);
   const int nl = 6 * nh;
   // stop flag: as in the y pass (tested first only over several RVEs)
   const bool single = launch_single(nrve);

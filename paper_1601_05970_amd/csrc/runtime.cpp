@@ -370,6 +370,7 @@ LaunchCfg fftg::choose_cfg(const GridSum& gs) {
     c.lext[a] = gs.lext[a];
     c.rtab[a] = gs.rtab[a];
   }
+  c.lext32x = gs.lext32x;
   c.xcd_remap = env_long("FFTG_XCD_REMAP", 1) == 1 ? 1 : 0;
   c.n0max = gs.n0;
   c.n1max = gs.n1;
@@ -823,7 +824,8 @@ static GridSum group_gridsum(const Group& g) {
     gs.big = gs.big || pl->big_radix;
     for (int a = 0; a < 3; ++a) {
       if (!(pl->ax_dev[a].rader == AX_DIRECT && pl->ax_dev[a].M == 31)) gs.direct31 &= ~(1 << a);
-      gs.lext[a] = std::max(gs.lext[a], line_ext(pl->ax_dev[a].rader, pl->ax_dev[a].M, pl->n[a]));
+      gs.lext[a] = std::max(gs.lext[a], line_ext(pl->ax_dev[a].rader, pl->ax_dev[a].M, pl->n[a], a == 0));
+      if (a == 0) gs.lext32x = std::max(gs.lext32x, line_ext(pl->ax_dev[a].rader, pl->ax_dev[a].M, pl->n[a]));
       if (pl->ax_dev[a].rader == AX_RADER) gs.rtab[a] = 1;
     }
   }
@@ -839,7 +841,7 @@ static void group_set_cfg(Group& g, const LaunchCfg& c) {
   g.lds_x = lds_x(0, c.lines_x, n0, c.lext[0], c.rtab[0]);
   g.lds_zf32 = lds_z(1, c.rows_per_tile, n2, c.lext[2], c.rtab[2]);
   g.lds_y32 = lds_y(1, c.lines_y, n1, c.lext[1], c.rtab[1]);
-  g.lds_x32 = lds_x(1, c.lines_x, n0, c.lext[0], c.rtab[0]);
+  g.lds_x32 = lds_x(1, c.lines_x, n0, c.lext32x, c.rtab[0]);
   g.lds_s = lds_slab(0, n1, n2);
   g.lds_s32 = lds_slab(1, n1, n2);
   for (auto& rv : g.h)
